@@ -1,0 +1,163 @@
+/*
+ * qrx -- mixed-precision QR factorisation and least-squares solver for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method (Zhang & Wu, "High Accuracy Low Precision QR Factorization and Least
+ * Square Solver on GPU with TensorCore"):
+ *   - QR by recursive blocked Gram-Schmidt (Alg. 2, eq. recqr): split the
+ *     columns [A1 | A2], factor A1, R12 = Q1^T A2, A2 -= Q1 R12, factor A2.
+ *     The two trailing products run on the matrix cores in FP16 or BF16 with
+ *     FP32 accumulation (Sec. 3.1.2); narrow panels at the leaves are
+ *     factored by a communication-avoiding TSQR whose blocks are orthogonalised
+ *     by modified Gram-Schmidt, run twice (eq. caqr, Alg. 4, Sec. 4.1.2).
+ *   - Least squares by a Krylov iteration (LSQR, or CGLS as in Alg. 5) on
+ *     A R^{-1}, i.e. right-preconditioned by the low-precision R (Sec. 3.2.3),
+ *     with FP64 vectors, FP64 triangular solves and an FP64 (double-double
+ *     accumulated) residual check.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are column-major. A is m x n with leading dimension lda >= m;
+ *     R is n x n with ldr >= n. The problem needs m >= n >= 1 (Sec. 2.2:
+ *     m > n and full column rank; m == n is accepted).
+ *   - Matrix and vector pointers are DEVICE pointers owned by the caller; the
+ *     library never frees them. `work` is an optional caller-owned device
+ *     workspace of `work_bytes` bytes (query the size with the *_workspace_size
+ *     call); with work == NULL the handle allocates and keeps its own.
+ *   - Return values: QRX_OK (0) or a negative code detected on the host
+ *     before any device work is enqueued (nothing is modified then).
+ *     Numerical outcomes (positive codes) are reported through the status /
+ *     info outputs described per call.
+ *   - A handle is bound to one device and is not thread-safe: use one handle
+ *     per host thread.
+ */
+#ifndef QRX_H
+#define QRX_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define QRX_OK          0
+#define QRX_EINVAL     -1   /* bad argument (sizes, NULL pointer, enum, tolerance, workspace) */
+#define QRX_ENOMEM     -2   /* device allocation by the handle failed */
+#define QRX_EHIP       -3   /* a HIP runtime call or kernel launch failed */
+#define QRX_ESINGULAR   1   /* R has a zero or non-finite diagonal entry: A is not of
+                               full column rank in working precision (Sec. 2.2) */
+#define QRX_ENONFINITE  2   /* A (or b) holds a NaN or Inf */
+#define QRX_ENOCONV     3   /* the Krylov iteration reached max_iter above tol */
+
+typedef struct qrx_handle_s *qrx_handle;
+
+/* Operand precision of the trailing products R12 = Q1^T A2 and
+ * A2 -= Q1 R12 (Alg. 2); accumulation is FP32 in every mode. */
+typedef enum { QRX_FP32 = 0, QRX_FP16 = 1, QRX_BF16 = 2 } qrx_prec;
+
+/* QR options; an all-zero struct selects the defaults. */
+typedef struct {
+    int gemm_prec;        /* qrx_prec for recursion nodes wider than `cutoff` */
+    int panel_width;      /* nb: TSQR panel width, 1..32 (0 = 32; Sec. 3.1.3 uses 32) */
+    int cutoff;           /* c: nodes of width <= c use FP32 products (0 = 128, the
+                             cutoff of Alg. 2); rounded up to a multiple of nb */
+    int block_rows;       /* b: TSQR block rows, only 256 is supported (0 = 256; Sec. 3.1.3) */
+    int no_col_scaling;   /* 1 = do not scale FP16/BF16 operand columns by powers of two */
+    int panel_single_pass;/* 1 = one MGS sweep per TSQR block instead of two */
+} qrx_qr_opts;
+
+/* Least-squares options; an all-zero struct selects the defaults. */
+typedef struct {
+    qrx_qr_opts qr;
+    int method;           /* 0 = LSQR (default), 1 = CGLS (Alg. 5) */
+    double tol;           /* target for eta_F (0 = 1e-10); must be >= 0 */
+    int max_iter;         /* Krylov iteration cap (0 = 200, the cap of Sec. 4.2.3) */
+    int use_x0;           /* 1 = x holds the starting iterate on entry */
+} qrx_lls_opts;
+
+/* Result of a least-squares solve (host memory). */
+typedef struct {
+    int status;           /* QRX_OK, QRX_ESINGULAR, QRX_ENONFINITE or QRX_ENOCONV */
+    int iters;            /* Krylov iterations over all restarts */
+    int restarts;         /* residual certifications that failed and restarted */
+    double eta_F;         /* ||A^T r|| / (||A||_F ||r||), r = b - A x, for the returned x */
+    double resid_norm;    /* ||r||_2 */
+    double normA_F;       /* ||A||_F */
+    double qr_ms;         /* device time of the factorisation */
+    double krylov_ms;     /* device time of the iteration and checks */
+} qrx_lls_info;
+
+/* Per-kernel timing record (see qrx_timing_*). */
+typedef struct {
+    char name[40];
+    int64_t launches;
+    double total_ms;      /* sum of launch durations (HIP events on the launch stream) */
+    double flops;         /* algorithmic flops summed over launches */
+    double bytes;         /* algorithmic HBM bytes summed over launches */
+} qrx_kernel_stat;
+
+/* ---- handle ------------------------------------------------------------ */
+int  qrx_create(qrx_handle *h, int device);
+int  qrx_destroy(qrx_handle h);
+const char *qrx_status_string(int status);
+
+/* ---- QR ---------------------------------------------------------------- */
+/* Bytes of device workspace qrx_qr_factor needs for (m, n, opts). */
+int qrx_qr_workspace_size(qrx_handle h, int64_t m, int64_t n,
+                          const qrx_qr_opts *opts, size_t *bytes);
+
+/* Thin QR, A = Q R (Sec. 2.2; Alg. 2 with TSQR panels, eq. caqr).
+ * On entry A holds the matrix; on exit it holds Q (m x n, orthonormal columns
+ * up to the precision of the mode). R receives the n x n upper-triangular
+ * factor with positive diagonal; its strictly-lower part is set to zero.
+ * `status` (device int, may be NULL) receives QRX_OK, QRX_ENONFINITE or
+ * QRX_ESINGULAR when the stream reaches the end of the call. Asynchronous
+ * on `stream`. */
+int qrx_qr_factor(qrx_handle h, int64_t m, int64_t n, float *A, int64_t lda,
+                  float *R, int64_t ldr, void *work, size_t work_bytes,
+                  const qrx_qr_opts *opts, int *status, hipStream_t stream);
+
+/* Out-of-place variant: A (const, lda) is read once by the input scan, which
+ * writes the working copy into Q (m x n, ldq >= m); Q then receives the
+ * orthonormal factor. Same R, status and stream semantics as qrx_qr_factor. */
+int qrx_qr_factor_out(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
+                      float *Q, int64_t ldq, float *R, int64_t ldr, void *work,
+                      size_t work_bytes, const qrx_qr_opts *opts, int *status,
+                      hipStream_t stream);
+
+/* ---- least squares ----------------------------------------------------- */
+int qrx_lls_workspace_size(qrx_handle h, int64_t m, int64_t n,
+                           const qrx_lls_opts *opts, size_t *bytes);
+
+/* x = argmin ||A x - b||_2 (Sec. 2.2, eq. opt:lls) by the QR of A followed
+ * by a Krylov iteration on A R^{-1} (Sec. 3.2.3, Alg. 5), stopped when the
+ * certified eta_F <= tol. A (FP32) and b (FP64, length m) are not modified;
+ * x (FP64, length n) receives the solution (and holds x0 on entry if
+ * use_x0). `info` is a HOST pointer (required). The call blocks until the
+ * solve is complete on `stream`. */
+int qrx_lls_solve(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
+                  const double *b, double *x, void *work, size_t work_bytes,
+                  const qrx_lls_opts *opts, qrx_lls_info *info, hipStream_t stream);
+
+/* The Krylov step alone with a caller-supplied preconditioner R (device,
+ * FP32, n x n upper triangular, ldr >= n), or the identity when R == NULL.
+ * Same kernels and semantics as qrx_lls_solve after its factorisation. */
+int qrx_lls_solve_with_R(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
+                         const float *R, int64_t ldr, const double *b, double *x,
+                         void *work, size_t work_bytes, const qrx_lls_opts *opts,
+                         qrx_lls_info *info, hipStream_t stream);
+
+/* ---- timing ------------------------------------------------------------ */
+/* When enabled, every kernel launch is bracketed by HIP events on its
+ * stream. qrx_timing_get synchronises those events and returns one record
+ * per kernel name (at most `capacity`; `count` receives the number). */
+int qrx_timing_enable(qrx_handle h, int enable);
+int qrx_timing_reset(qrx_handle h);
+int qrx_timing_get(qrx_handle h, qrx_kernel_stat *out, int capacity, int *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QRX_H */

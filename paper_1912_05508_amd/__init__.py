@@ -1,0 +1,167 @@
+"""Mixed-precision QR and least squares on AMD MI355X (gfx950).
+
+Python front-end over libqrx.so: torch supplies device memory and the current
+stream; the computation is the library's HIP kernels.
+
+    qr(A, prec="fp16")          -> (Q, R, status)   A: (m, n) float32 cuda tensor
+    lstsq(A, b, prec="fp16")    -> (x, info)        b: (m,) float64 cuda tensor
+
+A is read as a column-major matrix (a tensor with strides (1, lda)); other
+layouts are copied into one first.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _lib
+from ._lib import (QRX_BF16, QRX_EHIP, QRX_EINVAL, QRX_ENOCONV, QRX_ENOMEM,  # noqa: F401
+                   QRX_ENONFINITE, QRX_ESINGULAR, QRX_FP16, QRX_FP32, QRX_OK, QrxError,
+                   lls_opts, qr_opts, qrx_kernel_stat, qrx_lls_info, qrx_lls_opts,
+                   qrx_qr_opts, status_string)
+
+__all__ = ["Handle", "qr", "lstsq", "colmajor", "qr_opts", "lls_opts", "QrxError"]
+
+
+def colmajor(t, ld=None):
+    """A (m, n) tensor laid out column-major with leading dimension ld >= m."""
+    import torch
+    m, n = t.shape
+    ld = ld or m
+    if t.stride() == (1, ld) or (n == 1 and t.stride(0) == 1 and ld == m):
+        return t
+    buf = torch.empty((n, ld), dtype=t.dtype, device=t.device)
+    out = buf.t()[:m, :]
+    out.copy_(t)
+    return out
+
+
+def _ld(t):
+    return t.stride(1) if t.shape[1] > 1 else max(t.shape[0], 1)
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Handle:
+    """Owns a qrx handle bound to the current CUDA (HIP) device."""
+
+    def __init__(self, device=None):
+        import torch
+        lib = _lib.load()
+        dev = torch.cuda.current_device() if device is None else device
+        h = C.c_void_p()
+        _lib.check(lib.qrx_create(C.byref(h), int(dev)), "qrx_create")
+        self.h = h
+        self.lib = lib
+
+    def close(self):
+        if self.h:
+            self.lib.qrx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- QR -----------------------------------------------------------------
+    def qr(self, A, prec="fp32", R=None, status=None, **kw):
+        """Factor column-major A in place (A -> Q); returns (Q, R, status tensor)."""
+        import torch
+        m, n = A.shape
+        assert A.dtype == torch.float32 and A.is_cuda
+        A = colmajor(A)
+        if R is None:
+            R = torch.empty((n, n), dtype=torch.float32, device=A.device).t()
+        if status is None:
+            status = torch.zeros(1, dtype=torch.int32, device=A.device)
+        o = qr_opts(prec, **kw)
+        rc = self.lib.qrx_qr_factor(self.h, m, n, C.c_void_p(A.data_ptr()), _ld(A),
+                                    C.c_void_p(R.data_ptr()), _ld(R), None, 0, C.byref(o),
+                                    C.c_void_p(status.data_ptr()), _stream())
+        _lib.check(rc, "qrx_qr_factor")
+        return A, R, status
+
+    def qr_out(self, A, Q, R, status, prec="fp32", **kw):
+        """Out-of-place QR: A (column-major, untouched) -> Q, R (preallocated)."""
+        m, n = A.shape
+        o = qr_opts(prec, **kw)
+        rc = self.lib.qrx_qr_factor_out(self.h, m, n, C.c_void_p(A.data_ptr()), _ld(A),
+                                        C.c_void_p(Q.data_ptr()), _ld(Q),
+                                        C.c_void_p(R.data_ptr()), _ld(R), None, 0, C.byref(o),
+                                        C.c_void_p(status.data_ptr()), _stream())
+        _lib.check(rc, "qrx_qr_factor_out")
+        return Q, R, status
+
+    # -- least squares --------------------------------------------------------
+    def lstsq(self, A, b, prec="fp32", x=None, R=None, with_R=False, **kw):
+        """x = argmin ||A x - b|| (A untouched); returns (x, info dict)."""
+        import torch
+        m, n = A.shape
+        assert A.dtype == torch.float32 and A.is_cuda
+        A = colmajor(A)
+        b = b.contiguous()
+        assert b.dtype == torch.float64 and b.numel() == m
+        use_x0 = x is not None
+        if x is None:
+            x = torch.zeros(n, dtype=torch.float64, device=A.device)
+        o = lls_opts(prec, use_x0=use_x0, **kw)
+        info = qrx_lls_info()
+        if with_R:
+            rp = C.c_void_p(R.data_ptr()) if R is not None else None
+            ldr = _ld(R) if R is not None else n
+            rc = self.lib.qrx_lls_solve_with_R(self.h, m, n, C.c_void_p(A.data_ptr()), _ld(A),
+                                               rp, ldr, C.c_void_p(b.data_ptr()),
+                                               C.c_void_p(x.data_ptr()), None, 0, C.byref(o),
+                                               C.byref(info), _stream())
+        else:
+            rc = self.lib.qrx_lls_solve(self.h, m, n, C.c_void_p(A.data_ptr()), _ld(A),
+                                        C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                        None, 0, C.byref(o), C.byref(info), _stream())
+        _lib.check(rc, "qrx_lls_solve")
+        return x, info.as_dict()
+
+    # -- timing ---------------------------------------------------------------
+    def timing(self, enable=True):
+        _lib.check(self.lib.qrx_timing_enable(self.h, 1 if enable else 0))
+
+    def timing_reset(self):
+        _lib.check(self.lib.qrx_timing_reset(self.h))
+
+    def timing_get(self):
+        cap = 64
+        arr = (qrx_kernel_stat * cap)()
+        cnt = C.c_int()
+        _lib.check(self.lib.qrx_timing_get(self.h, arr, cap, C.byref(cnt)))
+        out = {}
+        for i in range(min(cnt.value, cap)):
+            s = arr[i]
+            out[s.name.decode()] = dict(launches=s.launches, total_ms=s.total_ms, flops=s.flops,
+                                        bytes=s.bytes)
+        return out
+
+
+_default = None
+
+
+def _handle():
+    global _default
+    if _default is None:
+        _default = Handle()
+    return _default
+
+
+def qr(A, prec="fp32", **kw):
+    """QR of a column-major copy of A: returns (Q, R, status)."""
+    import torch
+    m, n = A.shape
+    W = torch.empty((n, m), dtype=torch.float32, device=A.device).t()
+    W.copy_(A)
+    return _handle().qr(W, prec=prec, **kw)
+
+
+def lstsq(A, b, prec="fp32", **kw):
+    return _handle().lstsq(A, b, prec=prec, **kw)

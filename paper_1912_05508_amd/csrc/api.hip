@@ -1,0 +1,864 @@
+// Host runtime of the qrx C ABI: argument validation, workspace carving, the
+// static recursion schedule of Alg. 2, the TSQR level plan of eq. caqr, the
+// Krylov driver of Sec. 3.2.3 and per-kernel timing.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "krylov.hpp"
+#include "qrx_internal.hpp"
+
+using namespace qrx;
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct PendingTiming {
+    std::string name;
+    hipEvent_t a, b;
+    double flops, bytes;
+};
+
+struct qrx_handle_s {
+    int device = -1;
+    void *pool = nullptr;
+    size_t pool_bytes = 0;
+    double *host_state = nullptr;   // pinned mirror of the Krylov scalar state
+    int *host_flags = nullptr;
+    bool timing = false;
+    std::vector<PendingTiming> pending;
+    std::vector<hipEvent_t> spare;
+    std::map<std::string, qrx_kernel_stat> stats;
+
+    hipEvent_t ev() {
+        if (!spare.empty()) {
+            hipEvent_t e = spare.back();
+            spare.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        hipEventCreate(&e);
+        return e;
+    }
+};
+
+namespace {
+
+struct Rec {   // brackets one launch (or launch group) with events when timing is on
+    qrx_handle h;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    Rec(qrx_handle h_, hipStream_t s_) : h(h_), s(s_) {
+        if (h->timing) {
+            a = h->ev();
+            hipEventRecord(a, s);
+        }
+    }
+    void end(const char *name, double flops, double bytes) {
+        if (h->timing) {
+            hipEvent_t b = h->ev();
+            hipEventRecord(b, s);
+            h->pending.push_back({name, a, b, flops, bytes});
+        }
+    }
+};
+
+#define QRX_TRY(expr)                                \
+    do {                                             \
+        hipError_t e__ = (expr);                     \
+        if (e__ != hipSuccess) return QRX_EHIP;      \
+    } while (0)
+
+// bump allocator over a device buffer (or a size counter when base == null)
+struct Carve {
+    char *base;
+    size_t off = 0;
+    explicit Carve(void *b) : base((char *)b) {}
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
+
+struct QrCfg {
+    int prec, nb, c, reorth, scaling;
+};
+
+int resolve_qr(const qrx_qr_opts *o, QrCfg &c) {
+    qrx_qr_opts z;
+    memset(&z, 0, sizeof(z));
+    if (!o) o = &z;
+    if (o->gemm_prec < 0 || o->gemm_prec > 2) return QRX_EINVAL;
+    if (o->panel_width < 0 || o->panel_width > 32) return QRX_EINVAL;
+    if (o->cutoff < 0) return QRX_EINVAL;
+    if (o->block_rows != 0 && o->block_rows != kPanelThreads) return QRX_EINVAL;
+    if (o->no_col_scaling < 0 || o->no_col_scaling > 1) return QRX_EINVAL;
+    if (o->panel_single_pass < 0 || o->panel_single_pass > 1) return QRX_EINVAL;
+    c.prec = o->gemm_prec;
+    c.nb = o->panel_width ? o->panel_width : 32;
+    int cut = o->cutoff ? o->cutoff : 128;
+    if (cut < c.nb) cut = c.nb;
+    c.c = (int)round_up(cut, c.nb);
+    c.reorth = o->panel_single_pass ? 0 : 1;
+    c.scaling = o->no_col_scaling ? 0 : 1;
+    return QRX_OK;
+}
+
+struct Op {
+    int kind;            // 0 = panel, 1 = node (projection + update)
+    int64_t c0, k, n2;   // panel: columns [c0, c0 + k); node: Q1 = [c0, c0+k), A2 = [c0+k, c0+k+n2)
+    int prec;
+};
+
+void plan_rec(int64_t c0, int64_t w, const QrCfg &c, std::vector<Op> &ops) {
+    if (w <= c.nb) {
+        ops.push_back({0, c0, w, 0, QRX_FP32});
+        return;
+    }
+    const int64_t unit = (w > c.c) ? c.c : c.nb;
+    const int64_t n1 = unit * ((w + 2 * unit - 1) / (2 * unit));
+    plan_rec(c0, n1, c, ops);
+    ops.push_back({1, c0, n1, w - n1, (w > c.c) ? c.prec : QRX_FP32});
+    plan_rec(c0 + n1, w - n1, c, ops);
+}
+
+// TSQR level sizes for a panel of m rows (level 0 .. nlev).
+void tsqr_sizes(int64_t m, int nb, std::vector<int64_t> &nblk) {
+    nblk.clear();
+    int64_t b0 = (m + kPanelThreads - 1) / kPanelThreads;
+    nblk.push_back(b0);
+    int64_t units = b0;
+    while (nblk.back() > 1) {
+        const int64_t rows = units * nb;
+        const int64_t nb_l = (rows + kPanelThreads - 1) / kPanelThreads;
+        nblk.push_back(nb_l);
+        units = nb_l;
+    }
+}
+
+struct QrWork {
+    int *flags;
+    float *colmax, *uscale, *part, *rtop, *stack_base;
+    double *colss, *normA;
+    size_t stack_floats;
+};
+
+void carve_qr(Carve &cv, int64_t m, int64_t n, const QrCfg &c, const std::vector<Op> &ops,
+              QrWork &w) {
+    w.flags = cv.take<int>(4);
+    w.colmax = cv.take<float>(n);
+    w.uscale = cv.take<float>(n);
+    w.colss = cv.take<double>(n);
+    w.normA = cv.take<double>(1);
+    size_t part = 1;
+    for (const Op &o : ops)
+        if (o.kind == 1) {
+            const size_t s = projection_splits(m, o.k, o.n2);
+            part = std::max(part, s * (size_t)o.k * (size_t)o.n2);
+        }
+    w.part = cv.take<float>(part);
+    w.rtop = cv.take<float>(32 * 32);
+    std::vector<int64_t> nblk;
+    tsqr_sizes(m, 32, nblk);
+    size_t st = 0;
+    for (size_t l = 1; l < nblk.size(); ++l) st += (size_t)nblk[l - 1] * 32 * 32 + 64;
+    w.stack_floats = st;
+    w.stack_base = cv.take<float>(st + 1);
+}
+
+int run_panel(qrx_handle h, hipStream_t s, int64_t m, float *P, int64_t ld, int w, float *R,
+              int64_t ldr, const float *colmax, const QrCfg &c, QrWork &ws) {
+    constexpr int NB = 32;
+    std::vector<int64_t> nblk;
+    tsqr_sizes(m, NB, nblk);
+    TsqrLevels lv;
+    memset(&lv, 0, sizeof(lv));
+    lv.nlev = (int)nblk.size() - 1;
+    if (lv.nlev > kMaxLevels) return QRX_EINVAL;
+    float *cur = ws.stack_base;
+    for (int l = 0; l <= lv.nlev; ++l) lv.nblk[l] = nblk[l];
+    for (int l = 1; l <= lv.nlev; ++l) {
+        lv.stack[l] = cur;
+        cur += nblk[l - 1] * NB * NB + 64;
+    }
+    const double flops_blk = (c.reorth ? 2.0 : 1.0) * 2.0 * 256.0 * w * w;
+    {
+        Rec r(h, s);
+        float *rn = lv.nlev ? lv.stack[1] : ws.rtop;
+        int64_t ldn = lv.nlev ? nblk[0] * NB : NB;
+        QRX_TRY(launch_tsqr_level(s, P, ld, m, w, nblk[0], 1, rn, ldn, c.reorth, colmax));
+        r.end("tsqr_leaf", flops_blk * nblk[0], 8.0 * m * w);
+    }
+    for (int l = 1; l <= lv.nlev; ++l) {
+        Rec r(h, s);
+        const int64_t rows = nblk[l - 1] * NB;
+        float *rn = (l < lv.nlev) ? lv.stack[l + 1] : ws.rtop;
+        int64_t ldn = (l < lv.nlev) ? nblk[l] * NB : NB;
+        QRX_TRY(launch_tsqr_level(s, lv.stack[l], rows, rows, w, nblk[l], NB, rn, ldn, c.reorth,
+                                  nullptr));
+        r.end("tsqr_tree", flops_blk * nblk[l], 8.0 * rows * w);
+    }
+    if (lv.nlev > 0) {
+        Rec r(h, s);
+        QRX_TRY(launch_tsqr_qform(s, P, ld, m, w, lv));
+        r.end("tsqr_qform", 2.0 * m * w * w, 8.0 * m * w);
+    }
+    {
+        Rec r(h, s);
+        QRX_TRY(launch_copy_r_block(s, ws.rtop, NB, w, R, ldr, colmax));
+        r.end("copy_r", 0, 0);
+    }
+    return QRX_OK;
+}
+
+// The QR of W (m x n, ld ldw, in place -> Q) into R; colmax must hold the
+// column max-abs of W on entry.
+int run_qr(qrx_handle h, hipStream_t s, int64_t m, int64_t n, float *W, int64_t ldw, float *R,
+           int64_t ldr, const QrCfg &c, const std::vector<Op> &ops, QrWork &ws) {
+    for (const Op &o : ops) {
+        if (o.kind == 0) {
+            int rc = run_panel(h, s, m, W + o.c0 * ldw, ldw, (int)o.k, R + o.c0 + o.c0 * ldr, ldr,
+                               ws.colmax + o.c0, c, ws);
+            if (rc) return rc;
+        } else {
+            const float *Q1 = W + o.c0 * ldw;
+            float *A2 = W + (o.c0 + o.k) * ldw;
+            float *R12 = R + o.c0 + (o.c0 + o.k) * ldr;
+            float *cm = ws.colmax + o.c0 + o.k;
+            const int splits = projection_splits(m, o.k, o.n2);
+            const double fl = 2.0 * m * o.k * o.n2;
+            const char *pn = o.prec == QRX_FP16 ? "proj_fp16" : (o.prec == QRX_BF16 ? "proj_bf16" : "proj_fp32");
+            const char *un = o.prec == QRX_FP16 ? "update_fp16" : (o.prec == QRX_BF16 ? "update_bf16" : "update_fp32");
+            {
+                Rec r(h, s);
+                QRX_TRY(launch_projection(s, o.prec, c.scaling, m, o.k, o.n2, Q1, A2, ldw, cm,
+                                          ws.part, splits));
+                r.end(pn, fl, 4.0 * m * (o.k + o.n2) + 4.0 * splits * o.k * o.n2);
+            }
+            {
+                Rec r(h, s);
+                QRX_TRY(launch_proj_reduce(s, o.prec, c.scaling, o.k, o.n2, ws.part, splits, R12,
+                                           ldr, cm, ws.uscale));
+                r.end("proj_reduce", (double)splits * o.k * o.n2, 4.0 * (splits + 1) * o.k * o.n2);
+            }
+            {
+                Rec r(h, s);
+                QRX_TRY(launch_update(s, o.prec, c.scaling, m, o.k, o.n2, Q1, A2, ldw, R12, ldr,
+                                      ws.uscale, cm));
+                r.end(un, fl, 4.0 * m * o.k + 8.0 * m * o.n2);
+            }
+        }
+    }
+    return QRX_OK;
+}
+
+bool bad_ptr(const void *p) { return p == nullptr; }
+
+int check_qr_args(qrx_handle h, int64_t m, int64_t n, int64_t lda, int64_t ldr) {
+    if (!h) return QRX_EINVAL;
+    if (n < 1 || m < n || lda < m || ldr < n) return QRX_EINVAL;
+    if (n > (int64_t)1 << 30 || m > ((int64_t)1 << 40)) return QRX_EINVAL;
+    return QRX_OK;
+}
+
+int ensure_pool(qrx_handle h, size_t bytes, void **out) {
+    if (h->device < 0) return QRX_EHIP;
+    if (h->pool_bytes < bytes) {
+        if (h->pool) hipFree(h->pool);
+        h->pool = nullptr;
+        h->pool_bytes = 0;
+        if (hipMalloc(&h->pool, bytes) != hipSuccess) return QRX_ENOMEM;
+        h->pool_bytes = bytes;
+    }
+    *out = h->pool;
+    return QRX_OK;
+}
+
+// ---- Krylov workspace --------------------------------------------------------
+struct KrWork {
+    double *Dinv, *u, *r, *v, *t, *d, *z, *y, *vt, *x, *xbest, *q;
+    double *part_n, *part_n2, *part_t, *ssq, *st;
+    int splits_n, splits_t;
+};
+
+void carve_kr(Carve &cv, int64_t m, int64_t n, KrWork &k) {
+    const int64_t np = round_up(n, kTrsvBlock);
+    k.splits_n = kr_gemv_n_splits(m, n);
+    k.splits_t = kr_gemv_t_splits(m);
+    k.Dinv = cv.take<double>((size_t)np * 64);
+    k.u = cv.take<double>(m);
+    k.r = cv.take<double>(m);
+    k.q = cv.take<double>(m);
+    k.v = cv.take<double>(np);
+    k.t = cv.take<double>(np);
+    k.d = cv.take<double>(np);
+    k.z = cv.take<double>(np);
+    k.y = cv.take<double>(np);
+    k.vt = cv.take<double>(np);
+    k.x = cv.take<double>(np);
+    k.xbest = cv.take<double>(np);
+    k.part_n = cv.take<double>((size_t)k.splits_n * m);
+    k.part_n2 = cv.take<double>((size_t)k.splits_n * m);
+    k.part_t = cv.take<double>((size_t)k.splits_t * np);
+    k.ssq = cv.take<double>((size_t)((std::max(m, np) + 255) / 256 + 1));
+    k.st = cv.take<double>(S_COUNT);
+}
+
+struct KrCfg {
+    int method, max_iter;
+    double tol;
+};
+
+int resolve_lls(const qrx_lls_opts *o, KrCfg &k) {
+    qrx_lls_opts z;
+    memset(&z, 0, sizeof(z));
+    if (!o) o = &z;
+    if (o->method < 0 || o->method > 1) return QRX_EINVAL;
+    if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return QRX_EINVAL;
+    if (o->max_iter < 0) return QRX_EINVAL;
+    if (o->use_x0 < 0 || o->use_x0 > 1) return QRX_EINVAL;
+    k.method = o->method;
+    k.tol = o->tol > 0.0 ? o->tol : 1e-10;
+    k.max_iter = o->max_iter ? o->max_iter : 200;
+    return QRX_OK;
+}
+
+int sync_state(qrx_handle h, hipStream_t s, const double *st) {
+    if (hipMemcpyAsync(h->host_state, st, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s) !=
+        hipSuccess)
+        return QRX_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return QRX_EHIP;
+    return QRX_OK;
+}
+
+unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// Certification: r = b - A x (double-double), z = A^T r, eta_F (into st).
+int certify(qrx_handle h, hipStream_t s, int64_t m, int64_t n, int64_t np, const float *A,
+            int64_t lda, const double *b, KrWork &k, double tol) {
+    Rec r(h, s);
+    QRX_TRY(kr_gemv_n(s, m, n, A, lda, k.x, k.part_n, k.part_n2, k.splits_n, 1));
+    QRX_TRY(kr_resid_combine(s, m, b, k.part_n, k.part_n2, k.splits_n, k.r, k.ssq));
+    QRX_TRY(kr_norm(s, k.ssq, nblocks(m), k.st, S_RNORM, 1));
+    QRX_TRY(kr_gemv_t(s, m, n, A, lda, k.r, k.part_t));
+    QRX_TRY(kr_combine_n(s, n, k.part_t, k.splits_t, k.z, k.ssq));
+    QRX_TRY(kr_norm(s, k.ssq, nblocks(n), k.st, S_ZNORM, 1));
+    QRX_TRY(kr_eta(s, k.st, tol));
+    r.end("certify", 2.0 * 2.0 * m * n, 8.0 * m * n + 24.0 * m);
+    return QRX_OK;
+}
+
+// Right-preconditioned LSQR / CGLS (Sec. 3.2.3) on the device, wrapped in
+// iterative refinement: every outer step certifies the current x with the
+// true residual (double-double) and restarts the inner iteration on the
+// correction problem min ||A R^{-1} dy - r||; the inner iteration runs until
+// its own estimate of ||R^{-T} A^T r|| / ||r||, scaled by rho / ||A||_F
+// (rho ~ ||R||_2), drops below tol * gam. The best certified iterate is
+// returned. Blocks until done.
+int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A, int64_t lda,
+               const float *R, int64_t ldr, const double *b, double *x_user, bool use_x0,
+               const KrCfg &cfg, KrWork &k, qrx_lls_info *info, double normA_host,
+               double rho) {
+    const int64_t np = round_up(n, kTrsvBlock);
+    const double tol = cfg.tol;
+    double *st = k.st;
+    double *hs = h->host_state;
+    {
+        Rec r(h, s);
+        if (R) QRX_TRY(kr_dinv(s, n, np, R, ldr, k.Dinv));
+        r.end("dinv", (double)np * 64 * 64 * 64 / 3.0, 4.0 * np * 64);
+    }
+    // the padded tails [n, np) of every n-vector must stay exactly zero
+    for (double *vec : {k.x, k.xbest, k.v, k.t, k.d, k.z, k.y, k.vt}) QRX_TRY(kr_zero(s, np, vec));
+    if (use_x0) QRX_TRY(hipMemcpyAsync(k.x, x_user, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    for (int i = 0; i < S_COUNT; ++i) QRX_TRY(kr_set(s, st, i, 0.0));
+    QRX_TRY(kr_set(s, st, S_NORMA, normA_host));
+    QRX_TRY(kr_set(s, st, S_GAMMA_TOL, 1.0));
+    const double trig_scale = (normA_host > 0.0) ? rho / normA_host : 1.0;
+
+    int rc;
+    auto trsv = [&](const double *in, double *out, int trans) -> int {
+        Rec r(h, s);
+        QRX_TRY(kr_trsv(s, n, np, R, ldr, k.Dinv, in, k.y, out, trans));
+        r.end(trans ? "trsv_t" : "trsv", R ? (double)np * np : 0.0, R ? 2.0 * np * np : 0.0);
+        return QRX_OK;
+    };
+    auto gemv_n = [&](const double *in) -> int {
+        Rec r(h, s);
+        QRX_TRY(kr_gemv_n(s, m, n, A, lda, in, k.part_n, nullptr, k.splits_n, 0));
+        r.end("gemv_n", 2.0 * m * n, 4.0 * m * n + 8.0 * k.splits_n * m);
+        return QRX_OK;
+    };
+    auto gemv_t = [&](const double *in) -> int {
+        Rec r(h, s);
+        QRX_TRY(kr_gemv_t(s, m, n, A, lda, in, k.part_t));
+        r.end("gemv_t", 2.0 * m * n, 4.0 * m * n + 8.0 * m);
+        return QRX_OK;
+    };
+    auto certify_now = [&](double &eta) -> int {
+        int e = certify(h, s, m, n, np, A, lda, b, k, tol);
+        if (e) return e;
+        e = sync_state(h, s, st);
+        if (e) return e;
+        eta = (hs[S_RNORM] > 0.0) ? hs[S_ETA] : 0.0;
+        return QRX_OK;
+    };
+
+    double eta = 0.0;
+    if ((rc = certify_now(eta))) return rc;
+    double best = eta, best_rn = hs[S_RNORM];
+    QRX_TRY(kr_copy(s, np, k.x, k.xbest));
+    int iters = 0, outers = 0, no_gain = 0;
+    double prev = best, gam = 1.0;
+    while (best > tol && iters < cfg.max_iter) {
+        ++outers;
+        // ---- restart on the certified residual r (k.r) and z = A^T r (k.z)
+        if (cfg.method == 0) {
+            // u = r (beta = ||r||); v = R^{-T} z / beta, alpha = ||v||, v /= alpha
+            QRX_TRY(kr_copy(s, m, k.r, k.u));
+            QRX_TRY(kr_lsqr_restart(s, st, 0));
+            if ((rc = trsv(k.z, k.vt, 1))) return rc;
+            QRX_TRY(kr_axpby(s, np, st, -2, S_BETA, k.vt, -1, 1.0, nullptr, k.v, k.ssq));
+            QRX_TRY(kr_norm(s, k.ssq, nblocks(np), st, S_ALPHA, 1));
+            QRX_TRY(kr_axpby(s, np, st, -2, S_ALPHA, k.v, -1, 1.0, nullptr, k.v, nullptr));
+            QRX_TRY(kr_lsqr_restart(s, st, 1));
+        } else {
+            // s = R^{-T} z, p = s (in v), gamma = ||s||^2; r (k.r) is the recurrence residual
+            if ((rc = trsv(k.z, k.vt, 1))) return rc;
+            QRX_TRY(kr_axpby(s, np, st, -2, -1, k.vt, -1, 1.0, nullptr, k.v, k.ssq));
+            QRX_TRY(kr_norm(s, k.ssq, nblocks(np), st, S_GAMMA, 0));
+        }
+        bool first = true;
+        double best_est = HUGE_VAL;
+        int kin = 0, last_new = 0;
+        while (iters < cfg.max_iter) {
+            ++iters;
+            ++kin;
+            if (cfg.method == 0) {
+                // t = R^{-1} v; u~ = A t - (alpha/beta_old) u~_old; beta = ||u~||
+                if ((rc = trsv(k.v, k.t, 0))) return rc;
+                if ((rc = gemv_n(k.t))) return rc;
+                {
+                    Rec r(h, s);
+                    QRX_TRY(kr_combine_m(s, m, k.part_n, k.splits_n, st, S_ALPHA, S_BETA, k.u, k.u,
+                                         k.ssq));
+                    QRX_TRY(kr_norm(s, k.ssq, nblocks(m), st, S_BETA, 1));
+                    r.end("lsqr_u", 0, 8.0 * m * (k.splits_n + 2));
+                }
+                if ((rc = gemv_t(k.u))) return rc;
+                {
+                    Rec r(h, s);
+                    QRX_TRY(kr_combine_n(s, n, k.part_t, k.splits_t, k.z, k.ssq));
+                    r.end("lsqr_z", 0, 8.0 * n * (k.splits_t + 1));
+                }
+                if ((rc = trsv(k.z, k.vt, 1))) return rc;
+                {
+                    Rec r(h, s);
+                    // v~ = vt / beta - beta v ; alpha = ||v~|| ; Givens step ; x, d update
+                    QRX_TRY(kr_axpby(s, np, st, -2, S_BETA, k.vt, S_BETA, -1.0, k.v, k.v, k.ssq));
+                    QRX_TRY(kr_norm(s, k.ssq, nblocks(np), st, S_ALPHA, 1));
+                    QRX_TRY(kr_lsqr_scalar(s, st, tol));
+                    QRX_TRY(kr_lsqr_xd(s, n, st, k.t, k.d, k.x, k.v, first ? 1 : 0));
+                    QRX_TRY(kr_lsqr_shift(s, st));
+                    r.end("lsqr_scalars", 0, 0);
+                }
+                first = false;
+            } else {
+                // Alg. 5: t = R^{-1} p; q = A t; alpha = gamma/||q||^2; x += alpha t;
+                // r -= alpha q; s = R^{-T} A^T r; beta = ||s||^2/gamma; p = s + beta p
+                if ((rc = trsv(k.v, k.t, 0))) return rc;
+                if ((rc = gemv_n(k.t))) return rc;
+                {
+                    Rec r(h, s);
+                    QRX_TRY(kr_combine_m(s, m, k.part_n, k.splits_n, st, 0, -1, nullptr, k.q, k.ssq));
+                    QRX_TRY(kr_norm(s, k.ssq, nblocks(m), st, S_DELTA, 0));
+                    QRX_TRY(kr_cgls_alpha(s, st));
+                    QRX_TRY(kr_cgls_xr(s, m, n, st, k.t, k.x, k.q, k.r, k.ssq));
+                    QRX_TRY(kr_norm(s, k.ssq, nblocks(std::max(m, n)), st, S_RSS, 0));
+                    r.end("cgls_vec", 0, 0);
+                }
+                if ((rc = gemv_t(k.r))) return rc;
+                {
+                    Rec r(h, s);
+                    QRX_TRY(kr_combine_n(s, n, k.part_t, k.splits_t, k.z, k.ssq));
+                    r.end("cgls_z", 0, 0);
+                }
+                if ((rc = trsv(k.z, k.vt, 1))) return rc;
+                {
+                    Rec r(h, s);
+                    QRX_TRY(kr_axpby(s, np, st, -2, -1, k.vt, -1, 1.0, nullptr, k.vt, k.ssq));
+                    QRX_TRY(kr_norm(s, k.ssq, nblocks(np), st, S_GAMMANEW, 0));
+                    QRX_TRY(kr_cgls_beta(s, st, tol));
+                    QRX_TRY(kr_axpby(s, np, st, -2, -1, k.vt, S_CGBETA, 1.0, k.v, k.v, nullptr));
+                    r.end("cgls_scalars", 0, 0);
+                }
+            }
+            if ((rc = sync_state(h, s, st))) return rc;
+            const double est = hs[S_EST];
+            if (est < 0.99 * best_est) {
+                best_est = est;
+                last_new = kin;
+            }
+            const bool finite = std::isfinite(est);
+            const bool cg_stall = cfg.method == 1 &&
+                                  ((kin - last_new) > std::max(100, kin / 2) || est > 100.0 * best_est);
+            if (!finite || est * trig_scale <= tol * gam || cg_stall) break;
+        }
+        // ---- certify; keep the best iterate
+        if ((rc = certify_now(eta))) return rc;
+        if (eta < best) {
+            best = eta;
+            best_rn = hs[S_RNORM];
+            QRX_TRY(kr_copy(s, np, k.x, k.xbest));
+        } else {
+            QRX_TRY(kr_copy(s, np, k.xbest, k.x));
+            if ((rc = certify_now(eta))) return rc;
+        }
+        no_gain = (best > 0.5 * prev) ? no_gain + 1 : 0;
+        prev = best;
+        if (no_gain >= 3) break;
+        if (best > tol) gam = std::max(0.01, 0.5 * gam);
+    }
+    QRX_TRY(hipMemcpyAsync(x_user, k.xbest, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    QRX_TRY(hipStreamSynchronize(s));
+    info->iters = iters;
+    info->restarts = outers > 0 ? outers - 1 : 0;
+    info->eta_F = best;
+    info->resid_norm = best_rn;
+    info->status = (best <= tol) ? QRX_OK : QRX_ENOCONV;
+    return QRX_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *qrx_status_string(int st) {
+    switch (st) {
+        case QRX_OK: return "QRX_OK: success";
+        case QRX_EINVAL: return "QRX_EINVAL: invalid argument";
+        case QRX_ENOMEM: return "QRX_ENOMEM: device allocation failed";
+        case QRX_EHIP: return "QRX_EHIP: HIP runtime error";
+        case QRX_ESINGULAR: return "QRX_ESINGULAR: R has a zero or non-finite diagonal entry";
+        case QRX_ENONFINITE: return "QRX_ENONFINITE: input holds NaN or Inf";
+        case QRX_ENOCONV: return "QRX_ENOCONV: iteration limit reached above tolerance";
+        default: return "unknown qrx status";
+    }
+}
+
+int qrx_create(qrx_handle *out, int device) {
+    if (!out) return QRX_EINVAL;
+    *out = nullptr;
+    qrx_handle h = new qrx_handle_s();
+    h->device = device;
+    if (device >= 0) {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || device >= count ||
+            hipSetDevice(device) != hipSuccess) {
+            delete h;
+            return QRX_EHIP;
+        }
+        if (hipHostMalloc((void **)&h->host_state, S_COUNT * sizeof(double)) != hipSuccess) {
+            delete h;
+            return QRX_ENOMEM;
+        }
+        if (hipHostMalloc((void **)&h->host_flags, 4 * sizeof(int)) != hipSuccess) {
+            hipHostFree(h->host_state);
+            delete h;
+            return QRX_ENOMEM;
+        }
+    }
+    *out = h;
+    return QRX_OK;
+}
+
+int qrx_destroy(qrx_handle h) {
+    if (!h) return QRX_EINVAL;
+    if (h->device >= 0) {
+        hipSetDevice(h->device);
+        for (auto &p : h->pending) {
+            hipEventDestroy(p.a);
+            hipEventDestroy(p.b);
+        }
+        for (auto e : h->spare) hipEventDestroy(e);
+        if (h->pool) hipFree(h->pool);
+        if (h->host_state) hipHostFree(h->host_state);
+        if (h->host_flags) hipHostFree(h->host_flags);
+    }
+    delete h;
+    return QRX_OK;
+}
+
+int qrx_qr_workspace_size(qrx_handle h, int64_t m, int64_t n, const qrx_qr_opts *opts,
+                          size_t *bytes) {
+    if (!bytes) return QRX_EINVAL;
+    int rc = check_qr_args(h, m, n, m, n);
+    if (rc) return rc;
+    QrCfg c;
+    if ((rc = resolve_qr(opts, c))) return rc;
+    std::vector<Op> ops;
+    plan_rec(0, n, c, ops);
+    Carve cv(nullptr);
+    QrWork w;
+    carve_qr(cv, m, n, c, ops, w);
+    *bytes = cv.off + 256;
+    return QRX_OK;
+}
+
+static int qr_common(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
+                     float *Q, int64_t ldq, float *R, int64_t ldr, void *work,
+                     size_t work_bytes, const qrx_qr_opts *opts, int *status,
+                     hipStream_t stream) {
+    int rc = check_qr_args(h, m, n, lda, ldr);
+    if (rc) return rc;
+    if (ldq < m) return QRX_EINVAL;
+    if (bad_ptr(A) || bad_ptr(R) || bad_ptr(Q)) return QRX_EINVAL;
+    QrCfg c;
+    if ((rc = resolve_qr(opts, c))) return rc;
+    std::vector<Op> ops;
+    plan_rec(0, n, c, ops);
+    size_t need = 0;
+    {
+        Carve cv(nullptr);
+        QrWork w;
+        carve_qr(cv, m, n, c, ops, w);
+        need = cv.off + 256;
+    }
+    if (work && work_bytes < need) return QRX_EINVAL;
+    if (h->device < 0) return QRX_EHIP;
+    if (hipSetDevice(h->device) != hipSuccess) return QRX_EHIP;
+    if (!work) {
+        if ((rc = ensure_pool(h, need, &work))) return rc;
+    }
+    Carve cv(work);
+    QrWork ws;
+    carve_qr(cv, m, n, c, ops, ws);
+    QRX_TRY(hipMemsetAsync(ws.flags, 0, 4 * sizeof(int), stream));
+    {
+        Rec r(h, stream);
+        const bool copy = (Q != A);
+        QRX_TRY(launch_scan(stream, m, n, A, lda, copy ? Q : nullptr, ldq, ws.colmax, ws.colss,
+                            ws.flags));
+        r.end("scan", 0, (copy ? 8.0 : 4.0) * m * n);
+    }
+    if ((rc = run_qr(h, stream, m, n, Q, ldq, R, ldr, c, ops, ws))) return rc;
+    {
+        Rec r(h, stream);
+        QRX_TRY(launch_r_finalize(stream, n, R, ldr, ws.flags));
+        r.end("r_finalize", 0, 4.0 * n * n);
+    }
+    if (status) QRX_TRY(launch_status_out(stream, ws.flags, status));
+    return QRX_OK;
+}
+
+int qrx_qr_factor(qrx_handle h, int64_t m, int64_t n, float *A, int64_t lda, float *R,
+                  int64_t ldr, void *work, size_t work_bytes, const qrx_qr_opts *opts,
+                  int *status, hipStream_t stream) {
+    return qr_common(h, m, n, A, lda, A, lda, R, ldr, work, work_bytes, opts, status, stream);
+}
+
+int qrx_qr_factor_out(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
+                      float *Q, int64_t ldq, float *R, int64_t ldr, void *work,
+                      size_t work_bytes, const qrx_qr_opts *opts, int *status,
+                      hipStream_t stream) {
+    return qr_common(h, m, n, A, lda, Q, ldq, R, ldr, work, work_bytes, opts, status, stream);
+}
+
+static int lls_sizes(int64_t m, int64_t n, const QrCfg &c, const std::vector<Op> &ops,
+                     bool with_qr, size_t *bytes) {
+    Carve cv(nullptr);
+    QrWork w;
+    carve_qr(cv, m, n, c, ops, w);
+    if (with_qr) {
+        cv.take<float>((size_t)round_up(m, 64) * n);
+        cv.take<float>((size_t)round_up(n, 64) * n);
+    }
+    KrWork k;
+    carve_kr(cv, m, n, k);
+    *bytes = cv.off + 256;
+    return QRX_OK;
+}
+
+int qrx_lls_workspace_size(qrx_handle h, int64_t m, int64_t n, const qrx_lls_opts *opts,
+                           size_t *bytes) {
+    if (!bytes) return QRX_EINVAL;
+    int rc = check_qr_args(h, m, n, m, n);
+    if (rc) return rc;
+    QrCfg c;
+    KrCfg kc;
+    if ((rc = resolve_qr(opts ? &opts->qr : nullptr, c))) return rc;
+    if ((rc = resolve_lls(opts, kc))) return rc;
+    std::vector<Op> ops;
+    plan_rec(0, n, c, ops);
+    return lls_sizes(m, n, c, ops, true, bytes);
+}
+
+static int lls_common(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
+                      const float *Rin, int64_t ldr, bool with_qr, const double *b, double *x,
+                      void *work, size_t work_bytes, const qrx_lls_opts *opts,
+                      qrx_lls_info *info, hipStream_t stream) {
+    int rc = check_qr_args(h, m, n, lda, with_qr ? n : ldr);
+    if (rc) return rc;
+    if (bad_ptr(A) || bad_ptr(b) || bad_ptr(x) || !info) return QRX_EINVAL;
+    QrCfg c;
+    KrCfg kc;
+    if ((rc = resolve_qr(opts ? &opts->qr : nullptr, c))) return rc;
+    if ((rc = resolve_lls(opts, kc))) return rc;
+    std::vector<Op> ops;
+    plan_rec(0, n, c, ops);
+    size_t need = 0;
+    lls_sizes(m, n, c, ops, with_qr, &need);
+    if (work && work_bytes < need) return QRX_EINVAL;
+    memset(info, 0, sizeof(*info));
+    if (h->device < 0) return QRX_EHIP;
+    if (hipSetDevice(h->device) != hipSuccess) return QRX_EHIP;
+    if (!work) {
+        if ((rc = ensure_pool(h, need, &work))) return rc;
+    }
+    Carve cv(work);
+    QrWork ws;
+    carve_qr(cv, m, n, c, ops, ws);
+    float *W = nullptr, *R = const_cast<float *>(Rin);
+    int64_t ldw = round_up(m, 64), ldR = ldr;
+    if (with_qr) {
+        W = cv.take<float>((size_t)ldw * n);
+        ldR = round_up(n, 64);
+        R = cv.take<float>((size_t)ldR * n);
+    }
+    KrWork kw;
+    carve_kr(cv, m, n, kw);
+
+    hipEvent_t e0, e1, e2;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    hipEventCreate(&e2);
+    hipEventRecord(e0, stream);
+    QRX_TRY(hipMemsetAsync(ws.flags, 0, 4 * sizeof(int), stream));
+    {
+        Rec r(h, stream);
+        QRX_TRY(launch_scan(stream, m, n, A, lda, W, ldw, ws.colmax, ws.colss, ws.flags));
+        QRX_TRY(launch_scan_vec(stream, m, b, ws.flags));
+        QRX_TRY(launch_norm_finalize(stream, n, ws.colss, ws.normA));
+        r.end("scan", 0, (with_qr ? 8.0 : 4.0) * m * n);
+    }
+    if (with_qr) {
+        if ((rc = run_qr(h, stream, m, n, W, ldw, R, ldR, c, ops, ws))) return rc;
+        Rec r(h, stream);
+        QRX_TRY(launch_r_finalize(stream, n, R, ldR, ws.flags));
+        r.end("r_finalize", 0, 4.0 * n * n);
+    }
+    hipEventRecord(e1, stream);
+    double normA = 0.0;
+    QRX_TRY(hipMemcpyAsync(h->host_flags, ws.flags, sizeof(int), hipMemcpyDeviceToHost, stream));
+    QRX_TRY(hipMemcpyAsync(h->host_state, ws.normA, sizeof(double), hipMemcpyDeviceToHost, stream));
+    QRX_TRY(hipStreamSynchronize(stream));
+    normA = h->host_state[0];
+    info->normA_F = normA;
+    const int flags = h->host_flags[0];
+    if (flags & 1) {
+        info->status = QRX_ENONFINITE;
+    } else if (flags & 2) {
+        info->status = QRX_ESINGULAR;
+    } else {
+        // rho ~ ||R||_2 for the stopping trigger: 1 for the identity, else the largest
+        // column norm of A (a lower bound of ||A||_2 = ||R||_2)
+        double rho = 1.0;
+        if (R) {
+            std::vector<double> css(n);
+            QRX_TRY(hipMemcpy(css.data(), ws.colss, n * sizeof(double), hipMemcpyDeviceToHost));
+            double mx = 0.0;
+            for (double v : css) mx = std::max(mx, v);
+            rho = std::sqrt(mx);
+        }
+        rc = run_krylov(h, stream, m, n, A, lda, R, ldR, b, x, opts && opts->use_x0, kc, kw, info,
+                        normA, rho);
+        if (rc) return rc;
+    }
+    hipEventRecord(e2, stream);
+    hipEventSynchronize(e2);
+    float ms1 = 0.f, ms2 = 0.f;
+    hipEventElapsedTime(&ms1, e0, e1);
+    hipEventElapsedTime(&ms2, e1, e2);
+    info->qr_ms = with_qr ? ms1 : 0.0;
+    info->krylov_ms = ms2;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipEventDestroy(e2);
+    return QRX_OK;
+}
+
+int qrx_lls_solve(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
+                  const double *b, double *x, void *work, size_t work_bytes,
+                  const qrx_lls_opts *opts, qrx_lls_info *info, hipStream_t stream) {
+    return lls_common(h, m, n, A, lda, nullptr, n, true, b, x, work, work_bytes, opts, info,
+                      stream);
+}
+
+int qrx_lls_solve_with_R(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
+                         const float *R, int64_t ldr, const double *b, double *x, void *work,
+                         size_t work_bytes, const qrx_lls_opts *opts, qrx_lls_info *info,
+                         hipStream_t stream) {
+    if (R && ldr < n) return QRX_EINVAL;
+    return lls_common(h, m, n, A, lda, R, R ? ldr : n, false, b, x, work, work_bytes, opts, info,
+                      stream);
+}
+
+int qrx_timing_enable(qrx_handle h, int enable) {
+    if (!h) return QRX_EINVAL;
+    h->timing = enable != 0;
+    return QRX_OK;
+}
+
+static int drain_timing(qrx_handle h) {
+    for (auto &p : h->pending) {
+        if (hipEventSynchronize(p.b) != hipSuccess) return QRX_EHIP;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, p.a, p.b);
+        qrx_kernel_stat &s = h->stats[p.name];
+        if (s.launches == 0) {
+            memset(&s, 0, sizeof(s));
+            strncpy(s.name, p.name.c_str(), sizeof(s.name) - 1);
+        }
+        s.launches += 1;
+        s.total_ms += ms;
+        s.flops += p.flops;
+        s.bytes += p.bytes;
+        h->spare.push_back(p.a);
+        h->spare.push_back(p.b);
+    }
+    h->pending.clear();
+    return QRX_OK;
+}
+
+int qrx_timing_reset(qrx_handle h) {
+    if (!h) return QRX_EINVAL;
+    int rc = drain_timing(h);
+    h->stats.clear();
+    return rc;
+}
+
+int qrx_timing_get(qrx_handle h, qrx_kernel_stat *out, int capacity, int *count) {
+    if (!h || !count || (capacity > 0 && !out)) return QRX_EINVAL;
+    int rc = drain_timing(h);
+    if (rc) return rc;
+    int i = 0;
+    for (auto &kv : h->stats) {
+        if (i < capacity) out[i] = kv.second;
+        ++i;
+    }
+    *count = i;
+    return QRX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Internal declarations shared by the qrx HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <type_traits>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "qrx.h"
+
+#define QRX_DEV __device__ __forceinline__
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace qrx {
+
+// Exponent E with v = f 2^E, f in [0.5, 1); the power of two 2^(target - E)
+// brings max-abs v into [2^(target-1), 2^target). Zero / non-finite -> 1.
+QRX_DEV float pow2_scale(float v, int target) {
+    if (!(v > 0.0f) || !(v <= 3.0e38f)) return 1.0f;
+    int e;
+    frexpf(v, &e);
+    return ldexpf(1.0f, target - e);
+}
+
+QRX_DEV float wave_sum_f(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+QRX_DEV double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+QRX_DEV float wave_max_f(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Error-free transformations for double-double accumulation.
+QRX_DEV void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+QRX_DEV void dd_add(double &hi, double &lo, double v) {   // (hi, lo) += v
+    double s, e;
+    two_sum(hi, v, s, e);
+    e += lo;
+    hi = s + e;
+    lo = e - (hi - s);
+}
+QRX_DEV void dd_add_prod(double &hi, double &lo, double a, double b) {  // += a*b exactly-ish
+    double p = a * b;
+    double pe = fma(a, b, -p);
+    dd_add(hi, lo, p);
+    lo += pe;
+}
+
+// Balanced partition of `units` units into `nblk` blocks: block i starts at
+// unit floor(i*units/nblk); blocks differ in size by at most one unit.
+QRX_DEV __host__ inline int64_t part_start(int64_t i, int64_t units, int64_t nblk) {
+    return (i * units) / nblk;
+}
+// Index of the block that contains unit u.
+QRX_DEV __host__ inline int64_t part_owner(int64_t u, int64_t units, int64_t nblk) {
+    return ((u + 1) * nblk - 1) / units;
+}
+
+constexpr int kPanelThreads = 256;   // TSQR block rows = threads (one row each)
+constexpr int kMaxLevels = 12;
+constexpr int kTrsvBlock = 256;      // TRSV diagonal block size
+
+// TSQR level descriptors of one panel (passed by value to the Q-formation kernel).
+struct TsqrLevels {
+    int nlev;                          // number of tree levels above level 0 (0 = single block)
+    int64_t nblk[kMaxLevels + 1];      // blocks at level l (level 0 = panel row blocks)
+    float *stack[kMaxLevels + 1];      // stack[l] (l >= 1): (nblk[l-1]*nb) x nb, ld = nblk[l-1]*nb
+};
+
+// ---- kernel launchers (one per .hip file section) --------------------------
+// scan.hip
+hipError_t launch_scan(hipStream_t s, int64_t m, int64_t n, const float *A, int64_t lda,
+                       float *W, int64_t ldw, float *colmax, double *colss, int *flags);
+hipError_t launch_scan_vec(hipStream_t s, int64_t m, const double *b, int *flags);
+hipError_t launch_norm_finalize(hipStream_t s, int64_t n, const double *colss, double *normA);
+hipError_t launch_fill_f32(hipStream_t s, float *p, int64_t count, float v);
+hipError_t launch_r_finalize(hipStream_t s, int64_t n, float *R, int64_t ldr, int *flags);
+hipError_t launch_status_out(hipStream_t s, const int *flags, int *status);
+
+// panel.hip : one TSQR panel of width w <= nb (nb = 32), m rows, column-major ld.
+hipError_t launch_tsqr_level(hipStream_t s, float *P, int64_t ld, int64_t rows, int w,
+                             int64_t nblk, int unit, float *rnext, int64_t ld_rnext, int reorth,
+                             const float *colmax);
+hipError_t launch_tsqr_qform(hipStream_t s, float *P, int64_t ld, int64_t m, int w,
+                             const TsqrLevels &lv);
+hipError_t launch_copy_r_block(hipStream_t s, const float *src, int64_t ld_src, int w,
+                               float *R, int64_t ldr, const float *colmax);
+
+// gemm.hip : trailing products of one recursion node.
+//   projection: Part[s] (k x n2, ld k) = Q1^T A2 over row split s.
+//   reduce:     R12 = sum_s Part[s] (unscaled), written into R (ldr);
+//               also per-column update scales and colmax reset.
+//   update:     A2 -= Q1 R12, refreshes colmax of A2 columns.
+hipError_t launch_projection(hipStream_t s, int prec, int scaling, int64_t m, int64_t k,
+                             int64_t n2, const float *Q1, const float *A2, int64_t lda,
+                             const float *colmax_a2, float *part, int splits);
+hipError_t launch_proj_reduce(hipStream_t s, int prec, int scaling, int64_t k, int64_t n2,
+                              const float *part, int splits, float *R12, int64_t ldr,
+                              float *colmax_a2, float *uscale);
+hipError_t launch_update(hipStream_t s, int prec, int scaling, int64_t m, int64_t k,
+                         int64_t n2, const float *Q1, float *A2, int64_t lda,
+                         const float *R12, int64_t ldr, const float *uscale,
+                         float *colmax_a2);
+int projection_splits(int64_t m, int64_t k, int64_t n2);
+
+}  // namespace qrx

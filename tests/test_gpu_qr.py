@@ -1,0 +1,143 @@
+"""GPU parity of the QR factorisation (Alg. 2 + TSQR/MGS panels) against the
+FP64 Householder oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import householder as H
+from oracle import metrics as M
+from oracle import rmgs as G
+
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qrx():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1912_05508_amd as P
+    h = P.Handle()
+    yield h
+    h.close()
+
+
+def _run(qrx, A, prec="fp32", ld=None, **kw):
+    import torch
+    Ad = dev(A, ld)
+    Q, R, st = qrx.qr(Ad, prec=prec, **kw)
+    torch.cuda.synchronize()
+    return host(Q), host(R), int(st.item())
+
+
+@pytest.mark.parametrize("m,n,ld", [(64, 64, None), (100, 1, None), (257, 33, 260), (300, 33, 303),
+                                    (1000, 100, None), (1024, 256, None), (2500, 300, None),
+                                    (513, 96, 515)])
+def test_fp32_qr_parity(qrx, m, n, ld):
+    g = np.random.default_rng(m * 7 + n)
+    A = g.standard_normal((m, n)).astype(np.float32)
+    Q, R, st = _run(qrx, A, ld=ld)
+    assert st == 0
+    Qo, Ro = H.qr(A)
+    be = M.qr_backward_error(A, Q, R)
+    orth = M.orthogonality(Q)
+    rerr = M.r_relative_error(R, Ro)
+    kappa = np.linalg.cond(A.astype(np.float64))
+    print(f"m={m} n={n} be={be:.2e} orth={orth:.2e} rerr={rerr:.2e} kappa={kappa:.1f}")
+    assert M.upper_triangular_ok(R)
+    assert be < 2e-6
+    # block Gram-Schmidt between panels loses orthogonality in proportion to
+    # kappa (Sec. 3.2.1); MGS2 inside the panels keeps it at O(u) there
+    assert orth < max(1e-5, 20 * kappa * 6e-8)
+    assert rerr < 20 * kappa * 6e-8
+
+
+def test_fp32_qr_c1_full_size(qrx):
+    p = synth.config_problem("c1")
+    Q, R, st = _run(qrx, p.A, panel_width=32)
+    Qo, Ro = H.qr(p.A)
+    assert st == 0
+    assert M.qr_backward_error(p.A, Q, R) < 2e-6
+    assert M.orthogonality(Q) < 1e-5
+    assert M.r_relative_error(R, Ro) < 1e-5
+
+
+@pytest.mark.parametrize("prec,be_bound", [("fp16", 4e-3), ("bf16", 3e-2)])
+def test_lowprec_qr_scaled_c2(qrx, prec, be_bound):
+    # c2 recipe (geometric spectrum, cond 1e3) at 2048 x 384, cutoff 128
+    p = synth.scaled_config("c2", 2048, 384, seed=0)
+    Q, R, st = _run(qrx, p.A, prec=prec, cutoff=128)
+    assert st == 0
+    be = M.qr_backward_error(p.A, Q, R)
+    orth = M.orthogonality(Q)
+    Qe, Re = G.rmgs(p.A.astype(np.float64), cutoff=128, prec=prec)
+    orth_e = M.orthogonality(Qe)
+    print(f"{prec}: be={be:.2e} orth={orth:.2e} emulated orth={orth_e:.2e}")
+    assert M.upper_triangular_ok(R)
+    assert be < be_bound
+    assert orth < 4 * orth_e + 1e-5
+
+
+def test_fp16_scaling_matters_for_small_columns(qrx):
+    # A matrix whose trailing columns are tiny (1e-7 relative) keeps FP16 accuracy
+    # only with the power-of-two column scaling.
+    g = np.random.default_rng(5)
+    A = synth.svd_matrix(g, 1024, 256, synth.spectrum("geometric", 256, 1e6))
+    Q, R, st = _run(qrx, A, prec="fp16", cutoff=64)
+    assert st == 0
+    assert M.qr_backward_error(A, Q, R) < 4e-3
+
+
+def test_status_nonfinite_and_singular(qrx):
+    g = np.random.default_rng(6)
+    A = g.standard_normal((300, 40)).astype(np.float32)
+    A[7, 3] = np.nan
+    _, _, st = _run(qrx, A)
+    assert st == 2                       # QRX_ENONFINITE
+    A = g.standard_normal((300, 40)).astype(np.float32)
+    A[:, 17] = 0.0
+    _, _, st = _run(qrx, A)
+    assert st == 1                       # QRX_ESINGULAR
+
+
+def test_closed_forms(qrx):
+    # [T; 0] -> R = T, Q = [I; 0]; orthonormal columns -> R = I.
+    g = np.random.default_rng(7)
+    T = np.triu(g.standard_normal((40, 40))).astype(np.float32)
+    T[np.diag_indices(40)] = np.abs(T[np.diag_indices(40)]) + 1.0
+    A = np.vstack([T, np.zeros((600, 40), np.float32)])
+    Q, R, st = _run(qrx, A)
+    assert st == 0
+    assert np.max(np.abs(R - T)) < 1e-5 * np.max(np.abs(T))
+    assert np.max(np.abs(Q[:40] - np.eye(40))) < 1e-5 and np.max(np.abs(Q[40:])) < 1e-6
+    Qo, _ = np.linalg.qr(g.standard_normal((700, 50)))
+    Q, R, st = _run(qrx, Qo.astype(np.float32))
+    assert np.max(np.abs(R - np.eye(50))) < 1e-5
+
+
+def test_deterministic(qrx):
+    p = synth.scaled_config("c2", 2048, 256, seed=3)
+    a = _run(qrx, p.A, prec="fp16", cutoff=64)
+    b = _run(qrx, p.A, prec="fp16", cutoff=64)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.slow
+def test_c2_full_size_sampled(qrx):
+    """c2 at full size (32768 x 4096, FP16, cutoff 128) in the bench's launch
+    configuration; the oracle checks sampled columns of A - QR and of Q^T Q."""
+    import torch
+    p = synth.config_problem("c2", device="cuda")
+    A_host = host(p.A)
+    Q, R, st = qrx.qr(p.A.clone(memory_format=torch.preserve_format), prec="fp16", cutoff=128)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    Qh, Rh = host(Q), host(R)
+    cols = np.random.default_rng(0).choice(4096, 64, replace=False)
+    be = M.qr_backward_error(A_host, Qh, Rh, cols=cols)
+    orth = M.orthogonality(Qh, cols=np.sort(cols))
+    print(f"c2 sampled: be={be:.2e} orth(sub)={orth:.2e}")
+    assert M.upper_triangular_ok(Rh)
+    assert be < 4e-3
+    assert orth < 1e-2
