@@ -42,6 +42,8 @@ def qr_flops(m, n):
 
 
 def kernel_bound(name):
+    if name.startswith(("proj_fp16x3", "update_fp16x3")):
+        return "mfma", PEAKS["fp16"] / 3.0, "TFLOP/s"
     if name.startswith(("proj_fp16", "update_fp16")):
         return "mfma", PEAKS["fp16"], "TFLOP/s"
     if name.startswith(("proj_bf16", "update_bf16")):
@@ -50,6 +52,8 @@ def kernel_bound(name):
         return "mfma", PEAKS["fp32_mfma"], "TFLOP/s"
     if name.startswith("tsqr"):
         return "alu", PEAKS["fp32_valu_nopk"], "TFLOP/s"
+    if name.startswith("gram"):
+        return "alu", PEAKS["fp64"], "TFLOP/s"
     return "hbm", PEAKS["hbm_gbs"], "GB/s"
 
 
@@ -69,7 +73,7 @@ def roofline_of(stats):
 def time_qr(h, A, Q, R, st, prec, steps, warmup, cutoff, timing=False):
     import torch
     for _ in range(warmup):
-        h.qr_out(A, Q, R, st, prec=prec, cutoff=cutoff, panel_width=32)
+        h.qr_out(A, Q, R, st, prec=prec, cutoff=cutoff)
     torch.cuda.synchronize()
     if timing:
         h.timing_reset()
@@ -77,7 +81,7 @@ def time_qr(h, A, Q, R, st, prec, steps, warmup, cutoff, timing=False):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        h.qr_out(A, Q, R, st, prec=prec, cutoff=cutoff, panel_width=32)
+        h.qr_out(A, Q, R, st, prec=prec, cutoff=cutoff)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     stats = None
@@ -138,12 +142,13 @@ def lls_bench(h, prec, m_n, repeats):
         name, device="cuda", m=m_n[0], n=m_n[1])
     A, b = p.A, torch.as_tensor(p.b, device="cuda") if not torch.is_tensor(p.b) else p.b
     out = {}
-    for pr in ("fp16", "fp32"):
+    for pr, reps in (("fp16x3", repeats), ("fp32", repeats), ("fp16", 1)):
         times, infos = [], []
-        for r in range(repeats):
+        for r in range(reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            x, info = h.lstsq(A, b, prec=pr, tol=1e-10, max_iter=20000, cutoff=128)
+            x, info = h.lstsq(A, b, prec=pr, tol=1e-10, max_iter=20000, cutoff=128,
+                              node_reorth=True)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             infos.append(info)
@@ -216,7 +221,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"c2: QR of {m} x {n} A = U diag(s) V^T, s geometric 1..1e-3 "
                                f"(seed 0); {args.prec.upper()} MFMA trailing products with FP32 "
-                               f"accumulation, cutoff {args.cutoff}, 32-column MGS2 TSQR panels",
+                               f"accumulation, cutoff {args.cutoff}, 64-column panels (Cholesky QR "
+                               f"twice on an FP64 Gram matrix)",
                    "m": m, "n": n, "flops_per_step": flops, "parallelism": "single GPU"},
         "roofline": roof,
         "accuracy": acc,

@@ -54,18 +54,29 @@ extern "C" {
 typedef struct qrx_handle_s *qrx_handle;
 
 /* Operand precision of the trailing products R12 = Q1^T A2 and
- * A2 -= Q1 R12 (Alg. 2); accumulation is FP32 in every mode. */
-typedef enum { QRX_FP32 = 0, QRX_FP16 = 1, QRX_BF16 = 2 } qrx_prec;
+ * A2 -= Q1 R12 (Alg. 2); accumulation is FP32 in every mode. QRX_FP16X3
+ * splits each FP32 operand into FP16 hi + 2^-11 lo parts and forms
+ * hi*hi + 2^-11 (hi*lo + lo*hi) on the FP16 matrix cores (three products per
+ * step, ~22-bit operands): near-FP32 accuracy at FP16 matrix-core rates. */
+typedef enum { QRX_FP32 = 0, QRX_FP16 = 1, QRX_BF16 = 2, QRX_FP16X3 = 3 } qrx_prec;
 
 /* QR options; an all-zero struct selects the defaults. */
 typedef struct {
     int gemm_prec;        /* qrx_prec for recursion nodes wider than `cutoff` */
-    int panel_width;      /* nb: TSQR panel width, 1..32 (0 = 32; Sec. 3.1.3 uses 32) */
+    int panel_width;      /* nb: leaf panel width; 1..64 for the Gram panel (0 = 64),
+                             1..32 for the TSQR panel (0 = 32; Sec. 3.1.3 uses 32) */
     int cutoff;           /* c: nodes of width <= c use FP32 products (0 = 128, the
                              cutoff of Alg. 2); rounded up to a multiple of nb */
     int block_rows;       /* b: TSQR block rows, only 256 is supported (0 = 256; Sec. 3.1.3) */
     int no_col_scaling;   /* 1 = do not scale FP16/BF16 operand columns by powers of two */
-    int panel_single_pass;/* 1 = one MGS sweep per TSQR block instead of two */
+    int panel_single_pass;/* 1 = one orthogonalisation sweep per panel instead of two */
+    int panel_alg;        /* leaf panel: 0 = Cholesky QR twice on an FP64 Gram matrix
+                             (default), 1 = TSQR with modified Gram-Schmidt blocks run
+                             twice (eq. caqr with Alg. 4) */
+    int node_reorth;      /* re-orthogonalise at every recursion node (project and update
+                             twice, R12 accumulated; Sec. 4.1.2 remedy applied per node):
+                             0 = default (off for qrx_qr_factor*, on for qrx_lls_solve),
+                             1 = on, 2 = off */
 } qrx_qr_opts;
 
 /* Least-squares options; an all-zero struct selects the defaults. */

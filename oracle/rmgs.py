@@ -14,11 +14,13 @@ This follows the paper's algorithm step by step, in numpy:
 
 ``prec`` rounds the operands of the two trailing products the way a
 low-precision matrix unit would see them: "fp16" or "bf16" round-to-nearest-
-even of the FP32 operand after an exact power-of-two column scaling (max-abs
+even of the FP32 operand ("fp16x3": its FP16 hi part plus the FP16-rounded
+remainder scaled by 2^-11) after an exact power-of-two column scaling (max-abs
 of each A2 column brought to [2^13, 2^14), Q1 multiplied by 2^14, and each
-R12 column brought to [2^13, 2^14) before the update); products are summed in
-float64 and the results rounded to the working precision. ``prec=None`` is
-plain float64 arithmetic. This module calibrates error bounds for the
+R12 column brought to [2^13, 2^14) before the update); the products of the
+rounded operands are summed in float32 (a float32 matrix product), as a
+matrix unit with FP32 accumulation does, and the results rounded to the
+working precision. ``prec=None`` is plain float64 arithmetic. This module calibrates error bounds for the
 low-precision modes; it is not the definition of the factorisation (that is
 ``householder``). Parity of its FP16/BF16 rounding model is unpinned.
 """
@@ -40,6 +42,11 @@ def round_operand(x, prec):
     x32 = np.asarray(x, dtype=np.float32)
     if prec == "fp16":
         return x32.astype(np.float16).astype(np.float64)
+    if prec == "fp16x3":
+        # hi = fl16(x), lo = fl16((x - hi) 2^11); the operand seen is hi + 2^-11 lo
+        hi = x32.astype(np.float16).astype(np.float32)
+        lo = ((x32 - hi) * np.float32(2048.0)).astype(np.float16).astype(np.float64)
+        return hi.astype(np.float64) + lo / 2048.0
     if prec == "bf16":
         return to_bf16(x32).astype(np.float64)
     return np.asarray(x, dtype=np.float64)
@@ -75,15 +82,21 @@ def mgs2(A):
     return Q, R2 @ R1
 
 
+def _mm32(X, Y):
+    """Product of rounded operands with float32 summation (each operand is
+    exactly representable in float32, so only the sums round)."""
+    return (X.astype(np.float32) @ Y.astype(np.float32)).astype(np.float64)
+
+
 def _project(Q1, A2, prec, scale, work):
     if prec is None:
         return (Q1.T @ A2).astype(work)
     if scale:
         e = pow2_scale(np.max(np.abs(A2), axis=0))
         fq = 2.0 ** 14
-        acc = round_operand(Q1 * fq, prec).T @ round_operand(A2 * e, prec)
+        acc = _mm32(round_operand(Q1 * fq, prec).T, round_operand(A2 * e, prec))
         return (acc / (fq * e)).astype(np.float32).astype(work)
-    return (round_operand(Q1, prec).T @ round_operand(A2, prec)).astype(np.float32).astype(work)
+    return _mm32(round_operand(Q1, prec).T, round_operand(A2, prec)).astype(np.float32).astype(work)
 
 
 def _update(Q1, R12, A2, prec, scale, work):
@@ -92,10 +105,9 @@ def _update(Q1, R12, A2, prec, scale, work):
     if scale:
         fq = 2.0 ** 14
         h = pow2_scale(np.max(np.abs(R12), axis=0))
-        acc = round_operand(Q1 * fq, prec) @ round_operand(R12 * h, prec)
-        acc = acc.astype(np.float32).astype(np.float64)
+        acc = _mm32(round_operand(Q1 * fq, prec), round_operand(R12 * h, prec))
         return (A2 - acc / (fq * h)).astype(np.float32).astype(work)
-    acc = (round_operand(Q1, prec) @ round_operand(R12, prec)).astype(np.float32)
+    acc = _mm32(round_operand(Q1, prec), round_operand(R12, prec))
     return (A2 - acc).astype(np.float32).astype(work)
 
 

@@ -14,14 +14,15 @@ LIB_PATH = os.path.join(_HERE, "libqrx.so")
 
 QRX_OK, QRX_EINVAL, QRX_ENOMEM, QRX_EHIP = 0, -1, -2, -3
 QRX_ESINGULAR, QRX_ENONFINITE, QRX_ENOCONV = 1, 2, 3
-QRX_FP32, QRX_FP16, QRX_BF16 = 0, 1, 2
-PREC = {"fp32": QRX_FP32, "fp16": QRX_FP16, "bf16": QRX_BF16}
+QRX_FP32, QRX_FP16, QRX_BF16, QRX_FP16X3 = 0, 1, 2, 3
+PREC = {"fp32": QRX_FP32, "fp16": QRX_FP16, "bf16": QRX_BF16, "fp16x3": QRX_FP16X3}
 
 
 class qrx_qr_opts(C.Structure):
     _fields_ = [("gemm_prec", C.c_int), ("panel_width", C.c_int), ("cutoff", C.c_int),
                 ("block_rows", C.c_int), ("no_col_scaling", C.c_int),
-                ("panel_single_pass", C.c_int)]
+                ("panel_single_pass", C.c_int), ("panel_alg", C.c_int),
+                ("node_reorth", C.c_int)]
 
 
 class qrx_lls_opts(C.Structure):
@@ -106,8 +107,14 @@ def check(code, where="qrx"):
     return code
 
 
-def qr_opts(prec="fp32", panel_width=0, cutoff=0, col_scaling=True, reorth=True):
+PANEL = {"gram": 0, "tsqr": 1, "mgs": 1}
+
+
+def qr_opts(prec="fp32", panel_width=0, cutoff=0, col_scaling=True, reorth=True, panel="gram",
+            node_reorth=None):
     o = qrx_qr_opts()
+    o.node_reorth = 0 if node_reorth is None else (1 if node_reorth else 2)
+    o.panel_alg = PANEL[panel] if isinstance(panel, str) else int(panel)
     o.gemm_prec = PREC[prec] if isinstance(prec, str) else int(prec)
     o.panel_width = panel_width
     o.cutoff = cutoff

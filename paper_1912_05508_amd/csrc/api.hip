@@ -89,24 +89,29 @@ struct Carve {
 int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
 
 struct QrCfg {
-    int prec, nb, c, reorth, scaling;
+    int prec, nb, c, reorth, scaling, alg, node_reorth;
 };
 
-int resolve_qr(const qrx_qr_opts *o, QrCfg &c) {
+int resolve_qr(const qrx_qr_opts *o, QrCfg &c, bool lls = false) {
     qrx_qr_opts z;
     memset(&z, 0, sizeof(z));
     if (!o) o = &z;
-    if (o->gemm_prec < 0 || o->gemm_prec > 2) return QRX_EINVAL;
-    if (o->panel_width < 0 || o->panel_width > 32) return QRX_EINVAL;
+    if (o->gemm_prec < 0 || o->gemm_prec > 3) return QRX_EINVAL;
+    if (o->panel_alg < 0 || o->panel_alg > 1) return QRX_EINVAL;
+    const int max_nb = o->panel_alg == 1 ? 32 : 64;
+    if (o->panel_width < 0 || o->panel_width > max_nb) return QRX_EINVAL;
     if (o->cutoff < 0) return QRX_EINVAL;
     if (o->block_rows != 0 && o->block_rows != kPanelThreads) return QRX_EINVAL;
     if (o->no_col_scaling < 0 || o->no_col_scaling > 1) return QRX_EINVAL;
     if (o->panel_single_pass < 0 || o->panel_single_pass > 1) return QRX_EINVAL;
     c.prec = o->gemm_prec;
-    c.nb = o->panel_width ? o->panel_width : 32;
+    c.alg = o->panel_alg;
+    c.nb = o->panel_width ? o->panel_width : (c.alg == 1 ? 32 : 64);
     int cut = o->cutoff ? o->cutoff : 128;
     if (cut < c.nb) cut = c.nb;
     c.c = (int)round_up(cut, c.nb);
+    if (o->node_reorth < 0 || o->node_reorth > 2) return QRX_EINVAL;
+    c.node_reorth = o->node_reorth == 1 ? 1 : (o->node_reorth == 2 ? 0 : (lls ? 1 : 0));
     c.reorth = o->panel_single_pass ? 0 : 1;
     c.scaling = o->no_col_scaling ? 0 : 1;
     return QRX_OK;
@@ -146,8 +151,8 @@ void tsqr_sizes(int64_t m, int nb, std::vector<int64_t> &nblk) {
 
 struct QrWork {
     int *flags;
-    float *colmax, *uscale, *part, *rtop, *stack_base;
-    double *colss, *normA;
+    float *colmax, *uscale, *part, *rtop, *stack_base, *rcorr, *cmpart;
+    double *colss, *normA, *gram;
     size_t stack_floats;
 };
 
@@ -165,17 +170,31 @@ void carve_qr(Carve &cv, int64_t m, int64_t n, const QrCfg &c, const std::vector
             part = std::max(part, s * (size_t)o.k * (size_t)o.n2);
         }
     w.part = cv.take<float>(part);
+    size_t rc = 1;
+    if (c.node_reorth)
+        for (const Op &o : ops)
+            if (o.kind == 1) rc = std::max(rc, (size_t)o.k * (size_t)o.n2);
+    w.rcorr = cv.take<float>(rc);
+    w.cmpart = cv.take<float>((size_t)update_cmpart_slots(m) * (size_t)n);
     w.rtop = cv.take<float>(32 * 32);
     std::vector<int64_t> nblk;
     tsqr_sizes(m, 32, nblk);
     size_t st = 0;
     for (size_t l = 1; l < nblk.size(); ++l) st += (size_t)nblk[l - 1] * 32 * 32 + 64;
     w.stack_floats = st;
-    w.stack_base = cv.take<float>(st + 1);
+    w.stack_base = cv.take<float>(c.alg == 1 ? st + 1 : 1);
+    w.gram = cv.take<double>(c.alg == 0 ? gram_workspace_doubles(m, 64) : 1);
 }
 
 int run_panel(qrx_handle h, hipStream_t s, int64_t m, float *P, int64_t ld, int w, float *R,
               int64_t ldr, const float *colmax, const QrCfg &c, QrWork &ws) {
+    if (c.alg == 0) {
+        Rec r(h, s);
+        QRX_TRY(launch_gram_panel(s, P, ld, m, w, R, ldr, ws.gram, c.reorth));
+        // two sweeps of: Gram (m w^2 FMA), Q formation (m w^2 FMA), FP64
+        r.end("gram_panel", 2.0 * 2.0 * 2.0 * m * (double)w * w, 2.0 * 3.0 * 4.0 * m * w);
+        return QRX_OK;
+    }
     constexpr int NB = 32;
     std::vector<int64_t> nblk;
     tsqr_sizes(m, NB, nblk);
@@ -234,9 +253,14 @@ int run_qr(qrx_handle h, hipStream_t s, int64_t m, int64_t n, float *W, int64_t 
             float *R12 = R + o.c0 + (o.c0 + o.k) * ldr;
             float *cm = ws.colmax + o.c0 + o.k;
             const int splits = projection_splits(m, o.k, o.n2);
+            // column max-abs of the updated A2 is read later only by scaled low-precision
+            // projections inside A2 (width > cutoff) and by the TSQR panel's scaling
+            float *cm_out = (c.alg == 1 || (o.n2 > c.c && o.prec != QRX_FP32 && c.scaling)) ? cm
+                                                                                          : nullptr;
             const double fl = 2.0 * m * o.k * o.n2;
-            const char *pn = o.prec == QRX_FP16 ? "proj_fp16" : (o.prec == QRX_BF16 ? "proj_bf16" : "proj_fp32");
-            const char *un = o.prec == QRX_FP16 ? "update_fp16" : (o.prec == QRX_BF16 ? "update_bf16" : "update_fp32");
+            static const char *pnames[4] = {"proj_fp32", "proj_fp16", "proj_bf16", "proj_fp16x3"};
+            static const char *unames[4] = {"update_fp32", "update_fp16", "update_bf16", "update_fp16x3"};
+            const char *pn = pnames[o.prec], *un = unames[o.prec];
             {
                 Rec r(h, s);
                 QRX_TRY(launch_projection(s, o.prec, c.scaling, m, o.k, o.n2, Q1, A2, ldw, cm,
@@ -246,14 +270,38 @@ int run_qr(qrx_handle h, hipStream_t s, int64_t m, int64_t n, float *W, int64_t 
             {
                 Rec r(h, s);
                 QRX_TRY(launch_proj_reduce(s, o.prec, c.scaling, o.k, o.n2, ws.part, splits, R12,
-                                           ldr, cm, ws.uscale));
+                                           ldr, cm, ws.uscale, nullptr, 0));
                 r.end("proj_reduce", (double)splits * o.k * o.n2, 4.0 * (splits + 1) * o.k * o.n2);
             }
             {
                 Rec r(h, s);
                 QRX_TRY(launch_update(s, o.prec, c.scaling, m, o.k, o.n2, Q1, A2, ldw, R12, ldr,
-                                      ws.uscale, cm));
+                                      ws.uscale, (c.node_reorth && o.prec != QRX_FP32) ? cm : cm_out,
+                                      ws.cmpart));
                 r.end(un, fl, 4.0 * m * o.k + 8.0 * m * o.n2);
+            }
+            if (c.node_reorth) {
+                // second projection of the updated A2 against Q1: C = Q1^T A2,
+                // A2 -= Q1 C, R12 += C ("twice is enough")
+                {
+                    Rec r(h, s);
+                    QRX_TRY(launch_projection(s, o.prec, c.scaling, m, o.k, o.n2, Q1, A2, ldw, cm,
+                                              ws.part, splits));
+                    r.end(pn, fl, 4.0 * m * (o.k + o.n2) + 4.0 * splits * o.k * o.n2);
+                }
+                {
+                    Rec r(h, s);
+                    QRX_TRY(launch_proj_reduce(s, o.prec, c.scaling, o.k, o.n2, ws.part, splits,
+                                               ws.rcorr, o.k, cm, ws.uscale, R12, ldr));
+                    r.end("proj_reduce", (double)splits * o.k * o.n2,
+                          4.0 * (splits + 3) * o.k * o.n2);
+                }
+                {
+                    Rec r(h, s);
+                    QRX_TRY(launch_update(s, o.prec, c.scaling, m, o.k, o.n2, Q1, A2, ldw,
+                                          ws.rcorr, o.k, ws.uscale, cm_out, ws.cmpart));
+                    r.end(un, fl, 4.0 * m * o.k + 8.0 * m * o.n2);
+                }
             }
         }
     }
@@ -284,7 +332,7 @@ int ensure_pool(qrx_handle h, size_t bytes, void **out) {
 
 // ---- Krylov workspace --------------------------------------------------------
 struct KrWork {
-    double *Dinv, *u, *r, *v, *t, *d, *z, *y, *vt, *x, *xbest, *q;
+    double *Dinv, *u, *r, *rc, *v, *t, *d, *z, *y, *vt, *vt2, *x, *xbest, *q;
     double *part_n, *part_n2, *part_t, *ssq, *st;
     int splits_n, splits_t;
 };
@@ -296,6 +344,7 @@ void carve_kr(Carve &cv, int64_t m, int64_t n, KrWork &k) {
     k.Dinv = cv.take<double>((size_t)np * 64);
     k.u = cv.take<double>(m);
     k.r = cv.take<double>(m);
+    k.rc = cv.take<double>(m);
     k.q = cv.take<double>(m);
     k.v = cv.take<double>(np);
     k.t = cv.take<double>(np);
@@ -303,6 +352,7 @@ void carve_kr(Carve &cv, int64_t m, int64_t n, KrWork &k) {
     k.z = cv.take<double>(np);
     k.y = cv.take<double>(np);
     k.vt = cv.take<double>(np);
+    k.vt2 = cv.take<double>(np);
     k.x = cv.take<double>(np);
     k.xbest = cv.take<double>(np);
     k.part_n = cv.take<double>((size_t)k.splits_n * m);
@@ -346,11 +396,13 @@ int certify(qrx_handle h, hipStream_t s, int64_t m, int64_t n, int64_t np, const
             int64_t lda, const double *b, KrWork &k, double tol) {
     Rec r(h, s);
     QRX_TRY(kr_gemv_n(s, m, n, A, lda, k.x, k.part_n, k.part_n2, k.splits_n, 1));
-    QRX_TRY(kr_resid_combine(s, m, b, k.part_n, k.part_n2, k.splits_n, k.r, k.ssq));
+    QRX_TRY(kr_resid_combine(s, m, b, k.part_n, k.part_n2, k.splits_n, k.rc, k.ssq));
     QRX_TRY(kr_norm(s, k.ssq, nblocks(m), k.st, S_RNORM, 1));
-    QRX_TRY(kr_gemv_t(s, m, n, A, lda, k.r, k.part_t));
+    QRX_TRY(kr_gemv_t(s, m, n, A, lda, k.rc, k.part_t));
     QRX_TRY(kr_combine_n(s, n, k.part_t, k.splits_t, k.z, k.ssq));
     QRX_TRY(kr_norm(s, k.ssq, nblocks(n), k.st, S_ZNORM, 1));
+    QRX_TRY(kr_axpby(s, np, k.st, -2, -1, k.x, -1, 1.0, nullptr, k.vt2, k.ssq));
+    QRX_TRY(kr_norm(s, k.ssq, nblocks(np), k.st, S_XNORM, 1));
     QRX_TRY(kr_eta(s, k.st, tol));
     r.end("certify", 2.0 * 2.0 * m * n, 8.0 * m * n + 24.0 * m);
     return QRX_OK;
@@ -382,6 +434,12 @@ int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A
     for (int i = 0; i < S_COUNT; ++i) QRX_TRY(kr_set(s, st, i, 0.0));
     QRX_TRY(kr_set(s, st, S_NORMA, normA_host));
     QRX_TRY(kr_set(s, st, S_GAMMA_TOL, 1.0));
+    {   // ||b|| for the compatible-system test
+        Rec r(h, s);
+        QRX_TRY(kr_axpby(s, m, st, -2, -1, b, -1, 1.0, nullptr, k.q, k.ssq));
+        QRX_TRY(kr_norm(s, k.ssq, nblocks(m), st, S_BNORM, 1));
+        r.end("bnorm", 0, 16.0 * m);
+    }
     const double trig_scale = (normA_host > 0.0) ? rho / normA_host : 1.0;
 
     int rc;
@@ -403,19 +461,29 @@ int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A
         r.end("gemv_t", 2.0 * m * n, 4.0 * m * n + 8.0 * m);
         return QRX_OK;
     };
-    auto certify_now = [&](double &eta) -> int {
+    // certification: score = min(eta_F, compatible-system ratio) of the current x
+    auto certify_now = [&](double &score) -> int {
         int e = certify(h, s, m, n, np, A, lda, b, k, tol);
         if (e) return e;
         e = sync_state(h, s, st);
         if (e) return e;
-        eta = (hs[S_RNORM] > 0.0) ? hs[S_ETA] : 0.0;
+        score = hs[S_SCORE];
         return QRX_OK;
     };
 
-    double eta = 0.0;
-    if ((rc = certify_now(eta))) return rc;
-    double best = eta, best_rn = hs[S_RNORM];
+    double score = 0.0;
+    if ((rc = certify_now(score))) return rc;
+    double best = score, best_eta = hs[S_ETA], best_rn = hs[S_RNORM];
     QRX_TRY(kr_copy(s, np, k.x, k.xbest));
+    auto keep_if_better = [&](double sc) -> int {
+        if (sc < best) {
+            best = sc;
+            best_eta = hs[S_ETA];
+            best_rn = hs[S_RNORM];
+            QRX_TRY(kr_copy(s, np, k.x, k.xbest));
+        }
+        return QRX_OK;
+    };
     int iters = 0, outers = 0, no_gain = 0;
     double prev = best, gam = 1.0;
     while (best > tol && iters < cfg.max_iter) {
@@ -423,7 +491,7 @@ int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A
         // ---- restart on the certified residual r (k.r) and z = A^T r (k.z)
         if (cfg.method == 0) {
             // u = r (beta = ||r||); v = R^{-T} z / beta, alpha = ||v||, v /= alpha
-            QRX_TRY(kr_copy(s, m, k.r, k.u));
+            QRX_TRY(kr_copy(s, m, k.rc, k.u));
             QRX_TRY(kr_lsqr_restart(s, st, 0));
             if ((rc = trsv(k.z, k.vt, 1))) return rc;
             QRX_TRY(kr_axpby(s, np, st, -2, S_BETA, k.vt, -1, 1.0, nullptr, k.v, k.ssq));
@@ -431,15 +499,16 @@ int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A
             QRX_TRY(kr_axpby(s, np, st, -2, S_ALPHA, k.v, -1, 1.0, nullptr, k.v, nullptr));
             QRX_TRY(kr_lsqr_restart(s, st, 1));
         } else {
-            // s = R^{-T} z, p = s (in v), gamma = ||s||^2; r (k.r) is the recurrence residual
+            // r = certified residual; s = R^{-T} z, p = s (in v), gamma = ||s||^2
+            QRX_TRY(kr_copy(s, m, k.rc, k.r));
             if ((rc = trsv(k.z, k.vt, 1))) return rc;
             QRX_TRY(kr_axpby(s, np, st, -2, -1, k.vt, -1, 1.0, nullptr, k.v, k.ssq));
             QRX_TRY(kr_norm(s, k.ssq, nblocks(np), st, S_GAMMA, 0));
         }
         bool first = true;
         double best_est = HUGE_VAL;
-        int kin = 0, last_new = 0;
-        while (iters < cfg.max_iter) {
+        int kin = 0, last_new = 0, next_check = 10;
+        while (iters < cfg.max_iter && best > tol) {
             ++iters;
             ++kin;
             if (cfg.method == 0) {
@@ -511,16 +580,23 @@ int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A
             const bool cg_stall = cfg.method == 1 &&
                                   ((kin - last_new) > std::max(100, kin / 2) || est > 100.0 * best_est);
             if (!finite || est * trig_scale <= tol * gam || cg_stall) break;
+            // periodic check of the true residual without restarting: the
+            // preconditioned estimate can stay far above tol once eta_F has
+            // reached its floor (R^{-T} amplifies rounding-level residuals)
+            if (kin >= next_check) {
+                next_check = kin + std::max(10, iters / 8);
+                if ((rc = certify_now(score))) return rc;
+                if ((rc = keep_if_better(score))) return rc;
+            }
         }
+        if (best <= tol) break;
         // ---- certify; keep the best iterate
-        if ((rc = certify_now(eta))) return rc;
-        if (eta < best) {
-            best = eta;
-            best_rn = hs[S_RNORM];
-            QRX_TRY(kr_copy(s, np, k.x, k.xbest));
+        if ((rc = certify_now(score))) return rc;
+        if (score < best) {
+            if ((rc = keep_if_better(score))) return rc;
         } else {
             QRX_TRY(kr_copy(s, np, k.xbest, k.x));
-            if ((rc = certify_now(eta))) return rc;
+            if ((rc = certify_now(score))) return rc;
         }
         no_gain = (best > 0.5 * prev) ? no_gain + 1 : 0;
         prev = best;
@@ -531,7 +607,7 @@ int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A
     QRX_TRY(hipStreamSynchronize(s));
     info->iters = iters;
     info->restarts = outers > 0 ? outers - 1 : 0;
-    info->eta_F = best;
+    info->eta_F = best_eta;
     info->resid_norm = best_rn;
     info->status = (best <= tol) ? QRX_OK : QRX_ENOCONV;
     return QRX_OK;
@@ -697,7 +773,7 @@ int qrx_lls_workspace_size(qrx_handle h, int64_t m, int64_t n, const qrx_lls_opt
     if (rc) return rc;
     QrCfg c;
     KrCfg kc;
-    if ((rc = resolve_qr(opts ? &opts->qr : nullptr, c))) return rc;
+    if ((rc = resolve_qr(opts ? &opts->qr : nullptr, c, true))) return rc;
     if ((rc = resolve_lls(opts, kc))) return rc;
     std::vector<Op> ops;
     plan_rec(0, n, c, ops);
@@ -713,7 +789,7 @@ static int lls_common(qrx_handle h, int64_t m, int64_t n, const float *A, int64_
     if (bad_ptr(A) || bad_ptr(b) || bad_ptr(x) || !info) return QRX_EINVAL;
     QrCfg c;
     KrCfg kc;
-    if ((rc = resolve_qr(opts ? &opts->qr : nullptr, c))) return rc;
+    if ((rc = resolve_qr(opts ? &opts->qr : nullptr, c, true))) return rc;
     if ((rc = resolve_lls(opts, kc))) return rc;
     std::vector<Op> ops;
     plan_rec(0, n, c, ops);

@@ -15,8 +15,9 @@
 // The projection splits K = m over grid.y (split-K) and writes FP32 partial
 // products; a second kernel sums them in a fixed order (deterministic), writes
 // R12 into R, derives the update scales and clears the column max-abs of A2.
-// The update's epilogue subtracts in FP32 and refreshes that max-abs with an
-// atomic max (order-independent, so deterministic).
+// The update's epilogue subtracts in FP32 and, when a later step needs them,
+// writes per-tile partial column max-abs values that a small kernel reduces
+// (no atomics; deterministic).
 #include "qrx_internal.hpp"
 
 namespace qrx {
@@ -28,19 +29,33 @@ struct PF32 {
     static constexpr int KS = 4;    // K per MFMA
     static constexpr int BK = 32;   // K per LDS stage
     static constexpr int PAD = 4;
+    static constexpr bool SPLIT = false;
 };
 struct PF16 {
     using E = _Float16;
     static constexpr int KS = 32;
     static constexpr int BK = 64;
     static constexpr int PAD = 8;
+    static constexpr bool SPLIT = false;
 };
 struct PBF16 {
     using E = __bf16;
     static constexpr int KS = 32;
     static constexpr int BK = 64;
     static constexpr int PAD = 8;
+    static constexpr bool SPLIT = false;
 };
+// Split FP16: x = hi + 2^-11 lo with hi = fl16(x), lo = fl16((x - hi) 2^11);
+// x y ~ hi_x hi_y + 2^-11 (hi_x lo_y + lo_x hi_y), three FP16 MFMAs per step.
+struct PF16X3 {
+    using E = _Float16;
+    static constexpr int KS = 32;
+    static constexpr int BK = 64;
+    static constexpr int PAD = 8;
+    static constexpr bool SPLIT = true;
+};
+constexpr float kSplitLo = 2048.0f;          // 2^11
+constexpr float kSplitLoInv = 1.0f / 2048.0f;
 
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -55,6 +70,16 @@ QRX_DEV void st4(_Float16 *d, float a, float b, float c, float e) {
 QRX_DEV void st4(__bf16 *d, float a, float b, float c, float e) {
     bf16x4 v = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)e};
     *reinterpret_cast<bf16x4 *>(d) = v;
+}
+
+// hi / lo parts of four values
+QRX_DEV void st4_split(_Float16 *dh, _Float16 *dl, float a, float b, float c, float e) {
+    const _Float16 ha = (_Float16)a, hb = (_Float16)b, hc = (_Float16)c, he = (_Float16)e;
+    f16x4 vh = {ha, hb, hc, he};
+    f16x4 vl = {(_Float16)((a - (float)ha) * kSplitLo), (_Float16)((b - (float)hb) * kSplitLo),
+                (_Float16)((c - (float)hc) * kSplitLo), (_Float16)((e - (float)he) * kSplitLo)};
+    *reinterpret_cast<f16x4 *>(dh) = vh;
+    *reinterpret_cast<f16x4 *>(dl) = vl;
 }
 
 // One K-stage of MFMA work for a wave: FM x FN fragments of 16x16.
@@ -100,6 +125,38 @@ QRX_DEV void mma_stage(const typename Tr::E *As, const typename Tr::E *Bs, int a
     }
 }
 
+// Split-FP16 K-stage: acc += hi*hi, acc2 += hi*lo + lo*hi.
+template <int FM, int FN, int BK, int LS>
+QRX_DEV void mma_stage_split(const _Float16 *Ah, const _Float16 *Al, const _Float16 *Bh,
+                             const _Float16 *Bl, int arow0, int bcol0, f32x4 (&acc)[FM][FN],
+                             f32x4 (&acc2)[FM][FN], int lane) {
+    const int rl = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 32) {
+        f16x8 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+        for (int f = 0; f < FM; ++f) {
+            const int o = (arow0 + f * 16 + rl) * LS + kk + kq * 8;
+            ah[f] = *reinterpret_cast<const f16x8 *>(Ah + o);
+            al[f] = *reinterpret_cast<const f16x8 *>(Al + o);
+        }
+#pragma unroll
+        for (int f = 0; f < FN; ++f) {
+            const int o = (bcol0 + f * 16 + rl) * LS + kk + kq * 8;
+            bh[f] = *reinterpret_cast<const f16x8 *>(Bh + o);
+            bl[f] = *reinterpret_cast<const f16x8 *>(Bl + o);
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc2[i][j], 0, 0, 0);
+                acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc2[i][j], 0, 0, 0);
+            }
+    }
+}
+
 // Load a K-contiguous operand tile: C columns x BK rows of X (X[k + c*ld]),
 // k in [k0, kend), c in [c0, cend); zero outside. Each thread owns NR float4s.
 template <int BK, int C>
@@ -139,6 +196,17 @@ struct KLoader {
             const int cl = cc + p * COLS_PER_PASS;
             const float s = scale(c0 + cl);
             st4(S + cl * LS + 4 * q, v[p].x * s, v[p].y * s, v[p].z * s, v[p].w * s);
+        }
+    }
+    template <int LS, class F>
+    QRX_DEV void store_split(_Float16 *Sh, _Float16 *Sl, int64_t c0, int t, F scale) const {
+        const int q = t % CPC, cc = t / CPC;
+#pragma unroll
+        for (int p = 0; p < NR; ++p) {
+            const int cl = cc + p * COLS_PER_PASS;
+            const float s = scale(c0 + cl);
+            st4_split(Sh + cl * LS + 4 * q, Sl + cl * LS + 4 * q, v[p].x * s, v[p].y * s,
+                      v[p].z * s, v[p].w * s);
         }
     }
 };
@@ -190,6 +258,19 @@ struct MLoader {
             st4(d + 3 * LS, v[p][0].w * s, v[p][1].w * s, v[p][2].w * s, v[p][3].w * s);
         }
     }
+    template <int LS>
+    QRX_DEV void store_split(_Float16 *Sh, _Float16 *Sl, int t, float s) const {
+#pragma unroll
+        for (int p = 0; p < NB4; ++p) {
+            const int b = t + p * GT;
+            const int rb = b % RB, ib = b / RB;
+            const int o = (4 * rb) * LS + 4 * ib;
+            st4_split(Sh + o + 0 * LS, Sl + o + 0 * LS, v[p][0].x * s, v[p][1].x * s, v[p][2].x * s, v[p][3].x * s);
+            st4_split(Sh + o + 1 * LS, Sl + o + 1 * LS, v[p][0].y * s, v[p][1].y * s, v[p][2].y * s, v[p][3].y * s);
+            st4_split(Sh + o + 2 * LS, Sl + o + 2 * LS, v[p][0].z * s, v[p][1].z * s, v[p][2].z * s, v[p][3].z * s);
+            st4_split(Sh + o + 3 * LS, Sl + o + 3 * LS, v[p][0].w * s, v[p][1].w * s, v[p][2].w * s, v[p][3].w * s);
+        }
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -205,8 +286,9 @@ __global__ __launch_bounds__(GT) void projection_kernel(int64_t K, int64_t M, in
     using E = typename Tr::E;
     constexpr int BK = Tr::BK, LS = BK + Tr::PAD;
     constexpr int FM = BM / WM / 16, FN = BN / WN / 16;
-    __shared__ __attribute__((aligned(16))) E As[BM * LS];
-    __shared__ __attribute__((aligned(16))) E Bs[BN * LS];
+    constexpr int NS = Tr::SPLIT ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) E As[NS * BM * LS];
+    __shared__ __attribute__((aligned(16))) E Bs[NS * BN * LS];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wm = wv % WM, wn = wv / WM;
     const int64_t tiles_m = (M + BM - 1) / BM;
@@ -218,10 +300,17 @@ __global__ __launch_bounds__(GT) void projection_kernel(int64_t K, int64_t M, in
     const float qs = (lowp && scaling) ? 16384.0f : 1.0f;
 
     f32x4 acc[FM][FN];
+    f32x4 acc2[Tr::SPLIT ? FM : 1][Tr::SPLIT ? FN : 1];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (Tr::SPLIT) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc2[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
 
     KLoader<BK, BM> la;
     KLoader<BK, BN> lb;
@@ -229,18 +318,34 @@ __global__ __launch_bounds__(GT) void projection_kernel(int64_t K, int64_t M, in
         la.load(Q1, ld, kb, ke, i0, M, vec, t);
         lb.load(A2, ld, kb, ke, j0, N, vec, t);
     }
+    auto bscale = [&](int64_t c) {
+        return (lowp && scaling && c < N) ? pow2_scale(colmax[c], 14) : 1.0f;
+    };
     for (int64_t k0 = kb; k0 < ke; k0 += BK) {
         __syncthreads();
-        la.template store<E, LS>(As, i0, t, [&](int64_t) { return qs; });
-        lb.template store<E, LS>(Bs, j0, t, [&](int64_t c) {
-            return (lowp && scaling && c < N) ? pow2_scale(colmax[c], 14) : 1.0f;
-        });
+        if constexpr (Tr::SPLIT) {
+            la.template store_split<LS>(As, As + BM * LS, i0, t, [&](int64_t) { return qs; });
+            lb.template store_split<LS>(Bs, Bs + BN * LS, j0, t, bscale);
+        } else {
+            la.template store<E, LS>(As, i0, t, [&](int64_t) { return qs; });
+            lb.template store<E, LS>(Bs, j0, t, bscale);
+        }
         __syncthreads();
         if (k0 + BK < ke) {
             la.load(Q1, ld, k0 + BK, ke, i0, M, vec, t);
             lb.load(A2, ld, k0 + BK, ke, j0, N, vec, t);
         }
-        mma_stage<Tr, FM, FN>(As, Bs, wm * (BM / WM), wn * (BN / WN), acc, lane);
+        if constexpr (Tr::SPLIT)
+            mma_stage_split<FM, FN, BK, LS>(As, As + BM * LS, Bs, Bs + BN * LS, wm * (BM / WM),
+                                            wn * (BN / WN), acc, acc2, lane);
+        else
+            mma_stage<Tr, FM, FN>(As, Bs, wm * (BM / WM), wn * (BN / WN), acc, lane);
+    }
+    if constexpr (Tr::SPLIT) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[i][j] += acc2[i][j] * kSplitLoInv;
     }
     float *P = part + (int64_t)blockIdx.y * M * N;
 #pragma unroll
@@ -258,12 +363,13 @@ __global__ __launch_bounds__(GT) void projection_kernel(int64_t K, int64_t M, in
 }
 
 // R12[i, j] = unscale_j * sum_s part[s][i + j*M]; update scale of column j;
-// clear colmax of A2 column j (the update refreshes it).
+// with Racc, also Racc += R12 (second projection of a re-orthogonalised node).
 __global__ __launch_bounds__(256) void proj_reduce_kernel(int64_t M, int64_t N,
                                                           const float *__restrict__ part,
                                                           int splits, float *__restrict__ R12,
                                                           int64_t ldr, float *__restrict__ colmax,
-                                                          float *__restrict__ uscale, int lowp_scaled) {
+                                                          float *__restrict__ uscale, int lowp_scaled,
+                                                          float *__restrict__ Racc, int64_t ldacc) {
     const int64_t j = blockIdx.x;
     __shared__ float smax[4];
     const float unscale = lowp_scaled ? 1.0f / (16384.0f * pow2_scale(colmax[j], 14)) : 1.0f;
@@ -273,6 +379,7 @@ __global__ __launch_bounds__(256) void proj_reduce_kernel(int64_t M, int64_t N,
         for (int q = 0; q < splits; ++q) s += part[(int64_t)q * M * N + i + j * M];
         s *= unscale;
         R12[i + j * ldr] = s;
+        if (Racc) Racc[i + j * ldacc] += s;
         mx = fmaxf(mx, fabsf(s));
     }
     mx = wave_max_f(mx);
@@ -281,7 +388,6 @@ __global__ __launch_bounds__(256) void proj_reduce_kernel(int64_t M, int64_t N,
     if (threadIdx.x == 0) {
         float m2 = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
         uscale[j] = lowp_scaled ? pow2_scale(m2, 14) : 1.0f;
-        colmax[j] = 0.0f;
     }
 }
 
@@ -294,13 +400,14 @@ __global__ __launch_bounds__(GT) void update_kernel(int64_t M, int64_t N, int64_
                                                     float *__restrict__ A2, int64_t lda,
                                                     const float *__restrict__ R12, int64_t ldr,
                                                     const float *__restrict__ uscale,
-                                                    float *__restrict__ colmax, int scaling,
+                                                    float *__restrict__ cmpart, int scaling,
                                                     int vecq, int vecr, int veca) {
     using E = typename Tr::E;
     constexpr int BK = Tr::BK, LS = BK + Tr::PAD;
     constexpr int FM = BM / WM / 16, FN = BN / WN / 16;
-    __shared__ __attribute__((aligned(16))) E As[BM * LS];
-    __shared__ __attribute__((aligned(16))) E Bs[BN * LS];
+    constexpr int NS = Tr::SPLIT ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) E As[NS * BM * LS];
+    __shared__ __attribute__((aligned(16))) E Bs[NS * BN * LS];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wm = wv % WM, wn = wv / WM;
     const int64_t tiles_m = (M + BM - 1) / BM;
@@ -311,27 +418,48 @@ __global__ __launch_bounds__(GT) void update_kernel(int64_t M, int64_t N, int64_
     const float qs = scaled ? 16384.0f : 1.0f;
 
     f32x4 acc[FM][FN];
+    f32x4 acc2[Tr::SPLIT ? FM : 1][Tr::SPLIT ? FN : 1];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (Tr::SPLIT) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc2[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
 
     MLoader<BK, BM> la;
     KLoader<BK, BN> lb;
     la.load(Q1, ldq, r0, M, 0, K, vecq, t);
     lb.load(R12, ldr, 0, K, j0, N, vecr, t);
+    auto bscale = [&](int64_t c) { return (scaled && c < N) ? uscale[c] : 1.0f; };
     for (int64_t k0 = 0; k0 < K; k0 += BK) {
         __syncthreads();
-        la.template store<E, LS>(As, t, qs);
-        lb.template store<E, LS>(Bs, j0, t, [&](int64_t c) {
-            return (scaled && c < N) ? uscale[c] : 1.0f;
-        });
+        if constexpr (Tr::SPLIT) {
+            la.template store_split<LS>(As, As + BM * LS, t, qs);
+            lb.template store_split<LS>(Bs, Bs + BN * LS, j0, t, bscale);
+        } else {
+            la.template store<E, LS>(As, t, qs);
+            lb.template store<E, LS>(Bs, j0, t, bscale);
+        }
         __syncthreads();
         if (k0 + BK < K) {
             la.load(Q1, ldq, r0, M, k0 + BK, K, vecq, t);
             lb.load(R12, ldr, k0 + BK, K, j0, N, vecr, t);
         }
-        mma_stage<Tr, FM, FN>(As, Bs, wm * (BM / WM), wn * (BN / WN), acc, lane);
+        if constexpr (Tr::SPLIT)
+            mma_stage_split<FM, FN, BK, LS>(As, As + BM * LS, Bs, Bs + BN * LS, wm * (BM / WM),
+                                            wn * (BN / WN), acc, acc2, lane);
+        else
+            mma_stage<Tr, FM, FN>(As, Bs, wm * (BM / WM), wn * (BN / WN), acc, lane);
+    }
+    if constexpr (Tr::SPLIT) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[i][j] += acc2[i][j] * kSplitLoInv;
     }
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn) {
@@ -363,10 +491,27 @@ __global__ __launch_bounds__(GT) void update_kernel(int64_t M, int64_t N, int64_
                 }
             }
         }
-        cmax = fmaxf(cmax, __shfl_xor(cmax, 16));
-        cmax = fmaxf(cmax, __shfl_xor(cmax, 32));
-        if (jin && lane < 16) atomicMax(reinterpret_cast<unsigned int *>(colmax + j), __float_as_uint(cmax));
+        if (cmpart) {
+            // per-wave partial max of the updated column; reduced by colmax_reduce
+            cmax = fmaxf(cmax, __shfl_xor(cmax, 16));
+            cmax = fmaxf(cmax, __shfl_xor(cmax, 32));
+            const int64_t slot = (blockIdx.x % tiles_m) * WM + wm;
+            if (jin && lane < 16) cmpart[slot * N + j] = cmax;
+        }
     }
+}
+
+// colmax[j] = max over slots of cmpart[slot * N + j] (one wave per column).
+__global__ __launch_bounds__(256) void colmax_reduce_kernel(int64_t N, int64_t slots,
+                                                            const float *__restrict__ cmpart,
+                                                            float *__restrict__ colmax) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= N) return;
+    float mx = 0.0f;
+    for (int64_t q = lane; q < slots; q += 64) mx = fmaxf(mx, cmpart[q * N + j]);
+    mx = wave_max_f(mx);
+    if (lane == 0) colmax[j] = mx;
 }
 
 // ---------------------------------------------------------------------------
@@ -411,6 +556,7 @@ hipError_t launch_projection(hipStream_t s, int prec, int scaling, int64_t m, in
                              const float *colmax, float *part, int splits) {
     switch (prec) {
         case QRX_FP16: return proj_dispatch<PF16>(s, m, k, n2, Q1, A2, lda, colmax, part, splits, scaling);
+        case QRX_FP16X3: return proj_dispatch<PF16X3>(s, m, k, n2, Q1, A2, lda, colmax, part, splits, scaling);
         case QRX_BF16: return proj_dispatch<PBF16>(s, m, k, n2, Q1, A2, lda, colmax, part, splits, scaling);
         default: return proj_dispatch<PF32>(s, m, k, n2, Q1, A2, lda, colmax, part, splits, 0);
     }
@@ -418,45 +564,57 @@ hipError_t launch_projection(hipStream_t s, int prec, int scaling, int64_t m, in
 
 hipError_t launch_proj_reduce(hipStream_t s, int prec, int scaling, int64_t k, int64_t n2,
                               const float *part, int splits, float *R12, int64_t ldr,
-                              float *colmax, float *uscale) {
+                              float *colmax, float *uscale, float *Racc, int64_t ldacc) {
     const int lowp_scaled = (prec != QRX_FP32) && scaling;
     hipLaunchKernelGGL(proj_reduce_kernel, dim3((unsigned)n2), dim3(256), 0, s, k, n2, part,
-                       splits, R12, ldr, colmax, uscale, lowp_scaled);
+                       splits, R12, ldr, colmax, uscale, lowp_scaled, Racc, ldacc);
     return hipGetLastError();
 }
 
 template <class Tr, int BM, int BN, int WM, int WN>
 static hipError_t upd_go(hipStream_t s, int64_t m, int64_t k, int64_t n2, const float *Q1,
                          float *A2, int64_t lda, const float *R12, int64_t ldr,
-                         const float *uscale, float *colmax, int scaling) {
-    const int64_t tiles = ((m + BM - 1) / BM) * ((n2 + BN - 1) / BN);
+                         const float *uscale, float *colmax, float *cmpart, int scaling) {
+    const int64_t tiles_m = (m + BM - 1) / BM;
+    const int64_t tiles = tiles_m * ((n2 + BN - 1) / BN);
     const int vecq = aligned16(Q1) && (lda % 4 == 0);
     const int vecr = aligned16(R12) && (ldr % 4 == 0);
     const int veca = aligned16(A2) && (lda % 4 == 0);
+    float *cp = colmax ? cmpart : nullptr;
     hipLaunchKernelGGL((update_kernel<Tr, BM, BN, WM, WN>), dim3((unsigned)tiles), dim3(GT), 0, s,
-                       m, n2, k, Q1, lda, A2, lda, R12, ldr, uscale, colmax, scaling, vecq, vecr,
+                       m, n2, k, Q1, lda, A2, lda, R12, ldr, uscale, cp, scaling, vecq, vecr,
                        veca);
+    if (colmax)
+        hipLaunchKernelGGL(colmax_reduce_kernel, dim3((unsigned)((n2 + 3) / 4)), dim3(256), 0, s,
+                           n2, tiles_m * WM, cmpart, colmax);
     return hipGetLastError();
 }
+
+// Slots of partial column maxima the update may write (max over tile shapes).
+int64_t update_cmpart_slots(int64_t m) { return ((m + 127) / 128) * 2 + ((m + 255) / 256) * 4; }
 
 template <class Tr>
 static hipError_t upd_dispatch(hipStream_t s, int64_t m, int64_t k, int64_t n2, const float *Q1,
                                float *A2, int64_t lda, const float *R12, int64_t ldr,
-                               const float *uscale, float *colmax, int scaling) {
+                               const float *uscale, float *colmax, float *cmpart, int scaling) {
     if (n2 >= 128)
-        return upd_go<Tr, 128, 128, 2, 2>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax, scaling);
+        return upd_go<Tr, 128, 128, 2, 2>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax,
+                                          cmpart, scaling);
     if (n2 > 32)
-        return upd_go<Tr, 256, 64, 4, 1>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax, scaling);
-    return upd_go<Tr, 256, 32, 4, 1>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax, scaling);
+        return upd_go<Tr, 256, 64, 4, 1>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax,
+                                         cmpart, scaling);
+    return upd_go<Tr, 256, 32, 4, 1>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax, cmpart,
+                                     scaling);
 }
 
 hipError_t launch_update(hipStream_t s, int prec, int scaling, int64_t m, int64_t k, int64_t n2,
                          const float *Q1, float *A2, int64_t lda, const float *R12,
-                         int64_t ldr, const float *uscale, float *colmax) {
+                         int64_t ldr, const float *uscale, float *colmax, float *cmpart) {
     switch (prec) {
-        case QRX_FP16: return upd_dispatch<PF16>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax, scaling);
-        case QRX_BF16: return upd_dispatch<PBF16>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax, scaling);
-        default: return upd_dispatch<PF32>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax, 0);
+        case QRX_FP16: return upd_dispatch<PF16>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax, cmpart, scaling);
+        case QRX_FP16X3: return upd_dispatch<PF16X3>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax, cmpart, scaling);
+        case QRX_BF16: return upd_dispatch<PBF16>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax, cmpart, scaling);
+        default: return upd_dispatch<PF32>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax, cmpart, 0);
     }
 }
 

@@ -10,6 +10,7 @@ enum {
     S_GAMMA_TOL,           // trigger slack: stop estimate <= tol * this
     S_RNORM, S_ZNORM, S_NORMA, S_ETA, S_CONV,
     S_DELTA, S_GAMMA, S_GAMMANEW, S_CGALPHA, S_CGBETA, S_RSS,
+    S_XNORM, S_BNORM, S_SCORE,
     S_COUNT
 };
 

@@ -63,11 +63,11 @@ QRX_DEV void dd_add_prod(double &hi, double &lo, double a, double b) {  // += a*
 
 // Balanced partition of `units` units into `nblk` blocks: block i starts at
 // unit floor(i*units/nblk); blocks differ in size by at most one unit.
-QRX_DEV __host__ inline int64_t part_start(int64_t i, int64_t units, int64_t nblk) {
+__device__ __host__ inline int64_t part_start(int64_t i, int64_t units, int64_t nblk) {
     return (i * units) / nblk;
 }
 // Index of the block that contains unit u.
-QRX_DEV __host__ inline int64_t part_owner(int64_t u, int64_t units, int64_t nblk) {
+__device__ __host__ inline int64_t part_owner(int64_t u, int64_t units, int64_t nblk) {
     return ((u + 1) * nblk - 1) / units;
 }
 
@@ -101,6 +101,12 @@ hipError_t launch_tsqr_qform(hipStream_t s, float *P, int64_t ld, int64_t m, int
 hipError_t launch_copy_r_block(hipStream_t s, const float *src, int64_t ld_src, int w,
                                float *R, int64_t ldr, const float *colmax);
 
+// gram.hip : Cholesky QR twice on an FP64 Gram matrix (panel of w <= 128 columns);
+// ws holds gram_workspace_doubles(m, 128) doubles.
+hipError_t launch_gram_panel(hipStream_t s, float *P, int64_t ld, int64_t m, int w, float *R,
+                             int64_t ldr, double *ws, int reorth);
+size_t gram_workspace_doubles(int64_t m, int W);
+
 // gemm.hip : trailing products of one recursion node.
 //   projection: Part[s] (k x n2, ld k) = Q1^T A2 over row split s.
 //   reduce:     R12 = sum_s Part[s] (unscaled), written into R (ldr);
@@ -111,11 +117,12 @@ hipError_t launch_projection(hipStream_t s, int prec, int scaling, int64_t m, in
                              const float *colmax_a2, float *part, int splits);
 hipError_t launch_proj_reduce(hipStream_t s, int prec, int scaling, int64_t k, int64_t n2,
                               const float *part, int splits, float *R12, int64_t ldr,
-                              float *colmax_a2, float *uscale);
+                              float *colmax_a2, float *uscale, float *Racc, int64_t ldacc);
 hipError_t launch_update(hipStream_t s, int prec, int scaling, int64_t m, int64_t k,
                          int64_t n2, const float *Q1, float *A2, int64_t lda,
                          const float *R12, int64_t ldr, const float *uscale,
-                         float *colmax_a2);
+                         float *colmax_a2, float *cmpart);
+int64_t update_cmpart_slots(int64_t m);
 int projection_splits(int64_t m, int64_t k, int64_t n2);
 
 }  // namespace qrx

@@ -31,13 +31,14 @@ def _run(qrx, A, prec="fp32", ld=None, **kw):
     return host(Q), host(R), int(st.item())
 
 
+@pytest.mark.parametrize("panel,nb", [("gram", 0), ("gram", 16), ("gram", 32), ("tsqr", 0)])
 @pytest.mark.parametrize("m,n,ld", [(64, 64, None), (100, 1, None), (257, 33, 260), (300, 33, 303),
                                     (1000, 100, None), (1024, 256, None), (2500, 300, None),
                                     (513, 96, 515)])
-def test_fp32_qr_parity(qrx, m, n, ld):
+def test_fp32_qr_parity(qrx, m, n, ld, panel, nb):
     g = np.random.default_rng(m * 7 + n)
     A = g.standard_normal((m, n)).astype(np.float32)
-    Q, R, st = _run(qrx, A, ld=ld)
+    Q, R, st = _run(qrx, A, ld=ld, panel=panel, panel_width=nb)
     assert st == 0
     Qo, Ro = H.qr(A)
     be = M.qr_backward_error(A, Q, R)
@@ -63,11 +64,12 @@ def test_fp32_qr_c1_full_size(qrx):
     assert M.r_relative_error(R, Ro) < 1e-5
 
 
-@pytest.mark.parametrize("prec,be_bound", [("fp16", 4e-3), ("bf16", 3e-2)])
-def test_lowprec_qr_scaled_c2(qrx, prec, be_bound):
+@pytest.mark.parametrize("panel", ["gram", "tsqr"])
+@pytest.mark.parametrize("prec,be_bound", [("fp16", 4e-3), ("bf16", 3e-2), ("fp16x3", 2e-6)])
+def test_lowprec_qr_scaled_c2(qrx, prec, be_bound, panel):
     # c2 recipe (geometric spectrum, cond 1e3) at 2048 x 384, cutoff 128
     p = synth.scaled_config("c2", 2048, 384, seed=0)
-    Q, R, st = _run(qrx, p.A, prec=prec, cutoff=128)
+    Q, R, st = _run(qrx, p.A, prec=prec, cutoff=128, panel=panel)
     assert st == 0
     be = M.qr_backward_error(p.A, Q, R)
     orth = M.orthogonality(Q)
@@ -89,16 +91,31 @@ def test_fp16_scaling_matters_for_small_columns(qrx):
     assert M.qr_backward_error(A, Q, R) < 4e-3
 
 
-def test_status_nonfinite_and_singular(qrx):
+@pytest.mark.parametrize("panel", ["gram", "tsqr"])
+def test_status_nonfinite_and_singular(qrx, panel):
     g = np.random.default_rng(6)
     A = g.standard_normal((300, 40)).astype(np.float32)
     A[7, 3] = np.nan
-    _, _, st = _run(qrx, A)
+    _, _, st = _run(qrx, A, panel=panel)
     assert st == 2                       # QRX_ENONFINITE
     A = g.standard_normal((300, 40)).astype(np.float32)
     A[:, 17] = 0.0
-    _, _, st = _run(qrx, A)
+    _, _, st = _run(qrx, A, panel=panel)
     assert st == 1                       # QRX_ESINGULAR
+
+
+@pytest.mark.parametrize("panel", ["gram", "tsqr"])
+def test_ill_conditioned_column_scaled_panel(qrx, panel):
+    # c5 recipe (geometric cond 1e5, columns scaled by 10^U[-4,4]) at 4096 x 128:
+    # both panels stay backward stable and keep orthogonality at O(kappa u)
+    p = synth.scaled_config("c5", 4096, 128, seed=1)
+    Q, R, st = _run(qrx, p.A, panel=panel, cutoff=64, node_reorth=True)
+    assert st == 0
+    be = M.qr_backward_error(p.A, Q, R)
+    orth = M.orthogonality(Q)
+    print(panel, f"be={be:.2e} orth={orth:.2e}")
+    assert be < 2e-6
+    assert orth < 1e5 * 6e-8 * 20
 
 
 def test_closed_forms(qrx):
@@ -141,3 +158,21 @@ def test_c2_full_size_sampled(qrx):
     assert M.upper_triangular_ok(Rh)
     assert be < 4e-3
     assert orth < 1e-2
+
+
+@pytest.mark.parametrize("prec,orth_bound,kappa_bound", [("fp32", 1e-4, 1.2), ("fp16", 1.0, 5e3),
+                                                         ("fp16x3", 1e-3, 2.0)])
+def test_node_reorth_restores_orthogonality(qrx, prec, orth_bound, kappa_bound):
+    # Recursive block Gram-Schmidt loses orthogonality like kappa^2 u between
+    # blocks; projecting twice at each node brings ||Q^T Q - I|| back to
+    # O(kappa u) and A R^{-1} close to orthonormal (the Krylov preconditioner).
+    g = synth.rng(0)
+    A = synth.svd_matrix(g, 2048, 256, synth.spectrum("loguniform", 256, 1e6, g))
+    Q, R, st = _run(qrx, A, prec=prec, cutoff=32, panel_width=32, node_reorth=True)
+    assert st == 0
+    orth = M.orthogonality(Q)
+    s = np.linalg.svd(A.astype(np.float64) @ np.linalg.inv(R.astype(np.float64)), compute_uv=False)
+    print(prec, f"orth={orth:.2e} kappa(AR^-1)={s[0]/s[-1]:.3g}")
+    assert orth < orth_bound
+    assert s[0] / s[-1] < kappa_bound
+    assert M.qr_backward_error(A, Q, R) < (2e-6 if prec == "fp32" else 4e-3)
