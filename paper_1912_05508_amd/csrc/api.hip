@@ -154,7 +154,18 @@ struct QrWork {
     float *colmax, *uscale, *part, *rtop, *stack_base, *rcorr, *cmpart;
     double *colss, *normA, *gram;
     size_t stack_floats;
+    // 16-bit operand copies for low-precision nodes (null when there are none):
+    // Q column-major (ldc) and row-major (ldq), R12 of the current node (ld k)
+    uint16_t *qc, *qcl, *qr, *qrl, *rh, *rhl;
+    int64_t ldc, ldq;
 };
+
+bool has_lowp_nodes(const QrCfg &c, const std::vector<Op> &ops) {
+    for (const Op &o : ops)
+        if (o.kind == 1 && o.prec != QRX_FP32) return true;
+    (void)c;
+    return false;
+}
 
 void carve_qr(Carve &cv, int64_t m, int64_t n, const QrCfg &c, const std::vector<Op> &ops,
               QrWork &w) {
@@ -184,15 +195,54 @@ void carve_qr(Carve &cv, int64_t m, int64_t n, const QrCfg &c, const std::vector
     w.stack_floats = st;
     w.stack_base = cv.take<float>(c.alg == 1 ? st + 1 : 1);
     w.gram = cv.take<double>(c.alg == 0 ? gram_workspace_doubles(m, 64) : 1);
+    w.qc = w.qcl = w.qr = w.qrl = w.rh = w.rhl = nullptr;
+    w.ldc = round_up(m, 8);
+    w.ldq = round_up(n, 8);
+    if (has_lowp_nodes(c, ops)) {
+        const bool split = c.prec == QRX_FP16X3;
+        size_t rsz = 1;
+        for (const Op &o : ops)
+            if (o.kind == 1 && o.prec != QRX_FP32) rsz = std::max(rsz, (size_t)o.k * (size_t)o.n2);
+        w.qc = cv.take<uint16_t>((size_t)w.ldc * n);
+        w.qr = cv.take<uint16_t>((size_t)m * w.ldq);
+        w.rh = cv.take<uint16_t>(rsz);
+        if (split) {
+            w.qcl = cv.take<uint16_t>((size_t)w.ldc * n);
+            w.qrl = cv.take<uint16_t>((size_t)m * w.ldq);
+            w.rhl = cv.take<uint16_t>(rsz);
+        }
+    }
 }
 
-int run_panel(qrx_handle h, hipStream_t s, int64_t m, float *P, int64_t ld, int w, float *R,
-              int64_t ldr, const float *colmax, const QrCfg &c, QrWork &ws) {
+int run_panel_core(qrx_handle h, hipStream_t s, int64_t m, float *P, int64_t ld, int w,
+                   float *R, int64_t ldr, const float *colmax, const QrCfg &c, QrWork &ws);
+
+// One leaf panel (columns [c0, c0 + w) of W), then its 16-bit operand copies.
+int run_panel(qrx_handle h, hipStream_t s, int64_t m, float *W, int64_t ldw, int64_t c0, int w,
+              float *R, int64_t ldr, const QrCfg &c, QrWork &ws) {
+    float *P = W + c0 * ldw;
+    int rc = run_panel_core(h, s, m, P, ldw, w, R + c0 + c0 * ldr, ldr, ws.colmax + c0, c, ws);
+    if (rc) return rc;
+    if (ws.qc) {
+        Rec r(h, s);
+        QRX_TRY(launch_pack_q(s, c.prec, c.scaling, m, w, P, ldw, ws.qc + c0 * ws.ldc,
+                              ws.qcl ? ws.qcl + c0 * ws.ldc : nullptr, ws.ldc, ws.qr + c0,
+                              ws.qrl ? ws.qrl + c0 : nullptr, ws.ldq));
+        r.end("pack_q", 0.0, (4.0 + (ws.qcl ? 8.0 : 4.0)) * m * w);
+    }
+    return QRX_OK;
+}
+
+int run_panel_core(qrx_handle h, hipStream_t s, int64_t m, float *P, int64_t ld, int w, float *R,
+                   int64_t ldr, const float *colmax, const QrCfg &c, QrWork &ws) {
     if (c.alg == 0) {
         Rec r(h, s);
         QRX_TRY(launch_gram_panel(s, P, ld, m, w, R, ldr, ws.gram, c.reorth));
-        // two sweeps of: Gram (m w^2 FMA), Q formation (m w^2 FMA), FP64
-        r.end("gram_panel", 2.0 * 2.0 * 2.0 * m * (double)w * w, 2.0 * 3.0 * 4.0 * m * w);
+        // per sweep: Gram (m w(w+1)/2 FMA) and Q formation (m w(w+1)/2 FMA), FP64;
+        // panel traffic: read P, read P + write Q1, read Q1 + write Q (FP32)
+        const double sweeps = c.reorth ? 2.0 : 1.0;
+        r.end("gram_panel", sweeps * 2.0 * m * (double)w * (w + 1),
+              (c.reorth ? 5.0 : 3.0) * 4.0 * m * w);
         return QRX_OK;
     }
     constexpr int NB = 32;
@@ -242,10 +292,10 @@ int run_panel(qrx_handle h, hipStream_t s, int64_t m, float *P, int64_t ld, int 
 // column max-abs of W on entry.
 int run_qr(qrx_handle h, hipStream_t s, int64_t m, int64_t n, float *W, int64_t ldw, float *R,
            int64_t ldr, const QrCfg &c, const std::vector<Op> &ops, QrWork &ws) {
+    if (c.alg == 0) QRX_TRY(launch_fill_f32(s, (float *)gram_counter(ws.gram, m), 1, 0.0f));
     for (const Op &o : ops) {
         if (o.kind == 0) {
-            int rc = run_panel(h, s, m, W + o.c0 * ldw, ldw, (int)o.k, R + o.c0 + o.c0 * ldr, ldr,
-                               ws.colmax + o.c0, c, ws);
+            int rc = run_panel(h, s, m, W, ldw, o.c0, (int)o.k, R, ldr, c, ws);
             if (rc) return rc;
         } else {
             const float *Q1 = W + o.c0 * ldw;
@@ -261,47 +311,60 @@ int run_qr(qrx_handle h, hipStream_t s, int64_t m, int64_t n, float *W, int64_t 
             static const char *pnames[4] = {"proj_fp32", "proj_fp16", "proj_bf16", "proj_fp16x3"};
             static const char *unames[4] = {"update_fp32", "update_fp16", "update_bf16", "update_fp16x3"};
             const char *pn = pnames[o.prec], *un = unames[o.prec];
-            {
+            const bool lp = o.prec != QRX_FP32;
+            const size_t esz = lp ? (o.prec == QRX_FP16X3 ? 4 : 2) : 4;   // bytes per Q element read
+            // Rh = packed R12 (or correction) for the low-precision update
+            uint16_t *rh = lp ? ws.rh : nullptr, *rhl = lp ? ws.rhl : nullptr;
+            auto project = [&]() -> int {
                 Rec r(h, s);
-                QRX_TRY(launch_projection(s, o.prec, c.scaling, m, o.k, o.n2, Q1, A2, ldw, cm,
-                                          ws.part, splits));
-                r.end(pn, fl, 4.0 * m * (o.k + o.n2) + 4.0 * splits * o.k * o.n2);
-            }
+                if (lp)
+                    QRX_TRY(launch_projection_lp(s, o.prec, c.scaling, m, o.k, o.n2,
+                                                 ws.qc + o.c0 * ws.ldc,
+                                                 ws.qcl ? ws.qcl + o.c0 * ws.ldc : nullptr, ws.ldc,
+                                                 A2, ldw, cm, ws.part, splits));
+                else
+                    QRX_TRY(launch_projection(s, o.prec, c.scaling, m, o.k, o.n2, Q1, A2, ldw, cm,
+                                              ws.part, splits));
+                r.end(pn, fl, (double)esz * m * o.k + 4.0 * m * o.n2 + 4.0 * splits * o.k * o.n2);
+                return QRX_OK;
+            };
+            auto update = [&](const float *Rm, int64_t ldm, float *cmo) -> int {
+                Rec r(h, s);
+                if (lp)
+                    QRX_TRY(launch_update_lp(s, o.prec, c.scaling, m, o.k, o.n2, ws.qr + o.c0,
+                                             ws.qrl ? ws.qrl + o.c0 : nullptr, ws.ldq, rh, rhl,
+                                             o.k, A2, ldw, ws.uscale, cmo, ws.cmpart));
+                else
+                    QRX_TRY(launch_update(s, o.prec, c.scaling, m, o.k, o.n2, Q1, A2, ldw, Rm,
+                                          ldm, ws.uscale, cmo, ws.cmpart));
+                r.end(un, fl, (double)esz * m * o.k + 8.0 * m * o.n2);
+                return QRX_OK;
+            };
+            int rc = project();
+            if (rc) return rc;
             {
                 Rec r(h, s);
                 QRX_TRY(launch_proj_reduce(s, o.prec, c.scaling, o.k, o.n2, ws.part, splits, R12,
-                                           ldr, cm, ws.uscale, nullptr, 0));
+                                           ldr, cm, ws.uscale, nullptr, 0, rh, rhl, o.k));
                 r.end("proj_reduce", (double)splits * o.k * o.n2, 4.0 * (splits + 1) * o.k * o.n2);
             }
-            {
-                Rec r(h, s);
-                QRX_TRY(launch_update(s, o.prec, c.scaling, m, o.k, o.n2, Q1, A2, ldw, R12, ldr,
-                                      ws.uscale, (c.node_reorth && o.prec != QRX_FP32) ? cm : cm_out,
-                                      ws.cmpart));
-                r.end(un, fl, 4.0 * m * o.k + 8.0 * m * o.n2);
-            }
+            rc = update(R12, ldr, (c.node_reorth && lp) ? cm : cm_out);
+            if (rc) return rc;
             if (c.node_reorth) {
                 // second projection of the updated A2 against Q1: C = Q1^T A2,
                 // A2 -= Q1 C, R12 += C ("twice is enough")
-                {
-                    Rec r(h, s);
-                    QRX_TRY(launch_projection(s, o.prec, c.scaling, m, o.k, o.n2, Q1, A2, ldw, cm,
-                                              ws.part, splits));
-                    r.end(pn, fl, 4.0 * m * (o.k + o.n2) + 4.0 * splits * o.k * o.n2);
-                }
+                rc = project();
+                if (rc) return rc;
                 {
                     Rec r(h, s);
                     QRX_TRY(launch_proj_reduce(s, o.prec, c.scaling, o.k, o.n2, ws.part, splits,
-                                               ws.rcorr, o.k, cm, ws.uscale, R12, ldr));
+                                               ws.rcorr, o.k, cm, ws.uscale, R12, ldr, rh, rhl,
+                                               o.k));
                     r.end("proj_reduce", (double)splits * o.k * o.n2,
                           4.0 * (splits + 3) * o.k * o.n2);
                 }
-                {
-                    Rec r(h, s);
-                    QRX_TRY(launch_update(s, o.prec, c.scaling, m, o.k, o.n2, Q1, A2, ldw,
-                                          ws.rcorr, o.k, ws.uscale, cm_out, ws.cmpart));
-                    r.end(un, fl, 4.0 * m * o.k + 8.0 * m * o.n2);
-                }
+                rc = update(ws.rcorr, o.k, cm_out);
+                if (rc) return rc;
             }
         }
     }

@@ -101,11 +101,13 @@ hipError_t launch_tsqr_qform(hipStream_t s, float *P, int64_t ld, int64_t m, int
 hipError_t launch_copy_r_block(hipStream_t s, const float *src, int64_t ld_src, int w,
                                float *R, int64_t ldr, const float *colmax);
 
-// gram.hip : Cholesky QR twice on an FP64 Gram matrix (panel of w <= 128 columns);
-// ws holds gram_workspace_doubles(m, 128) doubles.
+// gram.hip : Cholesky QR twice on an FP64 Gram matrix (panel of w <= 64 columns);
+// ws holds gram_workspace_doubles(m, 64) doubles and its counter
+// (gram_counter) must be zeroed once before the first panel.
 hipError_t launch_gram_panel(hipStream_t s, float *P, int64_t ld, int64_t m, int w, float *R,
                              int64_t ldr, double *ws, int reorth);
 size_t gram_workspace_doubles(int64_t m, int W);
+int *gram_counter(double *ws, int64_t m);
 
 // gemm.hip : trailing products of one recursion node.
 //   projection: Part[s] (k x n2, ld k) = Q1^T A2 over row split s.
@@ -117,12 +119,33 @@ hipError_t launch_projection(hipStream_t s, int prec, int scaling, int64_t m, in
                              const float *colmax_a2, float *part, int splits);
 hipError_t launch_proj_reduce(hipStream_t s, int prec, int scaling, int64_t k, int64_t n2,
                               const float *part, int splits, float *R12, int64_t ldr,
-                              float *colmax_a2, float *uscale, float *Racc, int64_t ldacc);
+                              float *colmax_a2, float *uscale, float *Racc, int64_t ldacc,
+                              uint16_t *Rh, uint16_t *Rl, int64_t ldh);
 hipError_t launch_update(hipStream_t s, int prec, int scaling, int64_t m, int64_t k,
                          int64_t n2, const float *Q1, float *A2, int64_t lda,
                          const float *R12, int64_t ldr, const float *uscale,
                          float *colmax_a2, float *cmpart);
 int64_t update_cmpart_slots(int64_t m);
+hipError_t launch_colmax_reduce(hipStream_t s, int64_t n2, int64_t slots, const float *cmpart,
+                                float *colmax);
+
+// gemm_lp.hip : the same products in FP16 / BF16 / split FP16 on 16-bit operand
+// copies. pack_q writes the copies of one panel's Q columns (times 2^14 when
+// scaling): qc column-major (ldc), qr row-major (ldr), lo parts for split FP16;
+// the pointers address the panel's first column. Projection reads qc at Q1's
+// first column; the update reads qr there and Rh (k x n2, ld ldh) written by
+// launch_proj_reduce.
+hipError_t launch_pack_q(hipStream_t s, int prec, int scaling, int64_t m, int w, const float *Q,
+                         int64_t ldq, uint16_t *qc, uint16_t *qcl, int64_t ldc, uint16_t *qr,
+                         uint16_t *qrl, int64_t ldr);
+hipError_t launch_projection_lp(hipStream_t s, int prec, int scaling, int64_t m, int64_t k,
+                                int64_t n2, const uint16_t *qc, const uint16_t *qcl, int64_t ldc,
+                                const float *A2, int64_t lda, const float *colmax, float *part,
+                                int splits);
+hipError_t launch_update_lp(hipStream_t s, int prec, int scaling, int64_t m, int64_t k,
+                            int64_t n2, const uint16_t *qr, const uint16_t *qrl, int64_t ldq,
+                            const uint16_t *rh, const uint16_t *rhl, int64_t ldh, float *A2,
+                            int64_t lda, const float *uscale, float *colmax, float *cmpart);
 int projection_splits(int64_t m, int64_t k, int64_t n2);
 
 }  // namespace qrx
