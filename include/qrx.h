@@ -6,13 +6,15 @@
  * Square Solver on GPU with TensorCore"):
  *   - QR by recursive blocked Gram-Schmidt (Alg. 2, eq. recqr): split the
  *     columns [A1 | A2], factor A1, R12 = Q1^T A2, A2 -= Q1 R12, factor A2.
- *     The two trailing products run on the matrix cores in FP16 or BF16 with
- *     FP32 accumulation (Sec. 3.1.2); narrow panels at the leaves are
- *     factored by a communication-avoiding TSQR whose blocks are orthogonalised
- *     by modified Gram-Schmidt, run twice (eq. caqr, Alg. 4, Sec. 4.1.2).
+ *     The two trailing products run on the matrix cores in FP16, BF16 or
+ *     split FP16 with FP32 accumulation (Sec. 3.1.2); narrow panels at the
+ *     leaves are orthogonalised twice (Sec. 4.1.2), by Cholesky QR on an FP64
+ *     Gram matrix (default) or by a communication-avoiding TSQR with modified
+ *     Gram-Schmidt blocks (eq. caqr, Alg. 4).
  *   - Least squares by a Krylov iteration (LSQR, or CGLS as in Alg. 5) on
  *     A R^{-1}, i.e. right-preconditioned by the low-precision R (Sec. 3.2.3),
- *     with FP64 vectors, FP64 triangular solves and an FP64 (double-double
+ *     with FP64 vectors, R^{-1} formed once in FP64 and applied as a
+ *     triangular matrix-vector product, and an FP64 (double-double
  *     accumulated) residual check.
  *
  * Conventions for every entry point:
@@ -139,6 +141,9 @@ int qrx_qr_factor_out(qrx_handle h, int64_t m, int64_t n, const float *A, int64_
                       hipStream_t stream);
 
 /* ---- least squares ----------------------------------------------------- */
+/* Bytes of device workspace qrx_lls_solve needs: the QR workspace, a working
+ * copy of A, FP64 Krylov vectors, and X = R^{-1} as an FP64 np x np matrix
+ * (np = n rounded up to a multiple of 256), i.e. about 8 n^2 + 4 m n bytes. */
 int qrx_lls_workspace_size(qrx_handle h, int64_t m, int64_t n,
                            const qrx_lls_opts *opts, size_t *bytes);
 

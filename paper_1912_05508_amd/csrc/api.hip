@@ -395,7 +395,7 @@ int ensure_pool(qrx_handle h, size_t bytes, void **out) {
 
 // ---- Krylov workspace --------------------------------------------------------
 struct KrWork {
-    double *Dinv, *u, *r, *rc, *v, *t, *d, *z, *y, *vt, *vt2, *x, *xbest, *q;
+    double *X, *T, *tpart, *u, *r, *rc, *v, *t, *d, *z, *y, *vt, *vt2, *x, *xbest, *q;
     double *part_n, *part_n2, *part_t, *ssq, *st;
     int splits_n, splits_t;
 };
@@ -404,7 +404,9 @@ void carve_kr(Carve &cv, int64_t m, int64_t n, KrWork &k) {
     const int64_t np = round_up(n, kTrsvBlock);
     k.splits_n = kr_gemv_n_splits(m, n);
     k.splits_t = kr_gemv_t_splits(m);
-    k.Dinv = cv.take<double>((size_t)np * 64);
+    k.X = cv.take<double>((size_t)np * (size_t)np);
+    k.T = cv.take<double>(kr_trinv_tmp_doubles(np));
+    k.tpart = cv.take<double>(kr_trmv_part_doubles(np));
     k.u = cv.take<double>(m);
     k.r = cv.take<double>(m);
     k.rc = cv.take<double>(m);
@@ -488,8 +490,9 @@ int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A
     double *hs = h->host_state;
     {
         Rec r(h, s);
-        if (R) QRX_TRY(kr_dinv(s, n, np, R, ldr, k.Dinv));
-        r.end("dinv", (double)np * 64 * 64 * 64 / 3.0, 4.0 * np * 64);
+        if (R) QRX_TRY(kr_trinv(s, n, np, R, ldr, k.X, k.T));
+        // recursive block inversion: ~np^3/3 FMA in FP64
+        r.end("trinv", R ? 2.0 * (double)np * np * np / 3.0 : 0.0, R ? 8.0 * np * np : 0.0);
     }
     // the padded tails [n, np) of every n-vector must stay exactly zero
     for (double *vec : {k.x, k.xbest, k.v, k.t, k.d, k.z, k.y, k.vt}) QRX_TRY(kr_zero(s, np, vec));
@@ -508,8 +511,13 @@ int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A
     int rc;
     auto trsv = [&](const double *in, double *out, int trans) -> int {
         Rec r(h, s);
-        QRX_TRY(kr_trsv(s, n, np, R, ldr, k.Dinv, in, k.y, out, trans));
-        r.end(trans ? "trsv_t" : "trsv", R ? (double)np * np : 0.0, R ? 2.0 * np * np : 0.0);
+        if (R)
+            QRX_TRY(kr_trmv(s, np, k.X, in, out, k.tpart, trans));
+        else
+            QRX_TRY(kr_copy(s, np, in, out));
+        // upper triangle of X: np(np+1)/2 FP64 entries, one FMA each
+        r.end(trans ? "trmv_t" : "trmv_n", R ? (double)np * (np + 1) : 0.0,
+              R ? 4.0 * np * (np + 1) : 0.0);
         return QRX_OK;
     };
     auto gemv_n = [&](const double *in) -> int {

@@ -241,16 +241,24 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
     for (int k = 0; k < w; ++k) {
         const double d = S[k + k * LS];
         if (d > 0.0 && rg < NG && ri > k) {
+            // row ri of [U | L^{-1}] -= l * row k, on the L^{-1} part (c <= k) and the
+            // U part (c >= ri); all reads first, then branch-free selects
             const double l = S[k + ri * LS] / d;
+            double rk[QN], mine[QN];
 #pragma unroll
             for (int q = 0; q < QN; ++q) {
                 const int c = rg + NG * q;
-                // row ri of [U | L^{-1}]: L^{-1} part c <= k, U part c >= ri
-                if (c <= k || c >= ri) {
-                    const double coef = (c == k) ? 1.0 : S[k + c * LS];
-                    S[ri + c * LS] -= l * coef;
-                }
+                rk[q] = S[k + c * LS];
+                mine[q] = S[ri + c * LS];
             }
+#pragma unroll
+            for (int q = 0; q < QN; ++q) {
+                const int c = rg + NG * q;
+                const double coef = (c == k) ? 1.0 : rk[q];
+                mine[q] = (c <= k || c >= ri) ? fma(-l, coef, mine[q]) : mine[q];
+            }
+#pragma unroll
+            for (int q = 0; q < QN; ++q) S[ri + (rg + NG * q) * LS] = mine[q];
         }
         __syncthreads();
     }

@@ -2,153 +2,20 @@
 // (Sec. 3.2.3, Alg. 5; LSQR as the default variant).
 //
 // Per iteration the operator B = A R^{-1} and its transpose are applied as
-//   t = R^{-1} v (blocked back substitution, FP64 arithmetic on FP32 R),
+//   t = X v      (X = R^{-1} formed once in FP64, trinv.hip),
 //   q = A t      (GEMV-N: FP32 A streamed once, FP64 FMA),
 //   z = A^T u    (GEMV-T),
-//   v = R^{-T} z (blocked forward substitution on R^T).
+//   v = X^T z.
 // Both GEMVs split their reduction dimension over workgroups and sum the
-// FP64 partials in a fixed order (deterministic). The triangular solves use
-// 256-row blocks: one launch per block, whose first workgroup solves the
-// block (four 64-row sub-blocks via precomputed FP64 inverses of the 64x64
-// diagonal blocks) while the others apply the previously solved block to the
-// rows still pending. The true residual r = b - A x is accumulated in
-// double-double so the certified eta_F is not limited by FP64 cancellation.
+// FP64 partials in a fixed order (deterministic). The true residual
+// r = b - A x is accumulated in double-double so the certified eta_F is not
+// limited by FP64 cancellation.
 #include "qrx_internal.hpp"
 #include "krylov.hpp"
 
 namespace qrx {
 
 constexpr int KT = 256;
-constexpr int TB = kTrsvBlock;      // 256
-constexpr int SB = 64;              // inverted diagonal sub-block
-
-QRX_DEV double Rat(const float *R, int64_t ldr, int64_t n, int64_t i, int64_t j) {
-    if (i < n && j < n) return (double)R[i + j * ldr];
-    return (i == j) ? 1.0 : 0.0;
-}
-
-// ---- diagonal-block inverses ----------------------------------------------
-// Dinv[b] (64x64, column-major, FP64) = inverse of the upper-triangular block
-// R[64b:64b+64, 64b:64b+64] (identity-padded beyond n).
-__global__ __launch_bounds__(SB) void dinv_kernel(int64_t n, const float *__restrict__ R,
-                                                  int64_t ldr, double *__restrict__ Dinv) {
-    __shared__ double Rs[SB * (SB + 1)];
-    __shared__ double Xs[SB * (SB + 1)];
-    const int64_t b = blockIdx.x;
-    const int c = threadIdx.x;
-    const int64_t o = b * SB;
-    for (int i = 0; i < SB; ++i) Rs[i + c * (SB + 1)] = Rat(R, ldr, n, o + i, o + c);
-    __syncthreads();
-    for (int i = SB - 1; i >= 0; --i) {
-        double v = 0.0;
-        if (i <= c) {
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int l = i + 1; l <= c; ++l) s -= Rs[i + l * (SB + 1)] * Xs[l + c * (SB + 1)];
-            v = s / Rs[i + i * (SB + 1)];
-        }
-        Xs[i + c * (SB + 1)] = v;
-    }
-    for (int i = 0; i < SB; ++i) Dinv[b * SB * SB + i + c * SB] = Xs[i + c * (SB + 1)];
-}
-
-// ---- t = R^{-1} y, block J (backward order) --------------------------------
-__global__ __launch_bounds__(KT) void trsv_step_kernel(int64_t n, int64_t np,
-                                                       const float *__restrict__ R, int64_t ldr,
-                                                       const double *__restrict__ Dinv,
-                                                       double *__restrict__ y,
-                                                       double *__restrict__ out, int64_t J,
-                                                       int64_t nblk) {
-    const int t = threadIdx.x;
-    const int64_t c0 = (J + 1) * TB;   // columns of the block solved last launch
-    if (blockIdx.x == 0) {
-        __shared__ double z[TB], xs[TB], red[4][SB];
-        const int64_t row = J * TB + t;
-        double zt = y[row];
-        if (J + 1 < nblk) {
-            double acc = 0.0;
-            for (int c = 0; c < TB; ++c) acc = fma(Rat(R, ldr, n, row, c0 + c), out[c0 + c], acc);
-            zt -= acc;
-        }
-        z[t] = zt;
-        __syncthreads();
-        for (int s = TB / SB - 1; s >= 0; --s) {
-            const int i = t % SB, p = t / SB;
-            const double *D = Dinv + (J * (TB / SB) + s) * SB * SB;
-            double part = 0.0;
-            for (int c = p * 16; c < p * 16 + 16; ++c) part = fma(D[i + c * SB], z[s * SB + c], part);
-            red[p][i] = part;
-            __syncthreads();
-            if (t < SB) xs[s * SB + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
-            __syncthreads();
-            if (t < s * SB) {
-                double acc = 0.0;
-                for (int c = 0; c < SB; ++c)
-                    acc = fma(Rat(R, ldr, n, J * TB + t, J * TB + s * SB + c), xs[s * SB + c], acc);
-                z[t] -= acc;
-            }
-            __syncthreads();
-        }
-        out[row] = xs[t];
-    } else if (J + 1 < nblk) {
-        const int64_t row = (int64_t)(blockIdx.x - 1) * KT + t;
-        if (row < J * TB) {
-            double acc = 0.0;
-            for (int c = 0; c < TB; ++c) acc = fma(Rat(R, ldr, n, row, c0 + c), out[c0 + c], acc);
-            y[row] -= acc;
-        }
-    }
-}
-
-// ---- t = R^{-T} y, block J (forward order) ---------------------------------
-__global__ __launch_bounds__(KT) void trsvt_step_kernel(int64_t n, int64_t np,
-                                                        const float *__restrict__ R, int64_t ldr,
-                                                        const double *__restrict__ Dinv,
-                                                        double *__restrict__ y,
-                                                        double *__restrict__ out, int64_t J,
-                                                        int64_t nblk) {
-    const int t = threadIdx.x;
-    const int64_t r0 = (J - 1) * TB;   // rows of R (block solved last launch)
-    if (blockIdx.x == 0) {
-        __shared__ double z[TB], xs[TB], red[4][SB];
-        const int64_t col = J * TB + t;
-        double zt = y[col];
-        if (J >= 1) {
-            double acc = 0.0;
-            for (int c = 0; c < TB; ++c) acc = fma(Rat(R, ldr, n, r0 + c, col), out[r0 + c], acc);
-            zt -= acc;
-        }
-        z[t] = zt;
-        __syncthreads();
-        for (int s = 0; s < TB / SB; ++s) {
-            const int i = t % SB, p = t / SB;
-            const double *D = Dinv + (J * (TB / SB) + s) * SB * SB;
-            double part = 0.0;   // (D^T z)_i = sum_c D[c, i] z_c
-            for (int c = p * 16; c < p * 16 + 16; ++c) part = fma(D[c + i * SB], z[s * SB + c], part);
-            red[p][i] = part;
-            __syncthreads();
-            if (t < SB) xs[s * SB + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
-            __syncthreads();
-            if (t >= (s + 1) * SB) {
-                double acc = 0.0;
-                for (int c = 0; c < SB; ++c)
-                    acc = fma(Rat(R, ldr, n, J * TB + s * SB + c, J * TB + t), xs[s * SB + c], acc);
-                z[t] -= acc;
-            }
-            __syncthreads();
-        }
-        out[col] = xs[t];
-    } else if (J >= 1) {
-        // one wave per output column j >= (J+1)*TB: y[j] -= R[r0:r0+TB, j]^T out[r0:r0+TB]
-        const int lane = t & 63, wv = t >> 6;
-        const int64_t j = (J + 1) * TB + (int64_t)(blockIdx.x - 1) * 4 + wv;
-        if (j < np) {
-            double acc = 0.0;
-            for (int c = lane; c < TB; c += 64) acc = fma(Rat(R, ldr, n, r0 + c, j), out[r0 + c], acc);
-            acc = wave_sum_d(acc);
-            if (lane == 0) y[j] -= acc;
-        }
-    }
-}
 
 // ---- GEMV-N partials: part[s][r] = sum_{j in split s} A[r, j] x[j] --------
 // mode 0: FP64 accumulation; mode 1: double-double (hi in part, lo in part2).
@@ -446,11 +313,6 @@ __global__ __launch_bounds__(KT) void zero_kernel(int64_t n, double *dst) {
 // ---------------------------------------------------------------------------
 static unsigned nb256(int64_t n) { return (unsigned)((n + KT - 1) / KT); }
 
-hipError_t kr_dinv(hipStream_t s, int64_t n, int64_t np, const float *R, int64_t ldr, double *Dinv) {
-    hipLaunchKernelGGL(dinv_kernel, dim3((unsigned)(np / SB)), dim3(SB), 0, s, n, R, ldr, Dinv);
-    return hipGetLastError();
-}
-
 hipError_t kr_copy(hipStream_t s, int64_t n, const double *src, double *dst) {
     hipLaunchKernelGGL(copy_kernel, dim3(nb256(n)), dim3(KT), 0, s, n, src, dst);
     return hipGetLastError();
@@ -462,32 +324,6 @@ hipError_t kr_zero(hipStream_t s, int64_t n, double *dst) {
 hipError_t kr_set(hipStream_t s, double *st, int idx, double v) {
     hipLaunchKernelGGL(set_kernel, dim3(1), dim3(1), 0, s, st, idx, v);
     return hipGetLastError();
-}
-
-// out = R^{-1} in  (y is scratch of np entries; identity when R == null)
-hipError_t kr_trsv(hipStream_t s, int64_t n, int64_t np, const float *R, int64_t ldr,
-                   const double *Dinv, const double *in, double *y, double *out, int trans) {
-    if (!R) return kr_copy(s, np, in, out);
-    hipError_t e = kr_copy(s, np, in, y);
-    if (e != hipSuccess) return e;
-    const int64_t nblk = np / TB;
-    for (int64_t q = 0; q < nblk; ++q) {
-        const int64_t J = trans ? q : nblk - 1 - q;
-        unsigned grid;
-        if (trans) {
-            const int64_t rest = np - (J + 1) * TB;
-            grid = 1 + (unsigned)((J >= 1 && rest > 0) ? (rest + 3) / 4 : 0);
-            hipLaunchKernelGGL(trsvt_step_kernel, dim3(grid), dim3(KT), 0, s, n, np, R, ldr, Dinv,
-                               y, out, J, nblk);
-        } else {
-            grid = 1 + (unsigned)((J + 1 < nblk) ? J : 0);
-            hipLaunchKernelGGL(trsv_step_kernel, dim3(grid), dim3(KT), 0, s, n, np, R, ldr, Dinv, y,
-                               out, J, nblk);
-        }
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
 }
 
 int kr_gemv_n_splits(int64_t m, int64_t n) {

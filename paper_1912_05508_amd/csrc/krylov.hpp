@@ -14,12 +14,18 @@ enum {
     S_COUNT
 };
 
-hipError_t kr_dinv(hipStream_t s, int64_t n, int64_t np, const float *R, int64_t ldr, double *Dinv);
 hipError_t kr_copy(hipStream_t s, int64_t n, const double *src, double *dst);
 hipError_t kr_zero(hipStream_t s, int64_t n, double *dst);
 hipError_t kr_set(hipStream_t s, double *st, int idx, double v);
-hipError_t kr_trsv(hipStream_t s, int64_t n, int64_t np, const float *R, int64_t ldr,
-                   const double *Dinv, const double *in, double *y, double *out, int trans);
+// trinv.hip: X = R^{-1} (np x np FP64, ld np; np a multiple of 256; T holds
+// kr_trinv_tmp_doubles(np)), and out = X in (trans 0) or X^T in (trans 1),
+// part holding kr_trmv_part_doubles(np).
+hipError_t kr_trinv(hipStream_t s, int64_t n, int64_t np, const float *R, int64_t ldr, double *X,
+                    double *T);
+size_t kr_trinv_tmp_doubles(int64_t np);
+size_t kr_trmv_part_doubles(int64_t np);
+hipError_t kr_trmv(hipStream_t s, int64_t np, const double *X, const double *in, double *out,
+                   double *part, int trans);
 int kr_gemv_n_splits(int64_t m, int64_t n);
 int kr_gemv_t_splits(int64_t m);
 hipError_t kr_gemv_n(hipStream_t s, int64_t m, int64_t n, const float *A, int64_t lda,

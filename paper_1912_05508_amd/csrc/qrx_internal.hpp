@@ -73,7 +73,7 @@ __device__ __host__ inline int64_t part_owner(int64_t u, int64_t units, int64_t 
 
 constexpr int kPanelThreads = 256;   // TSQR block rows = threads (one row each)
 constexpr int kMaxLevels = 12;
-constexpr int kTrsvBlock = 256;      // TRSV diagonal block size
+constexpr int kTrsvBlock = 256;      // padding unit of the n-vectors and of X = R^{-1}
 
 // TSQR level descriptors of one panel (passed by value to the Q-formation kernel).
 struct TsqrLevels {

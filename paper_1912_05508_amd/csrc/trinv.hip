@@ -1,0 +1,243 @@
+// The preconditioner of the Krylov iteration as an explicit FP64 inverse.
+//
+// Right preconditioning applies R^{-1} and R^{-T} twice per iteration
+// (Sec. 3.2.3, Alg. 5) with the same R throughout, so X = R^{-1} is formed
+// once (FP64, from the FP32 R) and each application is one triangular
+// matrix-vector product: a bandwidth-bound stream over the n^2/2 entries of X
+// instead of a chain of dependent triangular-solve steps. X and X^T are
+// applied by the same matrix, so the preconditioned operator and its
+// transpose stay exact transposes of each other.
+//
+// X is built by recursive block inversion on a 64-column grid:
+//   [R11 R12; 0 R22]^{-1} = [X11, -X11 R12 X22; 0, X22],
+// leaves are the 64 x 64 diagonal blocks (inverted by back substitution in
+// FP64), and each node costs two triangular-times-dense FP64 products whose
+// K ranges skip the zero triangle. Beyond n, R is taken as the identity, so X
+// is the identity there and padded vector entries stay zero.
+#include "qrx_internal.hpp"
+#include "krylov.hpp"
+
+namespace qrx {
+
+constexpr int IB = 64;     // leaf block
+constexpr int TT = 256;    // threads
+
+QRX_DEV double Rpad(const float *R, int64_t ldr, int64_t n, int64_t i, int64_t j) {
+    if (i < n && j < n) return (double)R[i + j * ldr];
+    return (i == j) ? 1.0 : 0.0;
+}
+
+// X[o:o+64, o:o+64] = inverse of R[o:o+64, o:o+64] (identity-padded), o = 64 b.
+// One thread per column c: back substitution X(:, c) = R^{-1} e_c.
+__global__ __launch_bounds__(IB) void inv_diag_kernel(int64_t n, const float *__restrict__ R,
+                                                      int64_t ldr, double *__restrict__ X,
+                                                      int64_t ldx) {
+    __shared__ double Rs[IB * (IB + 1)];
+    __shared__ double Xs[IB * (IB + 1)];
+    const int64_t o = (int64_t)blockIdx.x * IB;
+    const int c = threadIdx.x;
+    for (int i = 0; i < IB; ++i) Rs[i + c * (IB + 1)] = Rpad(R, ldr, n, o + i, o + c);
+    __syncthreads();
+    for (int i = IB - 1; i >= 0; --i) {
+        double v = 0.0;
+        if (i <= c) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int l = i + 1; l <= c; ++l) s -= Rs[i + l * (IB + 1)] * Xs[l + c * (IB + 1)];
+            const double d = Rs[i + i * (IB + 1)];
+            v = (d != 0.0) ? s / d : 0.0;
+        }
+        Xs[i + c * (IB + 1)] = v;
+    }
+    for (int i = 0; i < IB; ++i) X[(o + i) + (o + c) * ldx] = Xs[i + c * (IB + 1)];
+}
+
+// C (M x N, ldc) = alpha * A B, FP64 accumulation, all dimensions multiples of
+// 64. A is FP32 or FP64 (element (i, k) at A[i + k*lda], zero where i >= arl
+// or k >= acl); B is FP64 (B[k + j*ldb]). TRI = 1: B is upper triangular (k <= j
+// contributes); TRI = 2: A is upper triangular (k >= i contributes).
+// Workgroup: 64 x 64 tile, thread 4 x 4 outputs, K stages of 16 through LDS.
+template <class TA, int TRI>
+__global__ __launch_bounds__(TT) void tri_gemm_kernel(int64_t M, int64_t N, int64_t K,
+                                                      const TA *__restrict__ A, int64_t lda,
+                                                      int64_t arl, int64_t acl,
+                                                      const double *__restrict__ B, int64_t ldb,
+                                                      double *__restrict__ C, int64_t ldc,
+                                                      double alpha) {
+    constexpr int BT = 64, BK = 16, LS = BT + 4;
+    __shared__ __align__(16) double As[BK * LS];   // As[k][i]
+    __shared__ __align__(16) double Bs[BK * LS];   // Bs[k][j]
+    const int t = threadIdx.x;
+    const int64_t tiles_m = M / BT;
+    const int64_t i0 = (blockIdx.x % tiles_m) * BT, j0 = (blockIdx.x / tiles_m) * BT;
+    const int64_t kb = (TRI == 2) ? i0 : 0;
+    const int64_t ke = (TRI == 1) ? ((j0 + BT < K) ? j0 + BT : K) : K;
+    const int ti = t % 16, tj = t / 16;
+    const int ar = t % 64, akq = t / 64;          // A loads: row ar, k = akq*4 + q
+    const int bk = t % 16, bjq = t / 16;          // B loads: k = bk, column bjq*4 + q
+    double pa[4], pb[4];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = i0 + ar, k = k0 + akq * 4 + q;
+            pa[q] = (i < arl && k < acl) ? (double)A[i + k * lda] : 0.0;
+            pb[q] = B[(k0 + bk) + (j0 + bjq * 4 + q) * ldb];
+        }
+    };
+    double acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    if (kb < ke) load(kb);
+    for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            As[(akq * 4 + q) * LS + ar] = pa[q];
+            Bs[bk * LS + bjq * 4 + q] = pb[q];
+        }
+        __syncthreads();
+        if (k0 + BK < ke) load(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = As[kk * LS + ti * 4 + q];
+                b[q] = Bs[kk * LS + tj * 4 + q];
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+        }
+    }
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+            C[(i0 + ti * 4 + x) + (j0 + tj * 4 + y) * ldc] = alpha * acc[x][y];
+}
+
+// ---- applications -----------------------------------------------------------
+constexpr int TCS = 256;   // columns per split of the upper-triangular GEMV
+
+// part[c][i] = sum_{j in split c, j >= i} X[i, j] v[j] for the splits c that
+// reach the diagonal of row block blockIdx.x (rows of 256).
+__global__ __launch_bounds__(TT) void trmv_n_kernel(int64_t np, const double *__restrict__ X,
+                                                    int64_t ldx, const double *__restrict__ v,
+                                                    double *__restrict__ part) {
+    const int64_t rb = blockIdx.x, c = blockIdx.y;
+    if ((c + 1) * TCS <= rb * TT) return;          // split entirely left of the diagonal
+    const int64_t i = rb * TT + threadIdx.x;
+    const int64_t j1 = (c + 1) * TCS;
+    const int64_t j0 = (c * TCS > i) ? c * TCS : i;
+    double acc = 0.0;
+    const double *xr = X + i;
+    int64_t j = j0;
+    for (; j + 4 <= j1; j += 4) {
+        const double x0 = xr[j * ldx], x1 = xr[(j + 1) * ldx];
+        const double x2 = xr[(j + 2) * ldx], x3 = xr[(j + 3) * ldx];
+        acc = fma(x0, v[j], acc);
+        acc = fma(x1, v[j + 1], acc);
+        acc = fma(x2, v[j + 2], acc);
+        acc = fma(x3, v[j + 3], acc);
+    }
+    for (; j < j1; ++j) acc = fma(xr[j * ldx], v[j], acc);
+    part[c * np + i] = acc;
+}
+
+// out[i] = sum over the splits that reach row i, in split order (deterministic).
+__global__ __launch_bounds__(TT) void trmv_n_combine_kernel(int64_t np, int64_t nsplit,
+                                                            const double *__restrict__ part,
+                                                            double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * TT + threadIdx.x;
+    if (i >= np) return;
+    double s = 0.0;
+    for (int64_t c = i / TCS; c < nsplit; ++c) s += part[c * np + i];
+    out[i] = s;
+}
+
+// out[j] = sum_{i <= j} X[i, j] u[i]: one wave per column, fixed reduction order.
+__global__ __launch_bounds__(TT) void trmv_t_kernel(int64_t np, const double *__restrict__ X,
+                                                    int64_t ldx, const double *__restrict__ u,
+                                                    double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * (TT / 64) + (threadIdx.x >> 6);
+    if (j >= np) return;
+    const double *xc = X + j * ldx;
+    double acc = 0.0;
+    int64_t i = lane;
+    for (; i + 192 <= j; i += 256) {
+        acc = fma(xc[i], u[i], acc);
+        acc = fma(xc[i + 64], u[i + 64], acc);
+        acc = fma(xc[i + 128], u[i + 128], acc);
+        acc = fma(xc[i + 192], u[i + 192], acc);
+    }
+    for (; i <= j; i += 64) acc = fma(xc[i], u[i], acc);
+    acc = wave_sum_d(acc);
+    if (lane == 0) out[j] = acc;
+}
+
+// ---------------------------------------------------------------------------
+size_t kr_trinv_tmp_doubles(int64_t np) { return (size_t)(np / 2 + IB) * (size_t)(np / 2 + IB); }
+
+template <class TA, int TRI>
+static hipError_t tri_gemm(hipStream_t s, int64_t M, int64_t N, int64_t K, const TA *A,
+                           int64_t lda, int64_t arl, int64_t acl, const double *B, int64_t ldb,
+                           double *C, int64_t ldc, double alpha) {
+    const unsigned tiles = (unsigned)((M / 64) * (N / 64));
+    hipLaunchKernelGGL((tri_gemm_kernel<TA, TRI>), dim3(tiles), dim3(TT), 0, s, M, N, K, A, lda,
+                       arl, acl, B, ldb, C, ldc, alpha);
+    return hipGetLastError();
+}
+
+// Columns [c0, c0 + w) of X (w a multiple of 64, leaves already inverted).
+static hipError_t trinv_node(hipStream_t s, int64_t n, const float *R, int64_t ldr, double *X,
+                             int64_t ldx, double *T, int64_t c0, int64_t w) {
+    if (w <= IB) return hipSuccess;
+    const int64_t s1 = IB * ((w / IB + 1) / 2), s2 = w - s1;
+    hipError_t e = trinv_node(s, n, R, ldr, X, ldx, T, c0, s1);
+    if (e != hipSuccess) return e;
+    e = trinv_node(s, n, R, ldr, X, ldx, T, c0 + s1, s2);
+    if (e != hipSuccess) return e;
+    // T = R12 X22 (s1 x s2, ld s1); R beyond n is the identity, so R12 is zero there
+    const int64_t arl = n - c0, acl = n - (c0 + s1);
+    e = tri_gemm<float, 1>(s, s1, s2, s2, R + c0 + (c0 + s1) * ldr, ldr, arl, acl,
+                           X + (c0 + s1) + (c0 + s1) * ldx, ldx, T, s1, 1.0);
+    if (e != hipSuccess) return e;
+    // X12 = -X11 T
+    const int64_t big = (int64_t)1 << 62;
+    return tri_gemm<double, 2>(s, s1, s2, s1, X + c0 + c0 * ldx, ldx, big, big, T, s1,
+                               X + c0 + (c0 + s1) * ldx, ldx, -1.0);
+}
+
+hipError_t kr_trinv(hipStream_t s, int64_t n, int64_t np, const float *R, int64_t ldr, double *X,
+                    double *T) {
+    if (np % IB) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(inv_diag_kernel, dim3((unsigned)(np / IB)), dim3(IB), 0, s, n, R, ldr, X,
+                       np);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return trinv_node(s, n, R, ldr, X, np, T, 0, np);
+}
+
+size_t kr_trmv_part_doubles(int64_t np) { return (size_t)((np + TCS - 1) / TCS) * (size_t)np; }
+
+hipError_t kr_trmv(hipStream_t s, int64_t np, const double *X, const double *in, double *out,
+                   double *part, int trans) {
+    if (np % TT) return hipErrorInvalidValue;
+    if (trans) {
+        hipLaunchKernelGGL(trmv_t_kernel, dim3((unsigned)(np / (TT / 64))), dim3(TT), 0, s, np, X,
+                           np, in, out);
+        return hipGetLastError();
+    }
+    const int64_t nsplit = (np + TCS - 1) / TCS;
+    hipLaunchKernelGGL(trmv_n_kernel, dim3((unsigned)(np / TT), (unsigned)nsplit), dim3(TT), 0, s,
+                       np, X, np, in, part);
+    hipLaunchKernelGGL(trmv_n_combine_kernel, dim3((unsigned)(np / TT)), dim3(TT), 0, s, np,
+                       nsplit, part, out);
+    return hipGetLastError();
+}
+
+}  // namespace qrx
