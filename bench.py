@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--lls-size", default=None, help="override the LLS workload size, e.g. 16384x2048")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is "
@@ -188,6 +190,14 @@ def main():
     import paper_1912_05508_amd as P
     assert torch.cuda.is_available(), "needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calib:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 256 MiB device-to-device copies")
+        del src, dst
     m, n = args.m, args.n
     log(f"generating c2 workload {m} x {n} ...")
     t0 = time.perf_counter()

@@ -165,6 +165,43 @@ int qrx_lls_solve_with_R(qrx_handle h, int64_t m, int64_t n, const float *A, int
                          void *work, size_t work_bytes, const qrx_lls_opts *opts,
                          qrx_lls_info *info, hipStream_t stream);
 
+/* ---- batched: many small problems, one workgroup each -------------------
+ * Problem i is A_i (m[i] x n[i], FP32, column-major, lda[i] >= m[i]) with
+ * 1 <= n[i] <= 256 and n[i] <= m[i] <= 2^31. The arrays m, n, lda, ldr, A, R,
+ * b, x, status and info are HOST arrays of length `batch`; the matrices and
+ * vectors they point to are device memory owned by the caller. Each problem
+ * runs Alg. 2 with 32-column Cholesky-QR panels (re-orthogonalised) and FP32
+ * products, or BF16 products (FP32 accumulation, no operand scaling: BF16
+ * has the FP32 exponent range) for nodes wider than the cutoff (0 = 64).
+ * Options other than gemm_prec in {QRX_FP32, QRX_BF16}, panel_width 0 or 32,
+ * cutoff and no_col_scaling are rejected with QRX_EINVAL (no TSQR panel,
+ * single-pass panel or node re-orthogonalisation here). Both calls block
+ * until the batch is done. Problems are independent: a singular or
+ * non-finite problem reports its own status and does not affect the others. */
+int qrx_qr_batched_workspace_size(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
+                                  const qrx_qr_opts *opts, size_t *bytes);
+
+/* In place: A_i receives Q_i, R_i (n[i] x n[i], ldr[i] >= n[i]) the upper-
+ * triangular factor; status[i] = QRX_OK, QRX_ESINGULAR or QRX_ENONFINITE. */
+int qrx_qr_factor_batched(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
+                          float *const *A, const int64_t *lda, float *const *R,
+                          const int64_t *ldr, void *work, size_t work_bytes,
+                          const qrx_qr_opts *opts, int *status, hipStream_t stream);
+
+int qrx_lls_batched_workspace_size(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
+                                   const qrx_lls_opts *opts, size_t *bytes);
+
+/* x_i = argmin ||A_i x - b_i|| (b_i FP64 of length m[i], x_i FP64 of length
+ * n[i]) by the batched QR followed by R-preconditioned LSQR with FP64 vectors,
+ * certified with a double-double residual (eta_F <= tol, as qrx_lls_solve).
+ * LSQR only (method 0) and no starting iterate (use_x0 = 0). A_i and b_i are
+ * not modified. info[i] as for qrx_lls_solve; qr_ms and krylov_ms are the
+ * device times of the whole batch's two phases. */
+int qrx_lls_solve_batched(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
+                          const float *const *A, const int64_t *lda, const double *const *b,
+                          double *const *x, void *work, size_t work_bytes,
+                          const qrx_lls_opts *opts, qrx_lls_info *info, hipStream_t stream);
+
 /* ---- timing ------------------------------------------------------------ */
 /* When enabled, every kernel launch is bracketed by HIP events on its
  * stream. qrx_timing_get synchronises those events and returns one record

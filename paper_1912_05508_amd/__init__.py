@@ -124,6 +124,52 @@ class Handle:
         _lib.check(rc, "qrx_lls_solve")
         return x, info.as_dict()
 
+    # -- batched ---------------------------------------------------------------
+    @staticmethod
+    def _arrays(mats, extra=()):
+        m = (C.c_int64 * len(mats))(*[int(a.shape[0]) for a in mats])
+        n = (C.c_int64 * len(mats))(*[int(a.shape[1]) for a in mats])
+        lda = (C.c_int64 * len(mats))(*[_ld(a) for a in mats])
+        return m, n, lda
+
+    def qr_batched(self, mats, prec="fp32", **kw):
+        """In-place QR of a list of column-major (m_i, n_i) float32 tensors
+        (n_i <= 256): returns (list of Q = the same tensors, list of R, statuses)."""
+        import torch
+        mats = [colmajor(a) for a in mats]
+        k = len(mats)
+        m, n, lda = self._arrays(mats)
+        Rs = [torch.empty((int(a.shape[1]),) * 2, dtype=torch.float32, device=a.device).t()
+              for a in mats]
+        ldr = (C.c_int64 * k)(*[_ld(r) for r in Rs])
+        Ap = (C.c_void_p * k)(*[a.data_ptr() for a in mats])
+        Rp = (C.c_void_p * k)(*[r.data_ptr() for r in Rs])
+        st = (C.c_int * k)()
+        o = qr_opts(prec, **kw)
+        rc = self.lib.qrx_qr_factor_batched(self.h, k, m, n, Ap, lda, Rp, ldr, None, 0,
+                                            C.byref(o), st, _stream())
+        _lib.check(rc, "qrx_qr_factor_batched")
+        return mats, Rs, list(st)
+
+    def lstsq_batched(self, mats, rhs, prec="bf16", **kw):
+        """Least squares for lists of column-major (m_i, n_i) float32 tensors and
+        float64 (m_i,) vectors: returns (list of x_i, list of info dicts)."""
+        import torch
+        mats = [colmajor(a) for a in mats]
+        rhs = [b.contiguous() for b in rhs]
+        k = len(mats)
+        m, n, lda = self._arrays(mats)
+        xs = [torch.zeros(int(a.shape[1]), dtype=torch.float64, device=a.device) for a in mats]
+        Ap = (C.c_void_p * k)(*[a.data_ptr() for a in mats])
+        bp = (C.c_void_p * k)(*[b.data_ptr() for b in rhs])
+        xp = (C.c_void_p * k)(*[x.data_ptr() for x in xs])
+        infos = (qrx_lls_info * k)()
+        o = lls_opts(prec, **kw)
+        rc = self.lib.qrx_lls_solve_batched(self.h, k, m, n, Ap, lda, bp, xp, None, 0,
+                                            C.byref(o), infos, _stream())
+        _lib.check(rc, "qrx_lls_solve_batched")
+        return xs, [infos[i].as_dict() for i in range(k)]
+
     # -- timing ---------------------------------------------------------------
     def timing(self, enable=True):
         _lib.check(self.lib.qrx_timing_enable(self.h, 1 if enable else 0))

@@ -62,6 +62,14 @@ _SIGS = {
                                 C.POINTER(qrx_lls_opts), C.POINTER(qrx_lls_info), _P]),
     "qrx_lls_solve_with_R": (C.c_int, [_P, _I64, _I64, _P, _I64, _P, _I64, _P, _P, _P, C.c_size_t,
                                        C.POINTER(qrx_lls_opts), C.POINTER(qrx_lls_info), _P]),
+    "qrx_qr_batched_workspace_size": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(qrx_qr_opts),
+                                                 C.POINTER(C.c_size_t)]),
+    "qrx_qr_factor_batched": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, _P, _P, C.c_size_t,
+                                        C.POINTER(qrx_qr_opts), _P, _P]),
+    "qrx_lls_batched_workspace_size": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(qrx_lls_opts),
+                                                  C.POINTER(C.c_size_t)]),
+    "qrx_lls_solve_batched": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, _P, _P, C.c_size_t,
+                                        C.POINTER(qrx_lls_opts), _P, _P]),
     "qrx_timing_enable": (C.c_int, [_P, C.c_int]),
     "qrx_timing_reset": (C.c_int, [_P]),
     "qrx_timing_get": (C.c_int, [_P, C.POINTER(qrx_kernel_stat), C.c_int, C.POINTER(C.c_int)]),

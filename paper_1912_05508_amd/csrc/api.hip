@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "batched.hpp"
 #include "krylov.hpp"
 #include "qrx_internal.hpp"
 
@@ -689,6 +690,108 @@ int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+// ---- batched (one workgroup per problem) -----------------------------------
+namespace {
+
+struct BPlan {
+    QrCfg c;
+    std::vector<BOp> ops;         // schedules of the distinct n, concatenated
+    std::vector<int> op0, nops;   // per problem
+    std::vector<int> order;       // longest first
+    size_t bytes = 0;
+};
+
+int resolve_batched(const qrx_qr_opts *o, QrCfg &c) {
+    qrx_qr_opts z;
+    memset(&z, 0, sizeof(z));
+    if (!o) o = &z;
+    if (o->gemm_prec != QRX_FP32 && o->gemm_prec != QRX_BF16) return QRX_EINVAL;
+    if (o->panel_alg != 0 || o->panel_single_pass != 0 || o->node_reorth == 1) return QRX_EINVAL;
+    if (o->panel_width != 0 && o->panel_width != kBPanel) return QRX_EINVAL;
+    if (o->cutoff < 0 || o->block_rows < 0) return QRX_EINVAL;
+    if (o->no_col_scaling < 0 || o->no_col_scaling > 1) return QRX_EINVAL;
+    c.prec = o->gemm_prec;
+    c.alg = 0;
+    c.nb = kBPanel;
+    int cut = o->cutoff ? o->cutoff : 64;
+    if (cut < c.nb) cut = c.nb;
+    c.c = (int)round_up(cut, c.nb);
+    c.reorth = 1;
+    c.scaling = 0;
+    c.node_reorth = 0;
+    return QRX_OK;
+}
+
+// Problem checks, schedules, launch order and workspace size (lls: working
+// copies and Krylov vectors too).
+int plan_batched(int batch, const int64_t *m, const int64_t *n, const int64_t *lda,
+                 const qrx_qr_opts *o, bool lls, BPlan &P) {
+    if (batch < 1 || !m || !n) return QRX_EINVAL;
+    int rc = resolve_batched(o, P.c);
+    if (rc) return rc;
+    std::map<int64_t, std::pair<int, int>> sched;
+    P.op0.resize(batch);
+    P.nops.resize(batch);
+    std::vector<double> cost(batch);
+    size_t bytes = 0;
+    auto add = [&](size_t b) { bytes = (bytes + 255) / 256 * 256 + b; };
+    for (int i = 0; i < batch; ++i) {
+        if (n[i] < 1 || n[i] > kBMaxN || m[i] < n[i] || m[i] > ((int64_t)1 << 31)) return QRX_EINVAL;
+        if (lda && lda[i] < m[i]) return QRX_EINVAL;
+        auto it = sched.find(n[i]);
+        if (it == sched.end()) {
+            std::vector<Op> ops;
+            plan_rec(0, n[i], P.c, ops);
+            const int start = (int)P.ops.size();
+            for (const Op &op : ops)
+                P.ops.push_back({op.kind, (int)op.c0, (int)op.k, (int)op.n2,
+                                 op.kind == 1 && op.prec != QRX_FP32 ? 1 : 0});
+            it = sched.emplace(n[i], std::make_pair(start, (int)ops.size())).first;
+        }
+        P.op0[i] = it->second.first;
+        P.nops[i] = it->second.second;
+        const double mm = (double)m[i], nn = (double)n[i];
+        cost[i] = mm * nn * nn + (lls ? 40.0 * mm * nn : 0.0);
+        add(sizeof(float) * (size_t)n[i] * (size_t)n[i]);                        // R
+        if (lls) {
+            add(sizeof(float) * (size_t)round_up(m[i], 4) * (size_t)n[i]);       // W
+            add(2 * sizeof(double) * (size_t)m[i]);                              // u, q
+        }
+    }
+    P.order.resize(batch);
+    for (int i = 0; i < batch; ++i) P.order[i] = i;
+    std::stable_sort(P.order.begin(), P.order.end(),
+                     [&](int a, int b) { return cost[a] > cost[b]; });
+    add(sizeof(BProb) * (size_t)batch);
+    add(sizeof(int) * (size_t)batch);
+    add(sizeof(BOp) * P.ops.size());
+    add(sizeof(BOut) * (size_t)batch);
+    P.bytes = bytes + 256;
+    return QRX_OK;
+}
+
+struct BRun {
+    BProb *probs;
+    int *order;
+    BOp *ops;
+    BOut *out;
+};
+
+// Carves the descriptor arrays (after the per-problem buffers) and uploads them.
+int upload_batched(hipStream_t s, Carve &cv, std::vector<BProb> &hp, const BPlan &P, BRun &r) {
+    const int batch = (int)hp.size();
+    r.probs = cv.take<BProb>(batch);
+    r.order = cv.take<int>(batch);
+    r.ops = cv.take<BOp>(P.ops.size());
+    r.out = cv.take<BOut>(batch);
+    QRX_TRY(hipMemcpyAsync(r.probs, hp.data(), sizeof(BProb) * batch, hipMemcpyHostToDevice, s));
+    QRX_TRY(hipMemcpyAsync(r.order, P.order.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
+    QRX_TRY(hipMemcpyAsync(r.ops, P.ops.data(), sizeof(BOp) * P.ops.size(), hipMemcpyHostToDevice, s));
+    return QRX_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *qrx_status_string(int st) {
@@ -959,6 +1062,150 @@ int qrx_lls_solve_with_R(qrx_handle h, int64_t m, int64_t n, const float *A, int
     if (R && ldr < n) return QRX_EINVAL;
     return lls_common(h, m, n, A, lda, R, R ? ldr : n, false, b, x, work, work_bytes, opts, info,
                       stream);
+}
+
+int qrx_qr_batched_workspace_size(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
+                                  const qrx_qr_opts *opts, size_t *bytes) {
+    if (!h || !bytes) return QRX_EINVAL;
+    BPlan P;
+    int rc = plan_batched(batch, m, n, nullptr, opts, false, P);
+    if (rc) return rc;
+    *bytes = P.bytes;
+    return QRX_OK;
+}
+
+int qrx_qr_factor_batched(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
+                          float *const *A, const int64_t *lda, float *const *R,
+                          const int64_t *ldr, void *work, size_t work_bytes,
+                          const qrx_qr_opts *opts, int *status, hipStream_t stream) {
+    if (!h || !A || !lda || !R || !ldr || !status) return QRX_EINVAL;
+    BPlan P;
+    int rc = plan_batched(batch, m, n, lda, opts, false, P);
+    if (rc) return rc;
+    for (int i = 0; i < batch; ++i)
+        if (!A[i] || !R[i] || ldr[i] < n[i]) return QRX_EINVAL;
+    if (work && work_bytes < P.bytes) return QRX_EINVAL;
+    if (h->device < 0 || hipSetDevice(h->device) != hipSuccess) return QRX_EHIP;
+    if (!work && (rc = ensure_pool(h, P.bytes, &work))) return rc;
+    Carve cv(work);
+    std::vector<BProb> hp(batch);
+    for (int i = 0; i < batch; ++i) {
+        BProb &b = hp[i];
+        memset(&b, 0, sizeof(b));
+        b.m = m[i];
+        b.n = n[i];
+        b.lda = lda[i];
+        b.ldw = lda[i];
+        b.ldr = ldr[i];
+        b.A = A[i];
+        b.W = A[i];
+        b.R = R[i];
+        b.op0 = P.op0[i];
+        b.nops = P.nops[i];
+        cv.take<float>((size_t)n[i] * (size_t)n[i]);   // keeps the layout of the size query
+    }
+    BRun r;
+    if ((rc = upload_batched(stream, cv, hp, P, r))) return rc;
+    {
+        Rec rec(h, stream);
+        QRX_TRY(launch_bqr(stream, P.c.prec, batch, r.probs, r.order, r.ops, 0, r.out));
+        rec.end("bqr", 0, 0);
+    }
+    std::vector<BOut> out(batch);
+    QRX_TRY(hipMemcpyAsync(out.data(), r.out, sizeof(BOut) * batch, hipMemcpyDeviceToHost, stream));
+    QRX_TRY(hipStreamSynchronize(stream));
+    for (int i = 0; i < batch; ++i) status[i] = out[i].status;
+    return QRX_OK;
+}
+
+int qrx_lls_batched_workspace_size(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
+                                   const qrx_lls_opts *opts, size_t *bytes) {
+    if (!h || !bytes) return QRX_EINVAL;
+    BPlan P;
+    int rc = plan_batched(batch, m, n, nullptr, opts ? &opts->qr : nullptr, true, P);
+    if (rc) return rc;
+    *bytes = P.bytes;
+    return QRX_OK;
+}
+
+int qrx_lls_solve_batched(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
+                          const float *const *A, const int64_t *lda, const double *const *b,
+                          double *const *x, void *work, size_t work_bytes,
+                          const qrx_lls_opts *opts, qrx_lls_info *info, hipStream_t stream) {
+    if (!h || !A || !lda || !b || !x || !info) return QRX_EINVAL;
+    BPlan P;
+    int rc = plan_batched(batch, m, n, lda, opts ? &opts->qr : nullptr, true, P);
+    if (rc) return rc;
+    KrCfg kc;
+    if ((rc = resolve_lls(opts, kc))) return rc;
+    if (opts && (opts->method != 0 || opts->use_x0)) return QRX_EINVAL;
+    for (int i = 0; i < batch; ++i)
+        if (!A[i] || !b[i] || !x[i]) return QRX_EINVAL;
+    if (work && work_bytes < P.bytes) return QRX_EINVAL;
+    if (h->device < 0 || hipSetDevice(h->device) != hipSuccess) return QRX_EHIP;
+    if (!work && (rc = ensure_pool(h, P.bytes, &work))) return rc;
+    Carve cv(work);
+    std::vector<BProb> hp(batch);
+    for (int i = 0; i < batch; ++i) {
+        BProb &q = hp[i];
+        memset(&q, 0, sizeof(q));
+        q.m = m[i];
+        q.n = n[i];
+        q.lda = lda[i];
+        q.ldr = n[i];
+        q.A = A[i];
+        q.b = b[i];
+        q.x = x[i];
+        q.R = cv.take<float>((size_t)n[i] * (size_t)n[i]);
+        q.ldw = round_up(m[i], 4);
+        q.W = cv.take<float>((size_t)q.ldw * (size_t)n[i]);
+        double *uq = cv.take<double>(2 * (size_t)m[i]);
+        q.u = uq;
+        q.q = uq + m[i];
+        q.op0 = P.op0[i];
+        q.nops = P.nops[i];
+    }
+    BRun r;
+    if ((rc = upload_batched(stream, cv, hp, P, r))) return rc;
+    hipEvent_t e0, e1, e2;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    hipEventCreate(&e2);
+    hipEventRecord(e0, stream);
+    {
+        Rec rec(h, stream);
+        QRX_TRY(launch_bqr(stream, P.c.prec, batch, r.probs, r.order, r.ops, 1, r.out));
+        rec.end("bqr", 0, 0);
+    }
+    hipEventRecord(e1, stream);
+    {
+        Rec rec(h, stream);
+        QRX_TRY(launch_blsqr(stream, batch, r.probs, r.order, kc.tol, kc.max_iter, r.out));
+        rec.end("blsqr", 0, 0);
+    }
+    hipEventRecord(e2, stream);
+    std::vector<BOut> out(batch);
+    QRX_TRY(hipMemcpyAsync(out.data(), r.out, sizeof(BOut) * batch, hipMemcpyDeviceToHost, stream));
+    QRX_TRY(hipStreamSynchronize(stream));
+    float ms1 = 0.f, ms2 = 0.f;
+    hipEventElapsedTime(&ms1, e0, e1);
+    hipEventElapsedTime(&ms2, e1, e2);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipEventDestroy(e2);
+    for (int i = 0; i < batch; ++i) {
+        qrx_lls_info &f = info[i];
+        memset(&f, 0, sizeof(f));
+        f.status = out[i].status;
+        f.iters = out[i].iters;
+        f.restarts = out[i].restarts;
+        f.eta_F = out[i].eta;
+        f.resid_norm = out[i].rnorm;
+        f.normA_F = out[i].normA;
+        f.qr_ms = ms1;
+        f.krylov_ms = ms2;
+    }
+    return QRX_OK;
 }
 
 int qrx_timing_enable(qrx_handle h, int enable) {

@@ -1,0 +1,574 @@
+// Batched least squares: many small problems, one workgroup per problem.
+//
+// Each problem runs the same method as the single-problem path (Alg. 2 with
+// Cholesky-QR-twice panels, then the R-preconditioned LSQR of Sec. 3.2.3 with
+// FP64 vectors and a double-double residual certification), but entirely
+// inside one workgroup: the problems are small (n <= 256), so a workgroup
+// streams its own matrix from HBM/L2 while 2 workgroups per CU keep the chip
+// busy. Problems are launched longest-first (one workgroup each, grid = batch),
+// so the hardware dispatcher balances the uneven sizes.
+//
+// bqr_kernel   scan (||A||_F, max column norm, finite check, working copy),
+//              the recursion over a per-n schedule: 32-column panels by the
+//              Gram sweeps of gram_common.hpp, nodes by in-workgroup MFMA
+//              projection / update (FP32, or BF16 above the cutoff), then R
+//              finalisation (strictly-lower part zeroed, diagonal checked).
+// blsqr_kernel LSQR on A R^{-1}: triangular solves in 64-row blocks, each
+//              diagonal block solved by one wave from registers (row or column
+//              of R per lane, values passed by cross-lane shuffles), the rest
+//              applied by all waves; GEMVs with FP64 accumulation; the
+//              iteration is certified with b - A x in double-double and
+//              restarted on the certified residual when needed.
+#include "gemm_common.hpp"
+#include "gram_common.hpp"
+#include "batched.hpp"
+
+namespace qrx {
+
+constexpr int BT = 256;   // threads per workgroup
+static_assert(BT == GT && BT == gram::GT, "one workgroup shape for every phase");
+
+// LDS of the QR kernel (doubles): the panel phase needs the most.
+constexpr int kPanelLds = gram::Lds<32>::C_DOUBLES + gram::Lds<32>::X_DOUBLES +
+                          gram::Lds<32>::RED_DOUBLES + 528 + 32 * 33 + 32 * 32 + 32;
+constexpr int kGemmLds = 2 * 128 * (64 + 8) * 2 / 8;   // two 128 x (BK+PAD) 16-bit tiles
+static_assert(2 * 128 * (32 + 4) * 4 / 8 <= kGemmLds, "FP32 tiles fit");
+constexpr int kBqrLds = kPanelLds > kGemmLds ? kPanelLds : kGemmLds;
+
+QRX_DEV bool al16(const void *p) { return (((uintptr_t)p) & 15) == 0; }
+
+// Sum over the workgroup (fixed order); every thread gets the result.
+QRX_DEV double bsum(double v, double *sh) {
+    v = wave_sum_d(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+QRX_DEV double bmax(double v, double *sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+// ---------------------------------------------------------------------------
+// In-workgroup trailing products (same tiles as the single-problem kernels).
+// ---------------------------------------------------------------------------
+// R12 (k x n2, ldr) = Q1^T A2 over K = m rows, 128 x 128 output tiles.
+template <class Tr>
+QRX_DEV void wg_project(int64_t m, int k, int n2, const float *Q1, const float *A2, int64_t ld,
+                        float *R12, int64_t ldr, typename Tr::E *As, typename Tr::E *Bs, int t) {
+    using E = typename Tr::E;
+    constexpr int BK = Tr::BK, LS = BK + Tr::PAD, FM = 4, FN = 4;
+    const int lane = t & 63, wv = t >> 6, wm = wv % 2, wn = wv / 2;
+    const bool vec = al16(Q1) && al16(A2) && (ld % 4 == 0);
+    auto one = [](int64_t) { return 1.0f; };
+    for (int i0 = 0; i0 < k; i0 += 128)
+        for (int j0 = 0; j0 < n2; j0 += 128) {
+            f32x4 acc[FM][FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            KLoader<BK, 128> la, lb;
+            la.load(Q1, ld, 0, m, i0, k, vec, t);
+            lb.load(A2, ld, 0, m, j0, n2, vec, t);
+            for (int64_t k0 = 0; k0 < m; k0 += BK) {
+                __syncthreads();
+                la.template store<E, LS>(As, i0, t, one);
+                lb.template store<E, LS>(Bs, j0, t, one);
+                __syncthreads();
+                if (k0 + BK < m) {
+                    la.load(Q1, ld, k0 + BK, m, i0, k, vec, t);
+                    lb.load(A2, ld, k0 + BK, m, j0, n2, vec, t);
+                }
+                mma_stage<Tr, FM, FN>(As, Bs, wm * 64, wn * 64, acc, lane);
+            }
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+                for (int fn = 0; fn < FN; ++fn) {
+                    const int j = j0 + wn * 64 + fn * 16 + (lane & 15);
+                    const int ib = i0 + wm * 64 + fm * 16 + 4 * (lane >> 4);
+                    if (j < n2) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (ib + v < k) R12[(ib + v) + (int64_t)j * ldr] = acc[fm][fn][v];
+                    }
+                }
+        }
+    __syncthreads();
+}
+
+// A2 (m x n2) -= Q1 (m x k) R12 (k x n2), 128-row x 128-column tiles.
+template <class Tr>
+QRX_DEV void wg_update(int64_t m, int k, int n2, const float *Q1, float *A2, int64_t ld,
+                       const float *R12, int64_t ldr, typename Tr::E *As, typename Tr::E *Bs,
+                       int t) {
+    using E = typename Tr::E;
+    constexpr int BK = Tr::BK, LS = BK + Tr::PAD, FM = 4, FN = 4;
+    const int lane = t & 63, wv = t >> 6, wm = wv % 2, wn = wv / 2;
+    const bool vecq = al16(Q1) && (ld % 4 == 0);
+    const bool vecr = al16(R12) && (ldr % 4 == 0);
+    const bool veca = al16(A2) && (ld % 4 == 0);
+    auto one = [](int64_t) { return 1.0f; };
+    for (int j0 = 0; j0 < n2; j0 += 128)
+        for (int64_t r0 = 0; r0 < m; r0 += 128) {
+            f32x4 acc[FM][FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            MLoader<BK, 128> la;
+            KLoader<BK, 128> lb;
+            la.load(Q1, ld, r0, m, 0, k, vecq, t);
+            lb.load(R12, ldr, 0, k, j0, n2, vecr, t);
+            for (int k0 = 0; k0 < k; k0 += BK) {
+                __syncthreads();
+                la.template store<E, LS>(As, t, 1.0f);
+                lb.template store<E, LS>(Bs, j0, t, one);
+                __syncthreads();
+                if (k0 + BK < k) {
+                    la.load(Q1, ld, r0, m, k0 + BK, k, vecq, t);
+                    lb.load(R12, ldr, k0 + BK, k, j0, n2, vecr, t);
+                }
+                mma_stage<Tr, FM, FN>(As, Bs, wm * 64, wn * 64, acc, lane);
+            }
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) {
+                const int j = j0 + wn * 64 + fn * 16 + (lane & 15);
+                if (j >= n2) continue;
+#pragma unroll
+                for (int fm = 0; fm < FM; ++fm) {
+                    const int64_t rb = r0 + wm * 64 + fm * 16 + 4 * (lane >> 4);
+                    float *dst = A2 + (int64_t)j * ld + rb;
+                    if (veca && rb + 3 < m) {
+                        float4 x = *reinterpret_cast<float4 *>(dst);
+                        x.x -= acc[fm][fn][0];
+                        x.y -= acc[fm][fn][1];
+                        x.z -= acc[fm][fn][2];
+                        x.w -= acc[fm][fn][3];
+                        *reinterpret_cast<float4 *>(dst) = x;
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (rb + v < m) dst[v] -= acc[fm][fn][v];
+                    }
+                }
+            }
+        }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// In-workgroup panel: Cholesky QR twice with FP64 Gram matrices (w <= 32).
+// ---------------------------------------------------------------------------
+QRX_DEV void wg_panel(float *P, int64_t ld, int64_t m, int w, float *Rb, int64_t ldr, double *lds,
+                      int t) {
+    using L = gram::Lds<32>;
+    double *C = lds;
+    double *Xs = C + L::C_DOUBLES;
+    double *red = Xs + L::X_DOUBLES;
+    double *Gl = red + L::RED_DOUBLES;
+    double *S = Gl + 528;
+    double *R1 = S + 32 * 33;
+    double *dg = R1 + 32 * 32;
+    const int64_t nch = (m + gram::CH - 1) / gram::CH;
+    double acc[4][4];
+    auto zero = [&]() {
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    };
+    auto factor = [&]() {   // Gl -> S -> elimination
+        for (int idx = t; idx < 32 * 32; idx += BT) {
+            const int i = idx % 32, j = idx / 32;
+            S[i + j * 33] = (i <= j && j < w) ? Gl[gram::upk(i, j)] : 0.0;
+        }
+        __syncthreads();
+        gram::chol_elim<32, BT>(S, dg, w, t);
+    };
+    zero();
+    gram::sweep<32, false, true>(P, ld, m, w, 0, nch, Xs, C, acc, t);
+    gram::gram_store<32>(acc, red, Gl, t);
+    __syncthreads();
+    factor();
+    for (int idx = t; idx < 32 * 32; idx += BT) {
+        const int i = idx % 32, j = idx / 32;
+        Xs[i * L::XLD + j] = gram::chol_X<32>(S, dg, w, i, j);
+        R1[idx] = gram::chol_R<32>(S, dg, w, i, j);
+    }
+    zero();
+    gram::sweep<32, true, true>(P, ld, m, w, 0, nch, Xs, C, acc, t);
+    gram::gram_store<32>(acc, red, Gl, t);
+    __syncthreads();
+    factor();
+    // R = R2 R1 into the diagonal block; X2 into Xs for the final sweep
+    for (int idx = t; idx < 32 * 32; idx += BT) {
+        const int i = idx % 32, j = idx / 32;
+        if (i < w && j < w) {
+            double v = 0.0;
+            if (i <= j) {
+                for (int l = i; l <= j; ++l) v = fma(S[i + l * 33], R1[l + j * 32], v);
+                v *= dg[i];
+            }
+            Rb[i + (int64_t)j * ldr] = (float)v;
+        }
+        Xs[i * L::XLD + j] = gram::chol_X<32>(S, dg, w, i, j);
+    }
+    gram::sweep<32, true, false>(P, ld, m, w, 0, nch, Xs, C, acc, t);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// QR kernel
+// ---------------------------------------------------------------------------
+template <class Tr>
+__global__ __launch_bounds__(BT) void bqr_kernel(const BProb *__restrict__ probs,
+                                                 const int *__restrict__ order,
+                                                 const BOp *__restrict__ ops, int copy,
+                                                 BOut *__restrict__ out) {
+    __shared__ __align__(16) double lds[kBqrLds];
+    __shared__ double sh[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int pi = order[blockIdx.x];
+    const BProb p = probs[pi];
+    const int64_t m = p.m;
+    const int n = (int)p.n;
+
+    // scan: ||A||_F^2 and the largest column norm (FP64), finite check, copy
+    double ss_tot = 0.0, ss_max = 0.0;
+    int bad = 0;
+    for (int j = wv; j < n; j += BT / 64) {
+        double s = 0.0;
+        const float *a = p.A + (int64_t)j * p.lda;
+        float *wcol = p.W + (int64_t)j * p.ldw;
+        for (int64_t r = lane; r < m; r += 64) {
+            const float v = a[r];
+            if (!(fabsf(v) <= 3.4028235e38f)) bad = 1;
+            s = fma((double)v, (double)v, s);
+            if (copy) wcol[r] = v;
+        }
+        s = wave_sum_d(s);
+        ss_tot += s;
+        ss_max = fmax(ss_max, s);
+    }
+    ss_tot = bsum(lane == 0 ? ss_tot : 0.0, sh);
+    ss_max = bmax(ss_max, sh);
+    bad = bsum(bad ? 1.0 : 0.0, sh) > 0.0;
+    __syncthreads();
+
+    if (!bad) {
+        using E = typename Tr::E;
+        for (int o = p.op0; o < p.op0 + p.nops; ++o) {
+            const BOp op = ops[o];
+            float *Wc = p.W + (int64_t)op.c0 * p.ldw;
+            if (op.kind == 0) {
+                wg_panel(Wc, p.ldw, m, op.k, p.R + op.c0 + (int64_t)op.c0 * p.ldr, p.ldr, lds, t);
+            } else {
+                float *A2 = p.W + (int64_t)(op.c0 + op.k) * p.ldw;
+                float *R12 = p.R + op.c0 + (int64_t)(op.c0 + op.k) * p.ldr;
+                if (op.lowp) {
+                    E *As = reinterpret_cast<E *>(lds);
+                    E *Bs = As + 128 * (Tr::BK + Tr::PAD);
+                    wg_project<Tr>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
+                    wg_update<Tr>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
+                } else {
+                    float *As = reinterpret_cast<float *>(lds);
+                    float *Bs = As + 128 * (PF32::BK + PF32::PAD);
+                    wg_project<PF32>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
+                    wg_update<PF32>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
+                }
+            }
+        }
+    }
+    // R finalisation: zero the strictly-lower part, check the diagonal
+    int sing = 0;
+    for (int idx = t; idx < n * n; idx += BT) {
+        const int i = idx % n, j = idx / n;
+        float *rij = p.R + i + (int64_t)j * p.ldr;
+        if (i > j || bad) *rij = 0.0f;
+        if (i == j && !bad) {
+            const float d = *rij;
+            if (!(d > 0.0f) || !(d <= 3.4028235e38f)) sing = 1;
+        }
+    }
+    sing = bsum(sing ? 1.0 : 0.0, sh) > 0.0;
+    if (t == 0) {
+        out[pi].status = bad ? QRX_ENONFINITE : (sing ? QRX_ESINGULAR : QRX_OK);
+        out[pi].normA = sqrt(ss_tot);
+        out[pi].rho = sqrt(ss_max);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LSQR kernel
+// ---------------------------------------------------------------------------
+struct BVec {   // n-vectors in LDS (kBMaxN each)
+    double *x, *xb, *v, *t, *d, *z, *y, *xs;
+};
+
+// out = R^{-1} in (trans 0) or R^{-T} in (trans 1); R FP32 upper (n x n, ldr),
+// arithmetic in FP64. y is scratch, Rb holds a 64 x 65 block (LDS). Blocks of
+// 64 rows: the diagonal block is staged in LDS and solved by wave 0 (one row
+// per lane, solved values passed by cross-lane shuffles); all waves then apply
+// the solved block to the remaining rows.
+QRX_DEV void wg_trsv(const float *R, int64_t ldr, int n, const double *in, double *y, double *out,
+                     float *Rb, int trans, int t) {
+    const int lane = t & 63, wv = t >> 6;
+    const int nblk = (n + 63) / 64;
+    for (int i = t; i < kBMaxN; i += BT) y[i] = (i < n) ? in[i] : 0.0;
+    for (int q = 0; q < nblk; ++q) {
+        const int J = trans ? q : nblk - 1 - q;
+        const int o = J * 64;
+        const int bw = (n - o < 64) ? n - o : 64;
+        // Rb[i * 65 + c] = block entry the lane i uses at step c:
+        // R[o+i][o+c] (trans 0) or R[o+c][o+i] (trans 1)
+        __syncthreads();
+        for (int idx = t; idx < 64 * 64; idx += BT) {
+            const int r = idx % 64, c = idx / 64;    // R[o+r][o+c], coalesced along r
+            const float v = (r < bw && c < bw) ? R[(o + r) + (int64_t)(o + c) * ldr] : 0.0f;
+            if (trans) Rb[c * 65 + r] = v; else Rb[r * 65 + c] = v;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            const bool in_b = lane < bw;
+            const float dgl = in_b ? Rb[lane * 65 + lane] : 1.0f;
+            const double dinv = (dgl != 0.0f) ? 1.0 / (double)dgl : 0.0;
+            double yi = y[o + lane];
+            double xi = 0.0;
+            for (int st = 0; st < bw; ++st) {
+                const int c = trans ? st : bw - 1 - st;
+                const double xc = __shfl(yi * dinv, c);
+                if (lane == c) xi = xc;
+                const bool upd = trans ? (lane > c) : (lane < c);
+                if (upd) yi = fma(-(double)Rb[lane * 65 + c], xc, yi);
+            }
+            out[o + lane] = in_b ? xi : 0.0;
+        }
+        __syncthreads();
+        if (!trans) {
+            for (int r = t; r < o; r += BT) {
+                double acc = 0.0;
+                for (int c = 0; c < bw; ++c) acc = fma((double)R[r + (int64_t)(o + c) * ldr], out[o + c], acc);
+                y[r] -= acc;
+            }
+        } else {
+            for (int j = o + 64 + t; j < n; j += BT) {
+                double acc = 0.0;
+                for (int c = 0; c < bw; ++c) acc = fma((double)R[(o + c) + (int64_t)j * ldr], out[o + c], acc);
+                y[j] -= acc;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = n + t; i < kBMaxN; i += BT) out[i] = 0.0;
+    __syncthreads();
+}
+
+// u <- A t - alpha u (alpha = 0: u <- A t); returns ||u||^2. t in LDS.
+QRX_DEV double wg_gemv_n(const BProb &p, const double *tv, double alpha, double *u, double *sh,
+                         int t) {
+    double ss = 0.0;
+    for (int64_t r = t; r < p.m; r += BT) {
+        double acc = 0.0;
+        for (int j = 0; j < (int)p.n; ++j) acc = fma((double)p.A[r + (int64_t)j * p.lda], tv[j], acc);
+        const double v = (alpha != 0.0) ? acc - alpha * u[r] : acc;
+        u[r] = v;
+        ss = fma(v, v, ss);
+    }
+    return bsum(ss, sh);
+}
+
+// z <- A^T u (one wave per column, fixed reduction order); z in LDS.
+QRX_DEV void wg_gemv_t(const BProb &p, const double *u, double *z, int t) {
+    const int lane = t & 63, wv = t >> 6;
+    for (int j = wv; j < (int)p.n; j += BT / 64) {
+        const float *a = p.A + (int64_t)j * p.lda;
+        double acc = 0.0;
+        for (int64_t r = lane; r < p.m; r += 64) acc = fma((double)a[r], u[r], acc);
+        acc = wave_sum_d(acc);
+        if (lane == 0) z[j] = acc;
+    }
+    __syncthreads();
+}
+
+// Certification of x: q = b - A x (double-double), z = A^T q; returns the score
+// min(eta_F, ||r|| / (||A||_F ||x|| + ||b||)) and sets eta, rnorm.
+QRX_DEV double wg_certify(const BProb &p, const double *x, double *z, double *q, double normA,
+                          double bnorm, double &eta, double &rnorm, double *sh, int t) {
+    double ss = 0.0;
+    for (int64_t r = t; r < p.m; r += BT) {
+        double h = p.b[r], l = 0.0;
+        for (int j = 0; j < (int)p.n; ++j) dd_add_prod(h, l, -(double)p.A[r + (int64_t)j * p.lda], x[j]);
+        const double v = h + l;
+        q[r] = v;
+        ss = fma(v, v, ss);
+    }
+    rnorm = sqrt(bsum(ss, sh));
+    wg_gemv_t(p, q, z, t);
+    double zz = 0.0, xx = 0.0;
+    for (int j = t; j < (int)p.n; j += BT) {
+        zz = fma(z[j], z[j], zz);
+        xx = fma(x[j], x[j], xx);
+    }
+    zz = bsum(zz, sh);
+    xx = bsum(xx, sh);
+    eta = (rnorm > 0.0 && normA > 0.0) ? sqrt(zz) / (normA * rnorm) : 0.0;
+    const double den = normA * sqrt(xx) + bnorm;
+    const double s1 = den > 0.0 ? rnorm / den : 0.0;
+    return fmin(eta, s1);
+}
+
+__global__ __launch_bounds__(BT) void blsqr_kernel(const BProb *__restrict__ probs,
+                                                   const int *__restrict__ order, double tol,
+                                                   int max_iter, BOut *__restrict__ out) {
+    __shared__ double vecs[8 * kBMaxN];
+    __shared__ float Rb[64 * 65];
+    __shared__ double sh[4];
+    const int t = threadIdx.x;
+    const int pi = order[blockIdx.x];
+    const BProb p = probs[pi];
+    const int n = (int)p.n;
+    BVec V;
+    V.x = vecs;
+    V.xb = vecs + kBMaxN;
+    V.v = vecs + 2 * kBMaxN;
+    V.t = vecs + 3 * kBMaxN;
+    V.d = vecs + 4 * kBMaxN;
+    V.z = vecs + 5 * kBMaxN;
+    V.y = vecs + 6 * kBMaxN;
+    V.xs = vecs + 7 * kBMaxN;
+    for (int i = t; i < 8 * kBMaxN; i += BT) vecs[i] = 0.0;
+    __syncthreads();
+    const int qst = out[pi].status;
+    if (qst != QRX_OK) {
+        for (int j = t; j < n; j += BT) p.x[j] = 0.0;
+        if (t == 0) {
+            out[pi].iters = 0;
+            out[pi].restarts = 0;
+            out[pi].eta = 0.0;
+            out[pi].rnorm = 0.0;
+        }
+        return;
+    }
+    const double normA = out[pi].normA;
+    // the LSQR estimate bounds ||(A R^{-1})^T r|| / ||r||; the scaled test compares
+    // it with the eta_F target through the largest column norm
+    const double trig = normA > 0.0 ? out[pi].rho / normA : 1.0;
+    double bb = 0.0;
+    for (int64_t r = t; r < p.m; r += BT) bb = fma(p.b[r], p.b[r], bb);
+    const double bnorm = sqrt(bsum(bb, sh));
+
+    double gamma = 1.0, best = 1e300, eta = 0.0, rnorm = 0.0, best_eta = 0.0, best_rn = 0.0;
+    int iters = 0, restarts = 0, stall = 0, status = QRX_ENOCONV;
+    for (int outer = 0;; ++outer) {
+        // certify the current x; q = residual, z = A^T q
+        const double score = wg_certify(p, V.x, V.z, p.q, normA, bnorm, eta, rnorm, sh, t);
+        if (score < best) {
+            if (score < 0.5 * best) stall = 0; else ++stall;
+            best = score;
+            best_eta = eta;
+            best_rn = rnorm;
+            for (int j = t; j < kBMaxN; j += BT) V.xb[j] = V.x[j];
+        } else {
+            ++stall;
+        }
+        __syncthreads();
+        if (best <= tol) {
+            status = QRX_OK;
+            break;
+        }
+        if (iters >= max_iter || stall >= 3 || rnorm == 0.0) break;
+        if (outer > 0) {
+            ++restarts;
+            gamma = fmax(0.5 * gamma, 0.01);
+        }
+        // LSQR on the correction: min || A R^{-1} y - q ||, x += R^{-1} y
+        double beta = rnorm;
+        for (int64_t r = t; r < p.m; r += BT) p.u[r] = p.q[r] / beta;
+        for (int j = t; j < kBMaxN; j += BT) V.z[j] = V.z[j] / beta;   // A^T u
+        __syncthreads();
+        wg_trsv(p.R, p.ldr, n, V.z, V.y, V.v, Rb, 1, t);                     // v = R^{-T} A^T u
+        double aa = 0.0;
+        for (int j = t; j < kBMaxN; j += BT) aa = fma(V.v[j], V.v[j], aa);
+        double alpha = sqrt(bsum(aa, sh));
+        if (alpha == 0.0) break;
+        for (int j = t; j < kBMaxN; j += BT) V.v[j] /= alpha;
+        __syncthreads();
+        wg_trsv(p.R, p.ldr, n, V.v, V.y, V.t, Rb, 0, t);                     // t = R^{-1} v
+        for (int j = t; j < kBMaxN; j += BT) V.d[j] = V.t[j];
+        __syncthreads();
+        double phibar = beta, rhobar = alpha;
+        const int every = 50;
+        for (int it = 0; it < every && iters < max_iter; ++it) {
+            ++iters;
+            const double b2 = wg_gemv_n(p, V.t, alpha, p.u, sh, t);   // u = A t - alpha u
+            beta = sqrt(b2);
+            if (beta > 0.0)
+                for (int64_t r = t; r < p.m; r += BT) p.u[r] /= beta;
+            __syncthreads();
+            wg_gemv_t(p, p.u, V.z, t);                                   // z = A^T u
+            wg_trsv(p.R, p.ldr, n, V.z, V.y, V.xs, Rb, 1, t);                // xs = R^{-T} z
+            aa = 0.0;
+            for (int j = t; j < kBMaxN; j += BT) {
+                const double vj = V.xs[j] - beta * V.v[j];
+                V.v[j] = vj;
+                aa = fma(vj, vj, aa);
+            }
+            alpha = sqrt(bsum(aa, sh));
+            if (alpha > 0.0)
+                for (int j = t; j < kBMaxN; j += BT) V.v[j] /= alpha;
+            const double rho = hypot(rhobar, beta);
+            const double c = rhobar / rho, s = beta / rho;
+            const double theta = s * alpha;
+            rhobar = -c * alpha;
+            const double phi = c * phibar;
+            phibar = s * phibar;
+            for (int j = t; j < kBMaxN; j += BT) V.x[j] = fma(phi / rho, V.d[j], V.x[j]);
+            __syncthreads();
+            wg_trsv(p.R, p.ldr, n, V.v, V.y, V.t, Rb, 0, t);                 // t = R^{-1} v
+            for (int j = t; j < kBMaxN; j += BT) V.d[j] = V.t[j] - (theta / rho) * V.d[j];
+            __syncthreads();
+            const double est = alpha * fabs(c) * trig;
+            if (est <= tol * gamma || alpha == 0.0 || beta == 0.0) break;
+        }
+    }
+    for (int j = t; j < n; j += BT) p.x[j] = V.xb[j];
+    if (t == 0) {
+        out[pi].status = status;
+        out[pi].iters = iters;
+        out[pi].restarts = restarts;
+        out[pi].eta = best_eta;
+        out[pi].rnorm = best_rn;
+    }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_bqr(hipStream_t s, int prec, int batch, const BProb *probs, const int *order,
+                      const BOp *ops, int copy, BOut *out) {
+    const dim3 g((unsigned)batch), b(BT);
+    switch (prec) {
+        case QRX_FP32:
+            hipLaunchKernelGGL(bqr_kernel<PF32>, g, b, 0, s, probs, order, ops, copy, out);
+            break;
+        case QRX_BF16:
+            hipLaunchKernelGGL(bqr_kernel<PBF16>, g, b, 0, s, probs, order, ops, copy, out);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_blsqr(hipStream_t s, int batch, const BProb *probs, const int *order,
+                        double tol, int max_iter, BOut *out) {
+    hipLaunchKernelGGL(blsqr_kernel, dim3((unsigned)batch), dim3(BT), 0, s, probs, order, tol,
+                       max_iter, out);
+    return hipGetLastError();
+}
+
+}  // namespace qrx

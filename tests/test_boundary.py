@@ -148,3 +148,47 @@ def test_product_does_not_touch_the_oracle():
         if f.endswith(".py"):
             txt = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_1912_05508_amd" not in txt and "synth" not in txt, f
+
+
+def _i64(*v):
+    return (C.c_int64 * len(v))(*v)
+
+
+def test_batched_sizes_and_validation(lib, host_handle):
+    from paper_1912_05508_amd import _lib
+    sz = C.c_size_t()
+    m, n = _i64(100, 64, 300), _i64(40, 64, 256)
+    assert lib.qrx_lls_batched_workspace_size(host_handle, 3, m, n, None, C.byref(sz)) == 0
+    lls_bytes = sz.value
+    assert lib.qrx_qr_batched_workspace_size(host_handle, 3, m, n, None, C.byref(sz)) == 0
+    # the LLS workspace adds working copies and FP64 m-vectors to the QR one
+    assert lls_bytes > sz.value > 4 * (40 * 40 + 64 * 64 + 256 * 256)
+    EINVAL = _lib.QRX_EINVAL
+    for bad_m, bad_n in (((10,), (11,)), ((300,), (257,)), ((5,), (0,))):
+        assert lib.qrx_qr_batched_workspace_size(host_handle, 1, _i64(*bad_m), _i64(*bad_n), None,
+                                                 C.byref(sz)) == EINVAL
+    assert lib.qrx_qr_batched_workspace_size(host_handle, 0, m, n, None, C.byref(sz)) == EINVAL
+    for field, val in (("gemm_prec", 1), ("gemm_prec", 3), ("panel_alg", 1), ("panel_width", 16),
+                       ("panel_single_pass", 1), ("node_reorth", 1)):
+        o = _lib.qr_opts("fp32")
+        setattr(o, field, val)
+        assert lib.qrx_qr_batched_workspace_size(host_handle, 3, m, n, C.byref(o),
+                                                 C.byref(sz)) == EINVAL, field
+    o = _lib.qr_opts("bf16")
+    assert lib.qrx_qr_batched_workspace_size(host_handle, 3, m, n, C.byref(o), C.byref(sz)) == 0
+    # lda < m, null arrays and CGLS / x0 are rejected before any device work
+    ptrs = (C.c_void_p * 3)(0x1000, 0x1000, 0x1000)
+    info = (_lib.qrx_lls_info * 3)()
+    lo = _lib.lls_opts("bf16")
+    assert lib.qrx_lls_solve_batched(host_handle, 3, m, n, ptrs, _i64(99, 64, 300), ptrs, ptrs,
+                                     None, 0, C.byref(lo), info, None) == EINVAL
+    assert lib.qrx_lls_solve_batched(host_handle, 3, m, n, None, _i64(100, 64, 300), ptrs, ptrs,
+                                     None, 0, C.byref(lo), info, None) == EINVAL
+    for field, val in (("method", 1), ("use_x0", 1)):
+        lo = _lib.lls_opts("bf16")
+        setattr(lo, field, val)
+        assert lib.qrx_lls_solve_batched(host_handle, 3, m, n, ptrs, _i64(100, 64, 300), ptrs,
+                                         ptrs, None, 0, C.byref(lo), info, None) == EINVAL
+    st = (C.c_int * 3)()
+    assert lib.qrx_qr_factor_batched(host_handle, 3, m, n, ptrs, _i64(100, 64, 300), ptrs,
+                                     _i64(40, 63, 256), None, 0, None, st, None) == EINVAL

@@ -1,0 +1,130 @@
+"""GPU parity of the batched path (one workgroup per problem) against the
+oracle, through the C ABI: QR factors of uneven problems (FP32 and BF16
+products), per-problem statuses, and least-squares solutions certified to
+eta_F <= 1e-10."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import householder as H
+from oracle import lls as L
+from oracle import metrics as M
+from oracle import rmgs as G
+
+from gpu_util import dev, dev64, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qrx():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1912_05508_amd as P
+    h = P.Handle()
+    yield h
+    h.close()
+
+
+def _mixed_shapes():
+    # ragged n (multiples of 8 and not), m = n, tall, the 256-column maximum,
+    # and more rows than one 128-row update tile or one 64-row Gram chunk
+    return [(1, 1), (8, 8), (17, 5), (40, 40), (100, 33), (130, 64), (300, 96), (257, 128),
+            (1000, 129), (640, 160), (2048, 200), (256, 256), (3000, 256), (4096, 248)]
+
+
+def _matrix(g, m, n, scale=True):
+    A = g.standard_normal((m, n))
+    if scale:
+        A = A * 10.0 ** g.uniform(-2, 2, n)
+    return np.asfortranarray(A.astype(np.float32))
+
+
+@pytest.mark.parametrize("prec,be_bound", [("fp32", 2e-6), ("bf16", 4e-3)])
+def test_batched_qr_matches_oracle(qrx, prec, be_bound):
+    import torch
+    g = np.random.default_rng(11)
+    shapes = _mixed_shapes()
+    mats = [_matrix(g, m, n) for m, n in shapes]
+    Qs, Rs, st = qrx.qr_batched([dev(A) for A in mats], prec=prec)
+    torch.cuda.synchronize()
+    assert st == [0] * len(mats)
+    for A, Q, R in zip(mats, Qs, Rs):
+        Qh, Rh = host(Q), host(R)
+        n = A.shape[1]
+        assert M.upper_triangular_ok(Rh)
+        assert np.all(np.diag(Rh) > 0)
+        be = M.qr_backward_error(A, Qh, Rh)
+        assert be < be_bound, (A.shape, be)
+        # R against the oracle's sign-normalised Householder R, column by column
+        # (column scaling 10^[-2,2] makes a global norm meaningless)
+        _, Ro = H.qr(A.astype(np.float64))
+        cerr = np.linalg.norm(Rh - Ro, axis=0) / np.linalg.norm(Ro, axis=0)
+        kappa = np.linalg.cond(A.astype(np.float64) / np.linalg.norm(A, axis=0))
+        assert cerr.max() < max(1e-5, 50 * kappa * (6e-8 if prec == "fp32" else 4e-3)), A.shape
+        if n > 1:
+            # against the error-model emulator of the same recursion (BF16 operands
+            # unscaled, cutoff 64); FP32 products: O(kappa u32)
+            orth = M.orthogonality(Qh)
+            if prec == "bf16":
+                Qe, _ = G.rmgs(A.astype(np.float64), cutoff=64, prec="bf16", scale=False)
+                bound = max(4 * M.orthogonality(Qe), 1e-4)
+            else:
+                bound = max(1e-5, 20 * np.linalg.cond(A.astype(np.float64)) * 6e-8)
+            assert orth < bound, (A.shape, orth, bound)
+
+
+def test_batched_status_per_problem(qrx):
+    import torch
+    g = np.random.default_rng(12)
+    good = _matrix(g, 200, 48)
+    nan = _matrix(g, 150, 40)
+    nan[17, 3] = np.nan
+    zero = _matrix(g, 120, 24)
+    zero[:, 5] = 0.0
+    mats = [good, nan, zero, good.copy()]
+    Qs, Rs, st = qrx.qr_batched([dev(A) for A in mats], prec="bf16")
+    torch.cuda.synchronize()
+    assert st == [0, 2, 1, 0]                # OK, QRX_ENONFINITE, QRX_ESINGULAR, OK
+    assert M.qr_backward_error(good, host(Qs[0]), host(Rs[0])) < 4e-3
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_batched_lls_reaches_1e10(qrx, prec):
+    import torch
+    probs = synth.batched_problems(48, seed=3, nmin_j=1, nmax_j=32, kmin=2, kmax=16)
+    xs, infos = qrx.lstsq_batched([dev(p.A) for p in probs], [dev64(p.b) for p in probs],
+                                  prec=prec, tol=1e-10, max_iter=400)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for p, x, info in zip(probs, xs, infos):
+        xh = host(x)
+        assert info["status"] == 0, (p.A.shape, info)
+        eta = M.eta_F(p.A, p.b, xh)
+        worst = max(worst, eta)
+        assert eta <= 1.05e-10, (p.A.shape, eta, info)
+        assert abs(info["eta_F"] - eta) <= 0.05 * eta + 1e-13
+        xo, _, _ = L.lls_direct(p.A, p.b)
+        # a 1e-10 backward error bounds the forward error by cond * 1e-10 (columns
+        # scaled by up to 1e4 relative to each other)
+        kappa = np.linalg.cond(p.A.astype(np.float64))
+        assert M.forward_error(xh, xo) <= max(1e-8, 10 * kappa * 1e-10), p.A.shape
+    print(f"{prec}: worst eta_F {worst:.2e}, iters {[i['iters'] for i in infos[:8]]}")
+
+
+def test_batched_lls_deterministic_and_ragged(qrx):
+    import torch
+    g = np.random.default_rng(13)
+    mats, rhs = [], []
+    for m, n in ((33, 33), (65, 7), (700, 250), (129, 64)):
+        A = _matrix(g, m, n, scale=False)
+        _, b = synth.lls_problem(g, A, "rel1e-6")
+        mats.append(A)
+        rhs.append(b)
+    r1 = qrx.lstsq_batched([dev(A) for A in mats], [dev64(b) for b in rhs], prec="bf16")
+    r2 = qrx.lstsq_batched([dev(A) for A in mats], [dev64(b) for b in rhs], prec="bf16")
+    torch.cuda.synchronize()
+    for A, b, x1, x2, info in zip(mats, rhs, r1[0], r2[0], r1[1]):
+        assert np.array_equal(host(x1), host(x2))
+        assert info["status"] == 0
+        assert M.eta_F(A, b, host(x1)) <= 1.05e-10
