@@ -159,7 +159,9 @@ class Handle:
         rhs = [b.contiguous() for b in rhs]
         k = len(mats)
         m, n, lda = self._arrays(mats)
-        xs = [torch.zeros(int(a.shape[1]), dtype=torch.float64, device=a.device) for a in mats]
+        ns = [int(a.shape[1]) for a in mats]
+        flat = torch.zeros(sum(ns), dtype=torch.float64, device=mats[0].device)
+        xs = list(torch.split(flat, ns))
         Ap = (C.c_void_p * k)(*[a.data_ptr() for a in mats])
         bp = (C.c_void_p * k)(*[b.data_ptr() for b in rhs])
         xp = (C.c_void_p * k)(*[x.data_ptr() for x in xs])

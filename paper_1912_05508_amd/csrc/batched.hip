@@ -30,12 +30,15 @@ static_assert(BT == GT && BT == gram::GT, "one workgroup shape for every phase")
 
 // LDS of the QR kernel (doubles): the panel phase needs the most.
 constexpr int kPanelLds = gram::Lds<32>::C_DOUBLES + gram::Lds<32>::X_DOUBLES +
-                          gram::Lds<32>::RED_DOUBLES + 528 + 32 * 33 + 32 * 32 + 32;
+                          gram::Lds<32>::RED_DOUBLES + 528 + 2 * 32 * 33 + 256 + 32 * 32;
 constexpr int kGemmLds = 2 * 128 * (64 + 8) * 2 / 8;   // two 128 x (BK+PAD) 16-bit tiles
 static_assert(2 * 128 * (32 + 4) * 4 / 8 <= kGemmLds, "FP32 tiles fit");
 constexpr int kBqrLds = kPanelLds > kGemmLds ? kPanelLds : kGemmLds;
 
 QRX_DEV bool al16(const void *p) { return (((uintptr_t)p) & 15) == 0; }
+
+// Second panel sweep skipped when Q1^T Q1 is within this of I in every entry.
+constexpr double kBSkipTau = 1.0 / (1 << 21);
 
 // Sum over the workgroup (fixed order); every thread gets the result.
 QRX_DEV double bsum(double v, double *sh) {
@@ -170,12 +173,13 @@ QRX_DEV void wg_panel(float *P, int64_t ld, int64_t m, int w, float *Rb, int64_t
                       int t) {
     using L = gram::Lds<32>;
     double *C = lds;
-    double *Xs = C + L::C_DOUBLES;
+    double *Xs = C + L::C_DOUBLES;          // X row-major for the sweeps
     double *red = Xs + L::X_DOUBLES;
     double *Gl = red + L::RED_DOUBLES;
-    double *S = Gl + 528;
-    double *R1 = S + 32 * 33;
-    double *dg = R1 + 32 * 32;
+    double *S = Gl + 528;                   // G, then R (column-major, stride 33)
+    double *Xc = S + 32 * 33;               // R^{-1} (column-major, stride 33)
+    double *T = Xc + 32 * 33;               // block scratch of the inverse
+    double *R1 = T + 256;                   // first-sweep R
     const int64_t nch = (m + gram::CH - 1) / gram::CH;
     double acc[4][4];
     auto zero = [&]() {
@@ -184,13 +188,17 @@ QRX_DEV void wg_panel(float *P, int64_t ld, int64_t m, int w, float *Rb, int64_t
 #pragma unroll
             for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
     };
-    auto factor = [&]() {   // Gl -> S -> elimination
+    auto factor = [&]() {   // Gl -> S -> R, Xc; X into the sweep layout
         for (int idx = t; idx < 32 * 32; idx += BT) {
             const int i = idx % 32, j = idx / 32;
             S[i + j * 33] = (i <= j && j < w) ? Gl[gram::upk(i, j)] : 0.0;
         }
         __syncthreads();
-        gram::chol_elim<32, BT>(S, dg, w, t);
+        gram::chol_blocked<32, BT>(S, Xc, T, t);
+        for (int idx = t; idx < 32 * 32; idx += BT) {
+            const int i = idx % 32, j = idx / 32;
+            Xs[i * L::XLD + j] = (i <= j && j < w) ? Xc[i + j * 33] : 0.0;
+        }
     };
     zero();
     gram::sweep<32, false, true>(P, ld, m, w, 0, nch, Xs, C, acc, t);
@@ -199,26 +207,40 @@ QRX_DEV void wg_panel(float *P, int64_t ld, int64_t m, int w, float *Rb, int64_t
     factor();
     for (int idx = t; idx < 32 * 32; idx += BT) {
         const int i = idx % 32, j = idx / 32;
-        Xs[i * L::XLD + j] = gram::chol_X<32>(S, dg, w, i, j);
-        R1[idx] = gram::chol_R<32>(S, dg, w, i, j);
+        R1[idx] = (i <= j && j < w) ? S[i + j * 33] : 0.0;
     }
     zero();
     gram::sweep<32, true, true>(P, ld, m, w, 0, nch, Xs, C, acc, t);
     gram::gram_store<32>(acc, red, Gl, t);
     __syncthreads();
+    // Q1 already orthonormal to working accuracy: R = R1, no second factorisation
+    double dev = 0.0;
+    for (int idx = t; idx < 528; idx += BT) {
+        int j = 0;
+        while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+        const int i = idx - j * (j + 1) / 2;
+        if (j < w) {
+            const double e2 = fabs(Gl[idx] - (i == j ? 1.0 : 0.0));
+            dev = fmax(dev, (e2 == e2) ? e2 : 1e300);
+        }
+    }
+    if (bmax(dev, T) <= kBSkipTau) {
+        for (int idx = t; idx < 32 * 32; idx += BT) {
+            const int i = idx % 32, j = idx / 32;
+            if (i < w && j < w) Rb[i + (int64_t)j * ldr] = (float)R1[idx];
+        }
+        __syncthreads();
+        return;
+    }
     factor();
-    // R = R2 R1 into the diagonal block; X2 into Xs for the final sweep
+    // R = R2 R1 into the diagonal block (R2 in S, both upper triangular)
     for (int idx = t; idx < 32 * 32; idx += BT) {
         const int i = idx % 32, j = idx / 32;
         if (i < w && j < w) {
             double v = 0.0;
-            if (i <= j) {
-                for (int l = i; l <= j; ++l) v = fma(S[i + l * 33], R1[l + j * 32], v);
-                v *= dg[i];
-            }
+            for (int l = i; l <= j; ++l) v = fma(S[i + l * 33], R1[l + j * 32], v);
             Rb[i + (int64_t)j * ldr] = (float)v;
         }
-        Xs[i * L::XLD + j] = gram::chol_X<32>(S, dg, w, i, j);
     }
     gram::sweep<32, true, false>(P, ld, m, w, 0, nch, Xs, C, acc, t);
     __syncthreads();

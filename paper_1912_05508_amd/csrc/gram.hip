@@ -32,7 +32,7 @@ using gram::CH;
 using gram::GT;
 using gram::upk;
 constexpr int CT = 512;          // threads per reduce/Cholesky workgroup
-constexpr int kMaxParts = 256;   // Gram partials (one per sweep workgroup)
+constexpr int kMaxParts = 512;   // Gram partials (one per sweep workgroup)
 
 // One sweep over this workgroup's row chunks of P (m x w, column-major, ld).
 // DO_Q: rows <- fl32(rows X) with X upper triangular (W x W, FP64, column-
@@ -41,7 +41,9 @@ template <int W, bool DO_Q, bool DO_G>
 __global__ __launch_bounds__(GT) void gram_pass_kernel(float *__restrict__ P, int64_t ld,
                                                        int64_t m, int w, int64_t chunks_per,
                                                        const double *__restrict__ X,
-                                                       double *__restrict__ part) {
+                                                       double *__restrict__ part,
+                                                       const int *__restrict__ skip) {
+    if (skip && *skip) return;   // the first sweep already gave an orthonormal Q
     using L = gram::Lds<W>;
     __shared__ __align__(16) double C[L::C_DOUBLES];
     __shared__ __align__(16) double Xs[DO_Q ? L::X_DOUBLES : 2];
@@ -64,9 +66,13 @@ __global__ __launch_bounds__(GT) void gram_pass_kernel(float *__restrict__ P, in
 // G[e] = sum over the partials: a workgroup owns 64 entries (one per lane),
 // its 8 waves sum interleaved subsets of the partials and the 8 sums are added
 // in a fixed order (deterministic). The last workgroup to finish then factors
-// G = R^T R by gram::chol_elim and writes R and X = R^{-1} (FP64, W x W,
+// G = R^T R with gram::chol_blocked and writes R and X = R^{-1} (FP64, W x W,
 // column-major). If Rfinal is set, it also writes the panel's R block (FP32,
 // ldr): R Rprev when Rprev is set, else R.
+// With skip set (second sweep: G is the Gram matrix of the rounded Q1), a G
+// within tau of the identity in every entry means Q1 is already orthonormal
+// to working accuracy: then R = Rprev is written, *skip = 1 and the final
+// sweep does nothing; otherwise *skip = 0 and the factorisation proceeds.
 // *counter must be 0 on entry; the last workgroup leaves it 0.
 template <int W>
 __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict__ part, int nparts,
@@ -75,29 +81,41 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
                                                        double *__restrict__ Rout,
                                                        double *__restrict__ Xout,
                                                        const double *__restrict__ Rprev,
-                                                       float *__restrict__ Rfinal, int64_t ldr) {
+                                                       float *__restrict__ Rfinal, int64_t ldr,
+                                                       int *__restrict__ skip, double tau) {
     constexpr int NP = W * (W + 1) / 2;
     constexpr int LS = W + 1;
     constexpr int NW = CT / 64;
-    __shared__ double S[W * LS];
-    __shared__ double Rp[W * W];        // Rprev
-    __shared__ double sums[NW * 64];
-    __shared__ double dg[W];
+    constexpr int U = (NW * 64 > (W / 16 - 1) * 256) ? NW * 64 : (W / 16 - 1) * 256;   // >= 16
+    __shared__ double S[W * LS];       // G, then R (upper)
+    __shared__ double Xs[W * LS];      // R^{-1}, then Rprev
+    __shared__ double Ub[U];           // partial sums, then block scratch of the inverse
     __shared__ int last;
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
     const int e = blockIdx.x * 64 + lane;
     {
+        // wave wv sums partials wv, wv + NW, ...: eight loads in flight per step,
+        // added in a fixed order
         double s = 0.0;
-        if (e < NP)
-            for (int b = wv; b < nparts; b += NW) s += part[(int64_t)b * NP + e];
-        sums[wv * 64 + lane] = s;
+        if (e < NP) {
+            int b = wv;
+            for (; b + 7 * NW < nparts; b += 8 * NW) {
+                double v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(b + q * NW) * NP + e];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) s += v[q];
+            }
+            for (; b < nparts; b += NW) s += part[(int64_t)b * NP + e];
+        }
+        Ub[wv * 64 + lane] = s;
     }
     __syncthreads();
     if (wv == 0 && e < NP) {
-        double s = sums[lane];
+        double s = Ub[lane];
 #pragma unroll
-        for (int q = 1; q < NW; ++q) s += sums[q * 64 + lane];
+        for (int q = 1; q < NW; ++q) s += Ub[q * 64 + lane];
         G[e] = s;
     }
     __threadfence();
@@ -108,33 +126,81 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
     __threadfence();
     if (t == 0) atomicExch(counter, 0);
 
+    double dev = 0.0;
     for (int idx = t; idx < W * W; idx += CT) {
         const int i = idx % W, j = idx / W;
-        S[i + j * LS] = (i <= j && j < w) ? G[upk(i, j)] : 0.0;
-        if (Rprev) Rp[idx] = Rprev[idx];
+        const double g = (i <= j && j < w) ? G[upk(i, j)] : 0.0;
+        S[i + j * LS] = g;
+        if (i <= j && j < w) {
+            const double e2 = fabs(g - (i == j ? 1.0 : 0.0));
+            dev = fmax(dev, (e2 == e2) ? e2 : 1e300);   // a NaN entry never passes
+        }
+    }
+    if (skip) {
+        // max |G - I| over the workgroup (fixed reduction; the flag is uniform)
+#pragma unroll
+        for (int o2 = 32; o2 > 0; o2 >>= 1) dev = fmax(dev, __shfl_xor(dev, o2));
+        if (lane == 0) Ub[wv] = dev;
+        __syncthreads();
+        double mx = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) mx = fmax(mx, Ub[q]);
+        const bool done = mx <= tau;   // NaN compares false: factorise
+        if (t == 0) *skip = done ? 1 : 0;
+        if (done) {
+            for (int idx = t; idx < W * W; idx += CT) {
+                const int i = idx % W, j = idx / W;
+                if (i < w && j < w) Rfinal[i + (int64_t)j * ldr] = (float)Rprev[idx];
+            }
+            return;
+        }
     }
     __syncthreads();
-    gram::chol_elim<W, CT>(S, dg, w, t);
+    gram::chol_blocked<W, CT>(S, Xs, Ub, t);
     for (int idx = t; idx < W * W; idx += CT) {
         const int i = idx % W, j = idx / W;
-        Rout[idx] = gram::chol_R<W>(S, dg, w, i, j);
-        Xout[idx] = gram::chol_X<W>(S, dg, w, i, j);
+        const bool up = i <= j && j < w;
+        Rout[idx] = up ? S[i + j * LS] : 0.0;
+        Xout[idx] = up ? Xs[i + j * LS] : 0.0;
     }
-    if (Rfinal) {
-        for (int idx = t; idx < W * W; idx += CT) {
-            const int i = idx % W, j = idx / W;
-            if (i >= w || j >= w) continue;
-            double v = 0.0;
-            if (i <= j) {
-                if (Rprev) {
-                    for (int l = i; l <= j; ++l) v = fma(S[i + l * LS], Rp[l + j * W], v);
-                    v *= dg[i];
-                } else {
-                    v = S[i + j * LS] * dg[i];
+    if (!Rfinal) return;
+    if (Rprev) {
+        __syncthreads();
+        for (int idx = t; idx < W * W; idx += CT) Xs[(idx % W) + (idx / W) * LS] = Rprev[idx];
+        __syncthreads();
+    }
+    // R (or R Rprev) in 2 x 4 tiles; the lower parts of S and Rprev are zero
+    for (int tile = t; tile < (W / 2) * (W / 4); tile += CT) {
+        const int i0 = 2 * (tile % (W / 2)), j0 = 4 * (tile / (W / 2));
+        double v[2][4];
+#pragma unroll
+        for (int p2 = 0; p2 < 2; ++p2)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[p2][q] = 0.0;
+        if (Rprev) {
+            for (int l = i0; l <= j0 + 3; ++l) {
+                const double a0 = S[i0 + l * LS], a1 = S[i0 + 1 + l * LS];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double bq = Xs[l + (j0 + q) * LS];
+                    v[0][q] = fma(a0, bq, v[0][q]);
+                    v[1][q] = fma(a1, bq, v[1][q]);
                 }
             }
-            Rfinal[i + (int64_t)j * ldr] = (float)v;
+        } else {
+#pragma unroll
+            for (int p2 = 0; p2 < 2; ++p2)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    v[p2][q] = (i0 + p2 <= j0 + q) ? S[(i0 + p2) + (j0 + q) * LS] : 0.0;
         }
+#pragma unroll
+        for (int p2 = 0; p2 < 2; ++p2)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + p2, j = j0 + q;
+                if (i < w && j < w) Rfinal[i + (int64_t)j * ldr] = (float)v[p2][q];
+            }
     }
 }
 
@@ -155,7 +221,8 @@ static GramSplit gram_split(int64_t m) {
 }
 
 // Workspace (doubles): parts * W(W+1)/2 + W(W+1)/2 + 4 W^2, then one double
-// whose first word is the completion counter of gram_chol.
+// holding two ints: the completion counter of gram_chol and the skip flag of
+// the second sweep.
 size_t gram_workspace_doubles(int64_t m, int W) {
     const size_t np = (size_t)W * (W + 1) / 2;
     return (size_t)gram_split(m).parts * np + np + 4 * (size_t)W * W + 1;
@@ -164,6 +231,10 @@ size_t gram_workspace_doubles(int64_t m, int W) {
 int *gram_counter(double *ws, int64_t m) {
     return reinterpret_cast<int *>(ws + gram_workspace_doubles(m, 64) - 1);
 }
+
+// Re-orthogonalisation is skipped when every entry of Q1^T Q1 is within this
+// of the identity (a few FP32 rounding units: a second sweep could not do better).
+constexpr double kSkipTau = 1.0 / (1 << 21);
 
 template <int W>
 static hipError_t gram_go(hipStream_t s, float *P, int64_t ld, int64_t m, int w, float *R,
@@ -177,23 +248,27 @@ static hipError_t gram_go(hipStream_t s, float *P, int64_t ld, int64_t m, int w,
     double *R2 = X1 + W * W;
     double *X2 = R2 + W * W;
     int *counter = gram_counter(ws, m);
+    int *skip = counter + 1;
     const unsigned cb = (unsigned)((np + 63) / 64);
+    const int *noskip = nullptr;
     hipLaunchKernelGGL((gram_pass_kernel<W, false, true>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
-                       m, w, sp.chunks_per, (const double *)nullptr, part);
+                       m, w, sp.chunks_per, (const double *)nullptr, part, noskip);
     hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(cb), dim3(CT), 0, s, (const double *)part,
                        sp.parts, w, G, counter, R1, X1, (const double *)nullptr,
-                       reorth ? (float *)nullptr : R, ldr);
+                       reorth ? (float *)nullptr : R, ldr, (int *)nullptr, 0.0);
     if (!reorth) {
         hipLaunchKernelGGL((gram_pass_kernel<W, true, false>), dim3(sp.parts), dim3(GT), 0, s, P,
-                           ld, m, w, sp.chunks_per, (const double *)X1, (double *)nullptr);
+                           ld, m, w, sp.chunks_per, (const double *)X1, (double *)nullptr, noskip);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((gram_pass_kernel<W, true, true>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
-                       m, w, sp.chunks_per, (const double *)X1, part);
+                       m, w, sp.chunks_per, (const double *)X1, part, noskip);
     hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(cb), dim3(CT), 0, s, (const double *)part,
-                       sp.parts, w, G, counter, R2, X2, (const double *)R1, R, ldr);
+                       sp.parts, w, G, counter, R2, X2, (const double *)R1, R, ldr, skip,
+                       kSkipTau);
     hipLaunchKernelGGL((gram_pass_kernel<W, true, false>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
-                       m, w, sp.chunks_per, (const double *)X2, (double *)nullptr);
+                       m, w, sp.chunks_per, (const double *)X2, (double *)nullptr,
+                       (const int *)skip);
     return hipGetLastError();
 }
 

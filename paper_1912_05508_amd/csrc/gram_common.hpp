@@ -160,59 +160,151 @@ QRX_DEV void gram_store(double (&acc)[4][4], double *red, double *out, int t) {
     }
 }
 
-// Symmetric elimination of [G | I] in S (W x W, S[i + j*(W+1)], upper triangle
-// holding G on entry) by NT threads: step k subtracts multiples of row k from
-// the rows below it, leaving U = D L^T in the upper triangle and L^{-1} (unit
-// lower) strictly below, so R = D^{-1/2} U and R^{-1} = L^{-T} D^{-1/2}.
-// dg[k] = D_kk^{-1/2} (0 for a pivot <= 0: that row of R and column of R^{-1}
-// are zero). Ends with a barrier.
+// ---------------------------------------------------------------------------
+// Blocked Cholesky with the inverse of the factor, for W a multiple of 16:
+// G = R^T R (R upper, R_kk > 0) and X = R^{-1}, both FP64 in LDS (column-
+// major, stride W + 1). On entry S holds G in its upper triangle (zero beyond
+// w); on exit S holds R in its upper triangle and Xs holds X (zero below the
+// diagonal). A pivot <= 0 gives a zero row of R and a zero column of X.
+// Per 16-column block: one wave factors the diagonal block and inverts it in
+// registers (column per lane, values exchanged by cross-lane shuffles), then
+// all threads form the block row of R and update the trailing matrix; the
+// off-diagonal blocks of X follow by block products ordered by their distance
+// from the diagonal. T is LDS scratch of max(16, (W/16 - 1) * 256) doubles.
+// ---------------------------------------------------------------------------
+// v in lane l, as a wave-uniform value (two v_readlane).
+QRX_DEV double readlane_d(double v, int l) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)bits, l);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 1 / sqrt(d) for d > 0: hardware estimate plus one Newton step.
+QRX_DEV double rsqrt_d(double d) {
+    double y = __builtin_amdgcn_rsq(d);
+    return y * fma(-0.5 * d * y, y, 1.5);
+}
+
+// One wave: Cholesky of the 16 x 16 block at (o, o) of S (upper triangle,
+// updated in place to R) and its inverse into Xs. Lane j < 16 keeps column j
+// in registers; the entries of the pivot row are read from their lanes with
+// v_readlane. Lanes 16..63 compute copies and write nothing.
+template <int LS>
+QRX_DEV void diag16(double *S, double *Xs, int o, int lane) {
+    const int j = lane & 15;
+    const bool own = lane < 16;
+    double col[16], x[16], rdi[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) col[i] = (i <= j) ? S[(o + i) + (o + j) * LS] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const double d = readlane_d(col[k], k);      // G'[k][k]
+        const double rinv = (d > 0.0) ? rsqrt_d(d) : 0.0;
+        rdi[k] = rinv;                               // 1 / R[k][k] (0 for a bad pivot)
+        const double rkj = (j >= k) ? col[k] * rinv : 0.0;
+#pragma unroll
+        for (int i = k + 1; i < 16; ++i) {
+            const double rki = readlane_d(col[k], i) * rinv;   // R[k][i]
+            if (i <= j) col[i] = fma(-rki, rkj, col[i]);
+        }
+        col[k] = rkj;                                // R[k][j]
+    }
+    // column j of X: R x = e_j by back substitution
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+        double acc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int l = i + 1; l < 16; ++l) acc = fma(-readlane_d(col[i], l), x[l], acc);
+        x[i] = (i <= j) ? acc * rdi[i] : 0.0;
+    }
+    if (own) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i <= j) S[(o + i) + (o + j) * LS] = col[i];
+            Xs[(o + i) + (o + j) * LS] = x[i];
+        }
+    }
+}
+
 template <int W, int NT>
-QRX_DEV void chol_elim(double *S, double *dg, int w, int t) {
+QRX_DEV void chol_blocked(double *S, double *Xs, double *T, int t) {
     constexpr int LS = W + 1;
-    constexpr int NG = (NT / W < W) ? NT / W : W;   // column groups per row
-    constexpr int QN = W / NG;
-    static_assert(NT % W == 0 && W % NG == 0, "elimination mapping");
-    const int ri = t % W, rg = t / W;
-    for (int k = 0; k < w; ++k) {
-        const double d = S[k + k * LS];
-        if (d > 0.0 && rg < NG && ri > k) {
-            // row ri of [U | L^{-1}] -= l * row k, on the L^{-1} part (c <= k) and the
-            // U part (c >= ri); all reads first, then branch-free selects
-            const double l = S[k + ri * LS] / d;
-            double rk[QN], mine[QN];
+    constexpr int NB = W / 16;
+    constexpr int PV = (16 * (W - 16) + NT - 1) / NT;     // panel entries per thread
+    static_assert(W % 16 == 0 && NT >= 64, "blocked Cholesky shape");
+    // zero the strictly-lower part of Xs (the blocks below the diagonal stay zero)
+    for (int idx = t; idx < W * W; idx += NT) {
+        const int i = idx % W, jj = idx / W;
+        if (i > jj) Xs[i + jj * LS] = 0.0;
+    }
+    for (int K = 0; K < NB; ++K) {
+        const int o = 16 * K, rest = W - o - 16;
+        if (t < 64) diag16<LS>(S, Xs, o, t);
+        __syncthreads();
+        if (rest > 0) {
+            // block row of R: R[o+i][c] = sum_{l <= i} X_KK[l][i] G'[o+l][c]
+            double v[PV > 0 ? PV : 1];
 #pragma unroll
-            for (int q = 0; q < QN; ++q) {
-                const int c = rg + NG * q;
-                rk[q] = S[k + c * LS];
-                mine[q] = S[ri + c * LS];
+            for (int q = 0; q < PV; ++q) {
+                const int idx = t + q * NT;
+                v[q] = 0.0;
+                if (idx < 16 * rest) {
+                    const int i = idx % 16, c = o + 16 + idx / 16;
+                    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int l = 0; l < 16; ++l)   // X_KK[l][i] = 0 for l > i
+                        a4[l & 3] = fma(Xs[(o + l) + (o + i) * LS], S[(o + l) + c * LS], a4[l & 3]);
+                    v[q] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+                }
             }
+            __syncthreads();
 #pragma unroll
-            for (int q = 0; q < QN; ++q) {
-                const int c = rg + NG * q;
-                const double coef = (c == k) ? 1.0 : rk[q];
-                mine[q] = (c <= k || c >= ri) ? fma(-l, coef, mine[q]) : mine[q];
+            for (int q = 0; q < PV; ++q) {
+                const int idx = t + q * NT;
+                if (idx < 16 * rest) S[(o + idx % 16) + (o + 16 + idx / 16) * LS] = v[q];
             }
+            __syncthreads();
+            // trailing update: G'[a][b] -= sum_i R[o+i][a] R[o+i][b], a <= b in the rest
+            for (int idx = t; idx < rest * rest; idx += NT) {
+                const int a = o + 16 + idx % rest, b = o + 16 + idx / rest;
+                if (a <= b) {
+                    double a4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int q = 0; q < QN; ++q) S[ri + (rg + NG * q) * LS] = mine[q];
+                    for (int i = 0; i < 16; ++i)
+                        a4[i & 3] = fma(S[(o + i) + a * LS], S[(o + i) + b * LS], a4[i & 3]);
+                    S[a + b * LS] -= (a4[0] + a4[1]) + (a4[2] + a4[3]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // off-diagonal blocks of X: X_IJ = -X_II sum_{L=I+1..J} R_IL X_LJ, by distance
+    for (int d = 1; d < NB; ++d) {
+        const int nblk = NB - d;
+        for (int idx = t; idx < nblk * 256; idx += NT) {
+            const int I = idx / 256, p = (idx % 256) % 16, q = (idx % 256) / 16;
+            const int J = I + d;
+            double a4[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int r = 16 * (I + 1); r <= 16 * J + 15; r += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    a4[u] = fma(S[(16 * I + p) + (r + u) * LS], Xs[(r + u) + (16 * J + q) * LS], a4[u]);
+            }
+            T[idx] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+        }
+        __syncthreads();
+        for (int idx = t; idx < nblk * 256; idx += NT) {
+            const int I = idx / 256, p = (idx % 256) % 16, q = (idx % 256) / 16;
+            const int J = I + d;
+            double a4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2)   // X_II[p][s2] = 0 for s2 < p
+                a4[s2 & 3] = fma(Xs[(16 * I + p) + (16 * I + s2) * LS], T[I * 256 + q * 16 + s2], a4[s2 & 3]);
+            Xs[(16 * I + p) + (16 * J + q) * LS] = -((a4[0] + a4[1]) + (a4[2] + a4[3]));
         }
         __syncthreads();
     }
-    if (t < W) {
-        const double d = (t < w) ? S[t + t * LS] : 0.0;
-        dg[t] = (d > 0.0) ? 1.0 / sqrt(d) : 0.0;
-    }
-    __syncthreads();
-}
-
-// R[i][j] = U[i][j] D_i^{-1/2} and X = R^{-1}[i][j] = Linv[j][i] D_j^{-1/2} (i <= j),
-// zero elsewhere and beyond w.
-template <int W>
-QRX_DEV double chol_R(const double *S, const double *dg, int w, int i, int j) {
-    return (i <= j && j < w) ? S[i + j * (W + 1)] * dg[i] : 0.0;
-}
-template <int W>
-QRX_DEV double chol_X(const double *S, const double *dg, int w, int i, int j) {
-    return (i <= j && j < w) ? ((i == j) ? 1.0 : S[j + i * (W + 1)]) * dg[j] : 0.0;
 }
 
 }  // namespace gram

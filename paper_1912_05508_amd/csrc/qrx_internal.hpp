@@ -41,13 +41,17 @@ QRX_DEV float wave_max_f(float v) {
     return v;
 }
 
-// Error-free transformations for double-double accumulation.
+// Error-free transformations for double-double accumulation. Contraction is
+// off inside them: fusing a product into a following sum (hi + a*b -> one
+// FMA) would break the exact-error identities they rely on.
 QRX_DEV void two_sum(double a, double b, double &s, double &e) {
+#pragma clang fp contract(off)
     s = a + b;
     double bb = s - a;
     e = (a - (s - bb)) + (b - bb);
 }
 QRX_DEV void dd_add(double &hi, double &lo, double v) {   // (hi, lo) += v
+#pragma clang fp contract(off)
     double s, e;
     two_sum(hi, v, s, e);
     e += lo;
@@ -55,8 +59,9 @@ QRX_DEV void dd_add(double &hi, double &lo, double v) {   // (hi, lo) += v
     lo = e - (hi - s);
 }
 QRX_DEV void dd_add_prod(double &hi, double &lo, double a, double b) {  // += a*b exactly-ish
-    double p = a * b;
-    double pe = fma(a, b, -p);
+#pragma clang fp contract(off)
+    const double p = a * b;
+    const double pe = fma(a, b, -p);
     dd_add(hi, lo, p);
     lo += pe;
 }

@@ -254,3 +254,38 @@ def batched_problems(count: int = 4096, seed: int = 0, nmin_j: int = 4,
         x, b = lls_problem(g, A, "rel1e-6")
         out.append(Problem(A=A, b=b, x_star=x, meta=dict(m=m, n=n)))
     return out
+
+
+def batched_sizes(count: int = 4096, seed: int = 0, nmin_j: int = 4, nmax_j: int = 32,
+                  kmin: int = 4, kmax: int = 16):
+    """The (m, n) list of the uneven batch: n = 8 j, j ~ U{nmin_j..nmax_j}, m = n k,
+    k ~ U{kmin..kmax} (drawn in that order per problem)."""
+    g = rng(seed)
+    out = []
+    for _ in range(count):
+        j = int(g.integers(nmin_j, nmax_j + 1))
+        k = int(g.integers(kmin, kmax + 1))
+        out.append((8 * j * k, 8 * j))
+    return out
+
+
+def batched_problems_device(count: int = 4096, seed: int = 0, device: str = "cuda", **kw):
+    """The batched recipe drawn on the device (torch's seeded generator) for the
+    full-size workload: sizes from ``batched_sizes``; A ~ N(0,1) with columns
+    scaled by 10^U[-2,2] (column-major FP32); x* ~ N(0,1); b = A x* + 1e-6
+    (||A x*|| / sqrt(m)) g in FP64. Returns (list of A, list of b)."""
+    import torch
+    sizes = batched_sizes(count, seed, **kw)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    mats, rhs = [], []
+    for m, n in sizes:
+        A = torch.randn((n, m), generator=gen, device=device, dtype=torch.float32).t()
+        A.mul_(10.0 ** (torch.rand(n, generator=gen, device=device, dtype=torch.float32) * 4 - 2))
+        x = torch.randn(n, generator=gen, device=device, dtype=torch.float64)
+        g = torch.randn(m, generator=gen, device=device, dtype=torch.float64)
+        Ax = A.double() @ x
+        b = Ax + 1e-6 * (Ax.norm() / math.sqrt(m)) * g
+        mats.append(A)
+        rhs.append(b.contiguous())
+    return mats, rhs
