@@ -178,7 +178,7 @@ void carve_qr(Carve &cv, int64_t m, int64_t n, const QrCfg &c, const std::vector
     size_t part = 1;
     for (const Op &o : ops)
         if (o.kind == 1) {
-            const size_t s = projection_splits(m, o.k, o.n2);
+            const size_t s = projection_splits(m, o.k, o.n2, o.prec);
             part = std::max(part, s * (size_t)o.k * (size_t)o.n2);
         }
     w.part = cv.take<float>(part);
@@ -303,7 +303,7 @@ int run_qr(qrx_handle h, hipStream_t s, int64_t m, int64_t n, float *W, int64_t 
             float *A2 = W + (o.c0 + o.k) * ldw;
             float *R12 = R + o.c0 + (o.c0 + o.k) * ldr;
             float *cm = ws.colmax + o.c0 + o.k;
-            const int splits = projection_splits(m, o.k, o.n2);
+            const int splits = projection_splits(m, o.k, o.n2, o.prec);
             // column max-abs of the updated A2 is read later only by scaled low-precision
             // projections inside A2 (width > cutoff) and by the TSQR panel's scaling
             float *cm_out = (c.alg == 1 || (o.n2 > c.c && o.prec != QRX_FP32 && c.scaling)) ? cm

@@ -371,8 +371,8 @@ hipError_t launch_projection_lp(hipStream_t s, int prec, int scaling, int64_t m,
                                 const float *A2, int64_t lda, const float *colmax, float *part,
                                 int splits) {
     switch (prec) {
-        case QRX_FP16: return projlp_dispatch<PF16>(s, m, k, n2, qc, qcl, ldc, A2, lda, colmax, part, splits, scaling);
-        case QRX_BF16: return projlp_dispatch<PBF16>(s, m, k, n2, qc, qcl, ldc, A2, lda, colmax, part, splits, scaling);
+        case QRX_FP16: return projlp_dispatch<PF16K32>(s, m, k, n2, qc, qcl, ldc, A2, lda, colmax, part, splits, scaling);
+        case QRX_BF16: return projlp_dispatch<PBF16K32>(s, m, k, n2, qc, qcl, ldc, A2, lda, colmax, part, splits, scaling);
         case QRX_FP16X3: return projlp_dispatch<PF16X3>(s, m, k, n2, qc, qcl, ldc, A2, lda, colmax, part, splits, scaling);
         default: return hipErrorInvalidValue;
     }
@@ -406,19 +406,12 @@ static hipError_t updlp_dispatch(hipStream_t s, int64_t m, int64_t k, int64_t n2
                                  const uint16_t *rh, const uint16_t *rhl, int64_t ldh, float *A2,
                                  int64_t lda, const float *uscale, float *colmax, float *cmpart,
                                  int scaling) {
-    if constexpr (Tr::SPLIT) {
-        if (n2 > 64)
-            return updlp_go<Tr, 128, 128, 2, 2>(s, m, k, n2, qr, qrl, ldq, rh, rhl, ldh, A2, lda,
-                                                uscale, colmax, cmpart, scaling);
-        return updlp_go<Tr, 128, 64, 2, 1>(s, m, k, n2, qr, qrl, ldq, rh, rhl, ldh, A2, lda,
-                                           uscale, colmax, cmpart, scaling);
-    } else {
-        if (n2 > 64)
-            return updlp_go<Tr, 256, 128, 2, 2>(s, m, k, n2, qr, qrl, ldq, rh, rhl, ldh, A2, lda,
-                                                uscale, colmax, cmpart, scaling);
-        return updlp_go<Tr, 256, 64, 4, 1>(s, m, k, n2, qr, qrl, ldq, rh, rhl, ldh, A2, lda,
-                                           uscale, colmax, cmpart, scaling);
-    }
+    // 128 x 128 tiles measured fastest for the large nodes
+    if (n2 > 64)
+        return updlp_go<Tr, 128, 128, 2, 2>(s, m, k, n2, qr, qrl, ldq, rh, rhl, ldh, A2, lda,
+                                            uscale, colmax, cmpart, scaling);
+    return updlp_go<Tr, 128, 64, 2, 1>(s, m, k, n2, qr, qrl, ldq, rh, rhl, ldh, A2, lda, uscale,
+                                       colmax, cmpart, scaling);
 }
 
 hipError_t launch_update_lp(hipStream_t s, int prec, int scaling, int64_t m, int64_t k,
@@ -426,8 +419,8 @@ hipError_t launch_update_lp(hipStream_t s, int prec, int scaling, int64_t m, int
                             const uint16_t *rh, const uint16_t *rhl, int64_t ldh, float *A2,
                             int64_t lda, const float *uscale, float *colmax, float *cmpart) {
     switch (prec) {
-        case QRX_FP16: return updlp_dispatch<PF16>(s, m, k, n2, qr, qrl, ldq, rh, rhl, ldh, A2, lda, uscale, colmax, cmpart, scaling);
-        case QRX_BF16: return updlp_dispatch<PBF16>(s, m, k, n2, qr, qrl, ldq, rh, rhl, ldh, A2, lda, uscale, colmax, cmpart, scaling);
+        case QRX_FP16: return updlp_dispatch<PF16K32>(s, m, k, n2, qr, qrl, ldq, rh, rhl, ldh, A2, lda, uscale, colmax, cmpart, scaling);
+        case QRX_BF16: return updlp_dispatch<PBF16K32>(s, m, k, n2, qr, qrl, ldq, rh, rhl, ldh, A2, lda, uscale, colmax, cmpart, scaling);
         case QRX_FP16X3: return updlp_dispatch<PF16X3>(s, m, k, n2, qr, qrl, ldq, rh, rhl, ldh, A2, lda, uscale, colmax, cmpart, scaling);
         default: return hipErrorInvalidValue;
     }

@@ -151,6 +151,6 @@ hipError_t launch_update_lp(hipStream_t s, int prec, int scaling, int64_t m, int
                             int64_t n2, const uint16_t *qr, const uint16_t *qrl, int64_t ldq,
                             const uint16_t *rh, const uint16_t *rhl, int64_t ldh, float *A2,
                             int64_t lda, const float *uscale, float *colmax, float *cmpart);
-int projection_splits(int64_t m, int64_t k, int64_t n2);
+int projection_splits(int64_t m, int64_t k, int64_t n2, int prec);
 
 }  // namespace qrx
