@@ -1,17 +1,20 @@
-"""Benchmark: mixed-precision QR (and the LLS solve) on one MI355X.
+"""Benchmark: mixed-precision QR, least squares and the batched solver on one MI355X.
 
 Step = one out-of-place QR of the 32768 x 4096 workload A = U diag(s) V^T
 (geometric spectrum, condition 1e3; FP16 MFMA trailing products with FP32
-accumulation, recursion cutoff 128, 32-column TSQR panels): the input scan,
-the whole recursion, and R finalisation. The input is resident in HBM before
-the timed region. Value = QR TFLOP/s with the Householder-equivalent count
-2 m n^2 - 2 n^3 / 3.
+accumulation, recursion cutoff 128, 64-column Cholesky-QR panels on an FP64
+Gram matrix): the input scan, the whole recursion and R finalisation. The
+input is resident in HBM before the timed region. Value = QR TFLOP/s with the
+Householder-equivalent count 2 m n^2 - 2 n^3 / 3.
 
-The same harness times the plain FP32 path (FP32 MFMA trailing products) and,
-with --lls, the least-squares time-to-1e-10 on the 65536 x 8192 workload for
-both paths. The dominant kernel's roofline figure comes from HIP events
-recorded around every launch on the launch stream during the timed region.
-The CPU baseline is the FP64 oracle timed on a bounded sample on the host.
+Legs (--legs, all by default): qr (the timed step above), fp32 (the same QR
+with FP32 MFMA products), lls (time to eta_F <= 1e-10 on the 65536 x 8192
+log-uniform workload, condition 1e6, for split-FP16, FP32 and FP16 trailing
+products), batched (4096 uneven problems in one batched call), cpu (the FP64
+oracle on a bounded sample of the QR workload, on the host cores). The
+dominant kernel's roofline figure comes from HIP events recorded around every
+launch on the launch stream during the timed region; its HBM traffic is the
+rocprofv3 counter measurement while the kernel's sources are unchanged.
 
 Prints ONE JSON line.
 """
@@ -41,6 +44,38 @@ def qr_flops(m, n):
     return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
 
 
+# HBM bytes per launch of a kernel, measured with two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE) on the 32768 x 4096 workload. On this chip
+# FETCH_SIZE reads half of a plain device copy's known size (scaled by 2) and
+# WRITE_SIZE reads it exactly (scale 1). Valid only while the kernel's sources
+# are the ones the counters were taken on (SHA-1 below); otherwise null.
+MEASURED_TRAFFIC = {
+    "gram_panel": {
+        "bytes_per_launch": 60.07e6,
+        "profile": "profiles/gram_panel_32768x4096_hbm_traffic.txt",
+        "sources": {
+            "paper_1912_05508_amd/csrc/gram.hip": "cb6cecd7d0dbb882a3d8a1492e23001c8953c46e",
+            "paper_1912_05508_amd/csrc/gram_common.hpp": "b8492c08d20bc1c535e68baca1f470c3e0889ac7",
+        },
+    },
+}
+
+
+def measured_traffic(name):
+    import hashlib
+    t = MEASURED_TRAFFIC.get(name)
+    if not t:
+        return None
+    for rel, sha in t["sources"].items():
+        try:
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha1(f.read()).hexdigest() != sha:
+                    return None
+        except OSError:
+            return None
+    return t["bytes_per_launch"]
+
+
 def kernel_bound(name):
     if name.startswith(("proj_fp16x3", "update_fp16x3")):
         return "mfma", PEAKS["fp16"] / 3.0, "TFLOP/s"
@@ -65,8 +100,11 @@ def roofline_of(stats):
         achieved = s["flops"] / (s["total_ms"] * 1e-3) / 1e12
     else:
         achieved = s["bytes"] / (s["total_ms"] * 1e-3) / 1e9
+    tr = measured_traffic(name)
     return name, {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                  "frac": achieved / peak, "traffic": None, "kernel": name,
+                  "frac": achieved / peak, "traffic": tr, "kernel": name,
+                  "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                  "algorithmic_bytes_per_launch": s["bytes"] / max(1, s["launches"]),
                   "avg_launch_ms": avg_ms, "launches": s["launches"]}
 
 
@@ -134,7 +172,7 @@ def cpu_baseline(A_host, seconds_target=15.0):
                       f"({m} x {ncols}) of the same matrix; {dt:.2f} s"}
 
 
-def lls_bench(h, prec, m_n, repeats):
+def lls_bench(h, prec, m_n, repeats, precs=("fp16x3", "fp32", "fp16")):
     import torch
     import synth
     name = "c3"
@@ -142,7 +180,8 @@ def lls_bench(h, prec, m_n, repeats):
         name, device="cuda", m=m_n[0], n=m_n[1])
     A, b = p.A, torch.as_tensor(p.b, device="cuda") if not torch.is_tensor(p.b) else p.b
     out = {}
-    for pr, reps in (("fp16x3", repeats), ("fp32", repeats), ("fp16", 1)):
+    for pr in precs:
+        reps = 1 if pr == "fp16" else repeats   # FP16 at condition 1e6: thousands of iterations
         times, infos = [], []
         for r in range(reps):
             torch.cuda.synchronize()
@@ -205,10 +244,13 @@ def main():
     ap.add_argument("--m", type=int, default=32768)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--cutoff", type=int, default=128)
-    ap.add_argument("--lls", action="store_true", help="also time the 65536 x 8192 LLS solve")
+    ap.add_argument("--lls", action="store_true", help="(kept for compatibility: lls is a default leg)")
     ap.add_argument("--lls-size", default=None, help="override the LLS workload size, e.g. 16384x2048")
+    ap.add_argument("--lls-precs", default="fp16x3,fp32,fp16")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--legs", default="qr,fp32,lls,batched,cpu",
+                    help="comma list of qr (the timed QR step), fp32, lls, batched, cpu")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-problem batched solve")
     ap.add_argument("--batched-count", type=int, default=4096)
     ap.add_argument("--copy-calib", action="store_true",
@@ -232,60 +274,77 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 x 256 MiB device-to-device copies")
         del src, dst
-    m, n = args.m, args.n
-    log(f"generating c2 workload {m} x {n} ...")
-    t0 = time.perf_counter()
-    p = synth.config_problem("c2", device="cuda", m=m, n=n)
-    A = p.A
-    torch.cuda.synchronize()
-    log(f"generated in {time.perf_counter() - t0:.1f} s")
-    Q = torch.empty((n, m), dtype=torch.float32, device=dev).t()
-    R = torch.empty((n, n), dtype=torch.float32, device=dev).t()
-    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    legs = set(args.legs.split(","))
+    if args.no_fp32:
+        legs.discard("fp32")
+    if args.no_batched:
+        legs.discard("batched")
+    if args.no_cpu:
+        legs.discard("cpu")
+    if args.lls:
+        legs.add("lls")
     h = P.Handle()
+    m, n = args.m, args.n
     flops = qr_flops(m, n)
-
-    dt, stats = time_qr(h, A, Q, R, st, args.prec, args.steps, args.warmup, args.cutoff,
-                        timing=True)
-    log(f"{args.prec} QR: {dt*1e3:.3f} ms/step, {flops/dt/1e12:.1f} TFLOP/s (timing events on)")
-    dt_clean, _ = time_qr(h, A, Q, R, st, args.prec, args.steps, 0, args.cutoff, timing=False)
-    log(f"{args.prec} QR: {dt_clean*1e3:.3f} ms/step without per-launch events")
-    status = int(st.item())
-    acc = accuracy_torch(A, Q, R)
-    acc["status"] = status
-    kname, roof = roofline_of(stats)
-    breakdown = {k: {"ms_per_step": v["total_ms"] / args.steps, "launches_per_step":
-                     v["launches"] / args.steps} for k, v in
-                 sorted(stats.items(), key=lambda kv: -kv[1]["total_ms"])}
-
     result = {
-        "metric": METRIC, "value": flops / dt_clean / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt_clean * 1e3,
+        "metric": METRIC, "value": None, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
         "data": "synthetic",
         "config": {"workload": f"c2: QR of {m} x {n} A = U diag(s) V^T, s geometric 1..1e-3 "
                                f"(seed 0); {args.prec.upper()} MFMA trailing products with FP32 "
                                f"accumulation, cutoff {args.cutoff}, 64-column panels (Cholesky QR "
-                               f"twice on an FP64 Gram matrix)",
+                               f"on an FP64 Gram matrix, re-orthogonalised when needed)",
                    "m": m, "n": n, "flops_per_step": flops, "parallelism": "single GPU"},
-        "roofline": roof,
-        "accuracy": acc,
-        "kernel_breakdown": breakdown,
     }
-    if not args.no_fp32:
+    A = None
+    if legs & {"qr", "fp32", "cpu"}:
+        log(f"generating c2 workload {m} x {n} ...")
+        t0 = time.perf_counter()
+        p = synth.config_problem("c2", device="cuda", m=m, n=n)
+        A = p.A
+        torch.cuda.synchronize()
+        log(f"generated in {time.perf_counter() - t0:.1f} s")
+        Q = torch.empty((n, m), dtype=torch.float32, device=dev).t()
+        R = torch.empty((n, n), dtype=torch.float32, device=dev).t()
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+    if "qr" in legs:
+        dt, stats = time_qr(h, A, Q, R, st, args.prec, args.steps, args.warmup, args.cutoff,
+                            timing=True)
+        log(f"{args.prec} QR: {dt*1e3:.3f} ms/step, {flops/dt/1e12:.1f} TFLOP/s (timing events on)")
+        dt_clean, _ = time_qr(h, A, Q, R, st, args.prec, args.steps, 0, args.cutoff,
+                              timing=False)
+        log(f"{args.prec} QR: {dt_clean*1e3:.3f} ms/step without per-launch events")
+        status = int(st.item())
+        acc = accuracy_torch(A, Q, R)
+        acc["status"] = status
+        _, roof = roofline_of(stats)
+        result["value"] = flops / dt_clean / 1e12
+        result["ms_per_step"] = dt_clean * 1e3
+        result["roofline"] = roof
+        result["accuracy"] = acc
+        result["kernel_breakdown"] = {
+            k: {"ms_per_step": v["total_ms"] / args.steps, "launches_per_step":
+                v["launches"] / args.steps}
+            for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["total_ms"])}
+    if "fp32" in legs:
         dt32, _ = time_qr(h, A, Q, R, st, "fp32", max(2, args.steps // 2), 1, args.cutoff)
         acc32 = accuracy_torch(A, Q, R)
         result["fp32_path"] = {"ms_per_step": dt32 * 1e3, "tflops": flops / dt32 / 1e12,
-                               "accuracy": acc32, "speedup_fp16_vs_fp32": dt32 / dt_clean}
+                               "accuracy": acc32}
+        if result["ms_per_step"]:
+            result["fp32_path"]["speedup_fp16_vs_fp32"] = dt32 * 1e3 / result["ms_per_step"]
         log(f"fp32 QR: {dt32*1e3:.3f} ms/step")
-    if args.lls:
+    if "lls" in legs:
         mn = tuple(int(v) for v in args.lls_size.split("x")) if args.lls_size else None
-        del Q
-        torch.cuda.empty_cache()
-        result["lls"] = lls_bench(h, args.prec, mn, repeats=3)
-    if not args.no_batched:
+        if A is not None:
+            del Q
+            torch.cuda.empty_cache()
+        result["lls"] = lls_bench(h, args.prec, mn, repeats=3,
+                                  precs=tuple(args.lls_precs.split(",")))
+    if "batched" in legs:
         result["batched"] = batched_bench(h, args.batched_count, "bf16")
-    if not args.no_cpu:
+    if "cpu" in legs:
         log("timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline(A.cpu().numpy())
     h.close()

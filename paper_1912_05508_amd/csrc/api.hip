@@ -239,11 +239,10 @@ int run_panel_core(qrx_handle h, hipStream_t s, int64_t m, float *P, int64_t ld,
     if (c.alg == 0) {
         Rec r(h, s);
         QRX_TRY(launch_gram_panel(s, P, ld, m, w, R, ldr, ws.gram, c.reorth));
-        // per sweep: Gram (m w(w+1)/2 FMA) and Q formation (m w(w+1)/2 FMA), FP64;
-        // panel traffic: read P, read P + write Q1, read Q1 + write Q (FP32)
-        const double sweeps = c.reorth ? 2.0 : 1.0;
-        r.end("gram_panel", sweeps * 2.0 * m * (double)w * (w + 1),
-              (c.reorth ? 5.0 : 3.0) * 4.0 * m * w);
+        // FP64 work: Gram of P, Q formation, Gram of Q1 (m w(w+1)/2 FMA each); the
+        // second Q formation runs only when Q1 is not yet orthonormal, so the
+        // usual case is counted. Traffic (FP32): read P, read P + write Q1.
+        r.end("gram_panel", (c.reorth ? 3.0 : 2.0) * m * (double)w * (w + 1), 12.0 * m * w);
         return QRX_OK;
     }
     constexpr int NB = 32;
