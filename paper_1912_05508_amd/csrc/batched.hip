@@ -178,7 +178,7 @@ QRX_DEV void wg_panel(float *P, int64_t ld, int64_t m, int w, float *Rb, int64_t
     double *Gl = red + L::RED_DOUBLES;
     double *S = Gl + 528;                   // G, then R (column-major, stride 33)
     double *Xc = S + 32 * 33;               // R^{-1} (column-major, stride 33)
-    double *T = Xc + 32 * 33;               // block scratch of the inverse
+    double *T = Xc + 32 * 33;               // pivot rows of the elimination (and scratch)
     double *R1 = T + 256;                   // first-sweep R
     const int64_t nch = (m + gram::CH - 1) / gram::CH;
     double acc[4][4];
@@ -194,7 +194,7 @@ QRX_DEV void wg_panel(float *P, int64_t ld, int64_t m, int w, float *Rb, int64_t
             S[i + j * 33] = (i <= j && j < w) ? Gl[gram::upk(i, j)] : 0.0;
         }
         __syncthreads();
-        gram::chol_blocked<32, BT>(S, Xc, T, t);
+        gram::chol_inv<32, BT>(S, Xc, T, t);
         for (int idx = t; idx < 32 * 32; idx += BT) {
             const int i = idx % 32, j = idx / 32;
             Xs[i * L::XLD + j] = (i <= j && j < w) ? Xc[i + j * 33] : 0.0;

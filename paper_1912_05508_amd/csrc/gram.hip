@@ -66,7 +66,7 @@ __global__ __launch_bounds__(GT) void gram_pass_kernel(float *__restrict__ P, in
 // G[e] = sum over the partials: a workgroup owns 64 entries (one per lane),
 // its 8 waves sum interleaved subsets of the partials and the 8 sums are added
 // in a fixed order (deterministic). The last workgroup to finish then factors
-// G = R^T R with gram::chol_blocked and writes R and X = R^{-1} (FP64, W x W,
+// G = R^T R with gram::chol_inv and writes R and X = R^{-1} (FP64, W x W,
 // column-major). If Rfinal is set, it also writes the panel's R block (FP32,
 // ldr): R Rprev when Rprev is set, else R.
 // With skip set (second sweep: G is the Gram matrix of the rounded Q1), a G
@@ -86,26 +86,28 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
     constexpr int NP = W * (W + 1) / 2;
     constexpr int LS = W + 1;
     constexpr int NW = CT / 64;
-    constexpr int U = (NW * 64 > (W / 16 - 1) * 256) ? NW * 64 : (W / 16 - 1) * 256;   // >= 16
+    constexpr int RB = 16;
+    constexpr int NQ = (W * W + CT - 1) / CT;   // entries of a W x W matrix per thread
+    constexpr int U = (NW * 64 > 4 * W + 4) ? NW * 64 : 4 * W + 4;   // partial sums, then pivot rows
     __shared__ double S[W * LS];       // G, then R (upper)
     __shared__ double Xs[W * LS];      // R^{-1}, then Rprev
-    __shared__ double Ub[U];           // partial sums, then block scratch of the inverse
+    __shared__ double Ub[U];           // partial sums, then pivot rows of the elimination
     __shared__ int last;
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
     const int e = blockIdx.x * 64 + lane;
     {
-        // wave wv sums partials wv, wv + NW, ...: eight loads in flight per step,
-        // added in a fixed order
+        // wave wv sums partials wv, wv + NW, ... in that order, with RB loads in
+        // flight per step (the partials come from every XCD: each round trip is long)
         double s = 0.0;
         if (e < NP) {
             int b = wv;
-            for (; b + 7 * NW < nparts; b += 8 * NW) {
-                double v[8];
+            for (; b + (RB - 1) * NW < nparts; b += RB * NW) {
+                double v[RB];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(b + q * NW) * NP + e];
+                for (int q = 0; q < RB; ++q) v[q] = part[(int64_t)(b + q * NW) * NP + e];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) s += v[q];
+                for (int q = 0; q < RB; ++q) s += v[q];
             }
             for (; b < nparts; b += NW) s += part[(int64_t)b * NP + e];
         }
@@ -127,13 +129,22 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
     if (t == 0) atomicExch(counter, 0);
 
     double dev = 0.0;
-    for (int idx = t; idx < W * W; idx += CT) {
-        const int i = idx % W, j = idx / W;
-        const double g = (i <= j && j < w) ? G[upk(i, j)] : 0.0;
-        S[i + j * LS] = g;
-        if (i <= j && j < w) {
-            const double e2 = fabs(g - (i == j ? 1.0 : 0.0));
-            dev = fmax(dev, (e2 == e2) ? e2 : 1e300);   // a NaN entry never passes
+    {
+        double gv[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {   // every load issued before the first use
+            const int idx = t + q * CT, i = idx % W, j = idx / W;
+            gv[q] = (idx < W * W && i <= j && j < w) ? G[upk(i, j)] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int idx = t + q * CT, i = idx % W, j = idx / W;
+            if (idx >= W * W) continue;
+            S[i + j * LS] = gv[q];
+            if (i <= j && j < w) {
+                const double e2 = fabs(gv[q] - (i == j ? 1.0 : 0.0));
+                dev = fmax(dev, (e2 == e2) ? e2 : 1e300);   // a NaN entry never passes
+            }
         }
     }
     if (skip) {
@@ -148,15 +159,22 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
         const bool done = mx <= tau;   // NaN compares false: factorise
         if (t == 0) *skip = done ? 1 : 0;
         if (done) {
-            for (int idx = t; idx < W * W; idx += CT) {
-                const int i = idx % W, j = idx / W;
-                if (i < w && j < w) Rfinal[i + (int64_t)j * ldr] = (float)Rprev[idx];
+            double rv[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int idx = t + q * CT;
+                rv[q] = (idx < W * W) ? Rprev[idx] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int idx = t + q * CT, i = idx % W, j = idx / W;
+                if (idx < W * W && i < w && j < w) Rfinal[i + (int64_t)j * ldr] = (float)rv[q];
             }
             return;
         }
     }
     __syncthreads();
-    gram::chol_blocked<W, CT>(S, Xs, Ub, t);
+    gram::chol_inv<W, CT>(S, Xs, Ub, t);
     for (int idx = t; idx < W * W; idx += CT) {
         const int i = idx % W, j = idx / W;
         const bool up = i <= j && j < w;
@@ -165,8 +183,18 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
     }
     if (!Rfinal) return;
     if (Rprev) {
+        double rv[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int idx = t + q * CT;
+            rv[q] = (idx < W * W) ? Rprev[idx] : 0.0;
+        }
         __syncthreads();
-        for (int idx = t; idx < W * W; idx += CT) Xs[(idx % W) + (idx / W) * LS] = Rprev[idx];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int idx = t + q * CT;
+            if (idx < W * W) Xs[(idx % W) + (idx / W) * LS] = rv[q];
+        }
         __syncthreads();
     }
     // R (or R Rprev) in 2 x 4 tiles; the lower parts of S and Rprev are zero

@@ -27,11 +27,21 @@ struct Lds {
 };
 
 // Xs (row-major, XLD) <- X (W x W, FP64, column-major, global). Caller syncs.
+// All loads are issued before the first store (one round trip to memory: X
+// was just written by another workgroup and is not in this CU's caches).
 template <int W>
 QRX_DEV void load_x(const double *__restrict__ X, double *Xs, int t) {
-    for (int idx = t; idx < W * W; idx += GT) {
-        const int i = idx % W, j = idx / W;
-        Xs[i * Lds<W>::XLD + j] = X[idx];
+    constexpr int NQ = (W * W + GT - 1) / GT;
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int idx = t + q * GT;
+        v[q] = (idx < W * W) ? X[idx] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int idx = t + q * GT;
+        if (idx < W * W) Xs[(idx % W) * Lds<W>::XLD + idx / W] = v[q];
     }
 }
 
@@ -161,150 +171,116 @@ QRX_DEV void gram_store(double (&acc)[4][4], double *red, double *out, int t) {
 }
 
 // ---------------------------------------------------------------------------
-// Blocked Cholesky with the inverse of the factor, for W a multiple of 16:
-// G = R^T R (R upper, R_kk > 0) and X = R^{-1}, both FP64 in LDS (column-
-// major, stride W + 1). On entry S holds G in its upper triangle (zero beyond
-// w); on exit S holds R in its upper triangle and Xs holds X (zero below the
-// diagonal). A pivot <= 0 gives a zero row of R and a zero column of X.
-// Per 16-column block: one wave factors the diagonal block and inverts it in
-// registers (column per lane, values exchanged by cross-lane shuffles), then
-// all threads form the block row of R and update the trailing matrix; the
-// off-diagonal blocks of X follow by block products ordered by their distance
-// from the diagonal. T is LDS scratch of max(16, (W/16 - 1) * 256) doubles.
+// Cholesky with the inverse of the factor: G = R^T R (R upper, R_kk > 0) and
+// X = R^{-1}, FP64 in LDS (column-major, stride W + 1). On entry S holds G in
+// its upper triangle (zero beyond w); on exit S holds R in its upper triangle
+// and Xs holds X (zero below the diagonal). A pivot <= 0 gives a zero row of R
+// and a zero column of X.
+// Symmetric elimination on the augmented W x 2W matrix [G | I]: step k
+// subtracts (entry k of row i) / pivot times row k from every row i > k; row k
+// scaled by 1/sqrt(pivot) is then row k of R on the left and row k of R^{-T}
+// on the right (the row operations that turn G into R turn I into R^{-T}).
+// The matrix lives in registers, RB x CB entries per thread, and row k stays
+// unscaled until the end. Row k is broadcast through a double-buffered row in
+// LDS with its pivot in a slot of its own and its left entries up to the
+// diagonal zeroed, so that rows <= k, whose entry in that row is zero, are
+// left unchanged without a branch. Waves whose rows are all <= k skip the
+// step; one barrier per step. Entries left of the diagonal take finite values
+// that are never read. T is LDS scratch of 4W + 4 doubles.
 // ---------------------------------------------------------------------------
-// v in lane l, as a wave-uniform value (two v_readlane).
-QRX_DEV double readlane_d(double v, int l) {
-    const long long bits = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)bits, l);
-    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // 1 / sqrt(d) for d > 0: hardware estimate plus one Newton step.
 QRX_DEV double rsqrt_d(double d) {
     double y = __builtin_amdgcn_rsq(d);
     return y * fma(-0.5 * d * y, y, 1.5);
 }
 
-// One wave: Cholesky of the 16 x 16 block at (o, o) of S (upper triangle,
-// updated in place to R) and its inverse into Xs. Lane j < 16 keeps column j
-// in registers; the entries of the pivot row are read from their lanes with
-// v_readlane. Lanes 16..63 compute copies and write nothing.
-template <int LS>
-QRX_DEV void diag16(double *S, double *Xs, int o, int lane) {
-    const int j = lane & 15;
-    const bool own = lane < 16;
-    double col[16], x[16], rdi[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) col[i] = (i <= j) ? S[(o + i) + (o + j) * LS] : 0.0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const double d = readlane_d(col[k], k);      // G'[k][k]
-        const double rinv = (d > 0.0) ? rsqrt_d(d) : 0.0;
-        rdi[k] = rinv;                               // 1 / R[k][k] (0 for a bad pivot)
-        const double rkj = (j >= k) ? col[k] * rinv : 0.0;
-#pragma unroll
-        for (int i = k + 1; i < 16; ++i) {
-            const double rki = readlane_d(col[k], i) * rinv;   // R[k][i]
-            if (i <= j) col[i] = fma(-rki, rkj, col[i]);
-        }
-        col[k] = rkj;                                // R[k][j]
-    }
-    // column j of X: R x = e_j by back substitution
-#pragma unroll
-    for (int i = 15; i >= 0; --i) {
-        double acc = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-        for (int l = i + 1; l < 16; ++l) acc = fma(-readlane_d(col[i], l), x[l], acc);
-        x[i] = (i <= j) ? acc * rdi[i] : 0.0;
-    }
-    if (own) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            if (i <= j) S[(o + i) + (o + j) * LS] = col[i];
-            Xs[(o + i) + (o + j) * LS] = x[i];
-        }
-    }
-}
-
 template <int W, int NT>
-QRX_DEV void chol_blocked(double *S, double *Xs, double *T, int t) {
+QRX_DEV void chol_inv(double *S, double *Xs, double *T, int t) {
     constexpr int LS = W + 1;
-    constexpr int NB = W / 16;
-    constexpr int PV = (16 * (W - 16) + NT - 1) / NT;     // panel entries per thread
-    static_assert(W % 16 == 0 && NT >= 64, "blocked Cholesky shape");
-    // zero the strictly-lower part of Xs (the blocks below the diagonal stay zero)
-    for (int idx = t; idx < W * W; idx += NT) {
-        const int i = idx % W, jj = idx / W;
-        if (i > jj) Xs[i + jj * LS] = 0.0;
-    }
-    for (int K = 0; K < NB; ++K) {
-        const int o = 16 * K, rest = W - o - 16;
-        if (t < 64) diag16<LS>(S, Xs, o, t);
-        __syncthreads();
-        if (rest > 0) {
-            // block row of R: R[o+i][c] = sum_{l <= i} X_KK[l][i] G'[o+l][c]
-            double v[PV > 0 ? PV : 1];
+    constexpr int E = 2 * W * W / NT;      // entries per thread
+    constexpr int CB = E >= 2 ? 2 : 1;
+    constexpr int RB = E / CB;
+    constexpr int NCB = 2 * W / CB;
+    constexpr int RL = 2 * W + 2;          // row buffer: 2W entries, the pivot, padding
+    static_assert(E * NT == 2 * W * W && (W / RB) * NCB == NT && NT % 64 == 0,
+                  "elimination thread mapping");
+    const int i0 = (t / NCB) * RB, j0 = (t % NCB) * CB;
+    // last row held by this wave (uniform)
+    const int wlast = __builtin_amdgcn_readfirstlane(((t | 63) / NCB) * RB + RB - 1);
+    double M[RB][CB], sc[RB];
 #pragma unroll
-            for (int q = 0; q < PV; ++q) {
-                const int idx = t + q * NT;
-                v[q] = 0.0;
-                if (idx < 16 * rest) {
-                    const int i = idx % 16, c = o + 16 + idx / 16;
-                    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < RB; ++r) {
+        sc[r] = 0.0;
 #pragma unroll
-                    for (int l = 0; l < 16; ++l)   // X_KK[l][i] = 0 for l > i
-                        a4[l & 3] = fma(Xs[(o + l) + (o + i) * LS], S[(o + l) + c * LS], a4[l & 3]);
-                    v[q] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < PV; ++q) {
-                const int idx = t + q * NT;
-                if (idx < 16 * rest) S[(o + idx % 16) + (o + 16 + idx / 16) * LS] = v[q];
-            }
-            __syncthreads();
-            // trailing update: G'[a][b] -= sum_i R[o+i][a] R[o+i][b], a <= b in the rest
-            for (int idx = t; idx < rest * rest; idx += NT) {
-                const int a = o + 16 + idx % rest, b = o + 16 + idx / rest;
-                if (a <= b) {
-                    double a4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int i = 0; i < 16; ++i)
-                        a4[i & 3] = fma(S[(o + i) + a * LS], S[(o + i) + b * LS], a4[i & 3]);
-                    S[a + b * LS] -= (a4[0] + a4[1]) + (a4[2] + a4[3]);
-                }
-            }
-            __syncthreads();
+        for (int c = 0; c < CB; ++c) {
+            const int i = i0 + r, j = j0 + c;
+            M[r][c] = (j < W) ? ((i <= j) ? S[i + j * LS] : S[j + i * LS])
+                              : ((j - W == i) ? 1.0 : 0.0);
         }
     }
-    // off-diagonal blocks of X: X_IJ = -X_II sum_{L=I+1..J} R_IL X_LJ, by distance
-    for (int d = 1; d < NB; ++d) {
-        const int nblk = NB - d;
-        for (int idx = t; idx < nblk * 256; idx += NT) {
-            const int I = idx / 256, p = (idx % 256) % 16, q = (idx % 256) / 16;
-            const int J = I + d;
-            double a4[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int r = 16 * (I + 1); r <= 16 * J + 15; r += 4) {
+    // row q (held as M[r]) into buffer q & 1: left entries j <= q zeroed, pivot apart
+    auto put_row = [&](int q, int r) {
+        double *dst = T + (q & 1) * RL;
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    a4[u] = fma(S[(16 * I + p) + (r + u) * LS], Xs[(r + u) + (16 * J + q) * LS], a4[u]);
-            }
-            T[idx] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+        for (int c = 0; c < CB; ++c) {
+            const int j = j0 + c;
+            dst[j] = (j <= q) ? 0.0 : M[r][c];
+            if (j == q) dst[2 * W] = M[r][c];
         }
-        __syncthreads();
-        for (int idx = t; idx < nblk * 256; idx += NT) {
-            const int I = idx / 256, p = (idx % 256) % 16, q = (idx % 256) / 16;
-            const int J = I + d;
-            double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    };
+    if (i0 == 0) put_row(0, 0);
+    __syncthreads();
+    for (int k = 0; k < W; ++k) {
+        if (wlast > k) {
+            const double *row = T + (k & 1) * RL;
+            const double d = row[2 * W];
+            double rr[RB], rc[CB];
 #pragma unroll
-            for (int s2 = 0; s2 < 16; ++s2)   // X_II[p][s2] = 0 for s2 < p
-                a4[s2 & 3] = fma(Xs[(16 * I + p) + (16 * I + s2) * LS], T[I * 256 + q * 16 + s2], a4[s2 & 3]);
-            Xs[(16 * I + p) + (16 * J + q) * LS] = -((a4[0] + a4[1]) + (a4[2] + a4[3]));
+            for (int r = 0; r < RB; ++r) rr[r] = row[i0 + r];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) rc[c] = row[j0 + c];
+            const double rinv = (d > 0.0) ? rsqrt_d(d) : 0.0;
+            const double dinv = rinv * rinv;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) rc[c] *= dinv;
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) M[r][c] = fma(-rr[r], rc[c], M[r][c]);
+            const int rk = k - i0;
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                if (rk == r) sc[r] = rinv;
+            const int rn = rk + 1;
+            if (k + 1 < W) {
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    if (rn == r) put_row(k + 1, r);
+            }
+        } else if (k - i0 >= 0 && k - i0 < RB) {
+            // the wave is done, but this thread still needs its scale for row k
+            const double d = T[(k & 1) * RL + 2 * W];
+            const double rinv = (d > 0.0) ? rsqrt_d(d) : 0.0;
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                if (k - i0 == r) sc[r] = rinv;
         }
         __syncthreads();
     }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int i = i0 + r, j = j0 + c;
+            const double v = M[r][c] * sc[r];
+            if (j < W) {
+                if (i <= j) S[i + j * LS] = v;
+            } else {
+                const int a = j - W;   // X[a][i] = (R^{-T})[i][a]
+                Xs[a + i * LS] = (a <= i) ? v : 0.0;
+            }
+        }
+    __syncthreads();
 }
 
 }  // namespace gram
