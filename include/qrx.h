@@ -57,9 +57,9 @@ typedef struct qrx_handle_s *qrx_handle;
 
 /* Operand precision of the trailing products R12 = Q1^T A2 and
  * A2 -= Q1 R12 (Alg. 2); accumulation is FP32 in every mode. QRX_FP16X3
- * splits each FP32 operand into FP16 hi + 2^-11 lo parts and forms
- * hi*hi + 2^-11 (hi*lo + lo*hi) on the FP16 matrix cores (three products per
- * step, ~22-bit operands): near-FP32 accuracy at FP16 matrix-core rates. */
+ * splits each FP32 operand x into FP16 parts hi = fl16(x), lo = fl16(x - hi)
+ * and forms hi*hi + hi*lo + lo*hi on the FP16 matrix cores (three products
+ * per step, ~22-bit operands): near-FP32 accuracy at FP16 matrix-core rates. */
 typedef enum { QRX_FP32 = 0, QRX_FP16 = 1, QRX_BF16 = 2, QRX_FP16X3 = 3 } qrx_prec;
 
 /* QR options; an all-zero struct selects the defaults. */

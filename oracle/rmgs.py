@@ -15,7 +15,7 @@ This follows the paper's algorithm step by step, in numpy:
 ``prec`` rounds the operands of the two trailing products the way a
 low-precision matrix unit would see them: "fp16" or "bf16" round-to-nearest-
 even of the FP32 operand ("fp16x3": its FP16 hi part plus the FP16-rounded
-remainder scaled by 2^-11) after an exact power-of-two column scaling (max-abs
+remainder) after an exact power-of-two column scaling (max-abs
 of each A2 column brought to [2^13, 2^14), Q1 multiplied by 2^14, and each
 R12 column brought to [2^13, 2^14) before the update); the products of the
 rounded operands are summed in float32 (a float32 matrix product), as a
@@ -43,10 +43,10 @@ def round_operand(x, prec):
     if prec == "fp16":
         return x32.astype(np.float16).astype(np.float64)
     if prec == "fp16x3":
-        # hi = fl16(x), lo = fl16((x - hi) 2^11); the operand seen is hi + 2^-11 lo
+        # hi = fl16(x), lo = fl16(x - hi); the operand seen is hi + lo
         hi = x32.astype(np.float16).astype(np.float32)
-        lo = ((x32 - hi) * np.float32(2048.0)).astype(np.float16).astype(np.float64)
-        return hi.astype(np.float64) + lo / 2048.0
+        lo = (x32 - hi).astype(np.float16).astype(np.float64)
+        return hi.astype(np.float64) + lo
     if prec == "bf16":
         return to_bf16(x32).astype(np.float64)
     return np.asarray(x, dtype=np.float64)

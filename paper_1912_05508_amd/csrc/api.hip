@@ -158,8 +158,23 @@ struct QrWork {
     // 16-bit operand copies for low-precision nodes (null when there are none):
     // Q column-major (ldc) and row-major (ldq), R12 of the current node (ld k)
     uint16_t *qc, *qcl, *qr, *qrl, *rh, *rhl;
+    // the node's A2 packed to 16-bit (column-major, ldc) for large-tile projections
+    uint16_t *a2h, *a2l;
     int64_t ldc, ldq;
 };
+
+// Whether a low-precision node's products take the large-tile kernels (their
+// operands are the packed copies, aligned when the node's first column is a
+// multiple of 8 and its width k is too).
+bool tn_proj(const Op &o, int64_t m) {
+    return o.prec != QRX_FP32 && m >= 256 && o.k >= 256 && o.n2 >= 256 && o.c0 % 8 == 0;
+}
+bool tn_upd(const Op &o, int64_t m) {
+    return o.prec != QRX_FP32 && m >= 256 && o.n2 >= 256 && o.c0 % 8 == 0 && o.k % 8 == 0;
+}
+int node_splits(const Op &o, int64_t m) {
+    return tn_proj(o, m) ? tn_projection_splits(m, o.k, o.n2) : projection_splits(m, o.k, o.n2, o.prec);
+}
 
 bool has_lowp_nodes(const QrCfg &c, const std::vector<Op> &ops) {
     for (const Op &o : ops)
@@ -178,7 +193,7 @@ void carve_qr(Carve &cv, int64_t m, int64_t n, const QrCfg &c, const std::vector
     size_t part = 1;
     for (const Op &o : ops)
         if (o.kind == 1) {
-            const size_t s = projection_splits(m, o.k, o.n2, o.prec);
+            const size_t s = node_splits(o, m);
             part = std::max(part, s * (size_t)o.k * (size_t)o.n2);
         }
     w.part = cv.take<float>(part);
@@ -196,7 +211,7 @@ void carve_qr(Carve &cv, int64_t m, int64_t n, const QrCfg &c, const std::vector
     w.stack_floats = st;
     w.stack_base = cv.take<float>(c.alg == 1 ? st + 1 : 1);
     w.gram = cv.take<double>(c.alg == 0 ? gram_workspace_doubles(m, 64) : 1);
-    w.qc = w.qcl = w.qr = w.qrl = w.rh = w.rhl = nullptr;
+    w.qc = w.qcl = w.qr = w.qrl = w.rh = w.rhl = w.a2h = w.a2l = nullptr;
     w.ldc = round_up(m, 8);
     w.ldq = round_up(n, 8);
     if (has_lowp_nodes(c, ops)) {
@@ -211,6 +226,13 @@ void carve_qr(Carve &cv, int64_t m, int64_t n, const QrCfg &c, const std::vector
             w.qcl = cv.take<uint16_t>((size_t)w.ldc * n);
             w.qrl = cv.take<uint16_t>((size_t)m * w.ldq);
             w.rhl = cv.take<uint16_t>(rsz);
+        }
+        size_t a2 = 0;
+        for (const Op &o : ops)
+            if (o.kind == 1 && tn_proj(o, m)) a2 = std::max(a2, (size_t)w.ldc * (size_t)o.n2);
+        if (a2) {
+            w.a2h = cv.take<uint16_t>(a2);
+            if (split) w.a2l = cv.take<uint16_t>(a2);
         }
     }
 }
@@ -302,7 +324,8 @@ int run_qr(qrx_handle h, hipStream_t s, int64_t m, int64_t n, float *W, int64_t 
             float *A2 = W + (o.c0 + o.k) * ldw;
             float *R12 = R + o.c0 + (o.c0 + o.k) * ldr;
             float *cm = ws.colmax + o.c0 + o.k;
-            const int splits = projection_splits(m, o.k, o.n2, o.prec);
+            const int splits = node_splits(o, m);
+            const bool big_p = tn_proj(o, m), big_u = tn_upd(o, m);
             // column max-abs of the updated A2 is read later only by scaled low-precision
             // projections inside A2 (width > cutoff) and by the TSQR panel's scaling
             float *cm_out = (c.alg == 1 || (o.n2 > c.c && o.prec != QRX_FP32 && c.scaling)) ? cm
@@ -316,6 +339,20 @@ int run_qr(qrx_handle h, hipStream_t s, int64_t m, int64_t n, float *W, int64_t 
             // Rh = packed R12 (or correction) for the low-precision update
             uint16_t *rh = lp ? ws.rh : nullptr, *rhl = lp ? ws.rhl : nullptr;
             auto project = [&]() -> int {
+                if (big_p) {
+                    {
+                        Rec r(h, s);
+                        QRX_TRY(launch_pack_cols(s, o.prec, c.scaling, m, o.n2, A2, ldw, cm,
+                                                 ws.a2h, ws.a2l, ws.ldc));
+                        r.end("pack_a2", 0.0, (4.0 + (ws.a2l ? 4.0 : 2.0)) * m * o.n2);
+                    }
+                    Rec r(h, s);
+                    QRX_TRY(launch_projection_tn(s, o.prec, m, o.k, o.n2, ws.qc + o.c0 * ws.ldc,
+                                                 ws.qcl ? ws.qcl + o.c0 * ws.ldc : nullptr,
+                                                 ws.ldc, ws.a2h, ws.a2l, ws.ldc, ws.part, splits));
+                    r.end(pn, fl, (double)esz * m * (o.k + o.n2) + 4.0 * splits * o.k * o.n2);
+                    return QRX_OK;
+                }
                 Rec r(h, s);
                 if (lp)
                     QRX_TRY(launch_projection_lp(s, o.prec, c.scaling, m, o.k, o.n2,
@@ -330,7 +367,11 @@ int run_qr(qrx_handle h, hipStream_t s, int64_t m, int64_t n, float *W, int64_t 
             };
             auto update = [&](const float *Rm, int64_t ldm, float *cmo) -> int {
                 Rec r(h, s);
-                if (lp)
+                if (big_u)
+                    QRX_TRY(launch_update_tn(s, o.prec, c.scaling, m, o.k, o.n2, ws.qr + o.c0,
+                                             ws.qrl ? ws.qrl + o.c0 : nullptr, ws.ldq, rh, rhl,
+                                             o.k, A2, ldw, ws.uscale, cmo, ws.cmpart));
+                else if (lp)
                     QRX_TRY(launch_update_lp(s, o.prec, c.scaling, m, o.k, o.n2, ws.qr + o.c0,
                                              ws.qrl ? ws.qrl + o.c0 : nullptr, ws.ldq, rh, rhl,
                                              o.k, A2, ldw, ws.uscale, cmo, ws.cmpart));

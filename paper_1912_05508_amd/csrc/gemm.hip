@@ -95,7 +95,7 @@ __global__ __launch_bounds__(GT) void projection_kernel(int64_t K, int64_t M, in
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FN; ++j) acc[i][j] += acc2[i][j] * kSplitLoInv;
+            for (int j = 0; j < FN; ++j) acc[i][j] += acc2[i][j];
     }
     float *P = part + (int64_t)blockIdx.y * M * N;
 #pragma unroll
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void proj_reduce_kernel(int64_t M, int64_t N,
             const _Float16 h = (_Float16)v;
             Rh[i + j * ldh] = *reinterpret_cast<const uint16_t *>(&h);
             if (eprec == 3) {
-                const _Float16 l = (_Float16)((v - (float)h) * kSplitLo);
+                const _Float16 l = (_Float16)(v - (float)h);
                 Rl[i + j * ldh] = *reinterpret_cast<const uint16_t *>(&l);
             }
         }
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(GT) void update_kernel(int64_t M, int64_t N, int64_
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FN; ++j) acc[i][j] += acc2[i][j] * kSplitLoInv;
+            for (int j = 0; j < FN; ++j) acc[i][j] += acc2[i][j];
     }
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn) {

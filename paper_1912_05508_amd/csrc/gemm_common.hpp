@@ -30,8 +30,8 @@ struct PBF16 {
     static constexpr int PAD = 8;
     static constexpr bool SPLIT = false;
 };
-// Split FP16: x = hi + 2^-11 lo with hi = fl16(x), lo = fl16((x - hi) 2^11);
-// x y ~ hi_x hi_y + 2^-11 (hi_x lo_y + lo_x hi_y), three FP16 MFMAs per step.
+// Split FP16: x = hi + lo with hi = fl16(x), lo = fl16(x - hi);
+// x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y, three FP16 MFMAs per step.
 struct PF16X3 {
     using E = _Float16;
     static constexpr int KS = 32;
@@ -56,8 +56,6 @@ struct PBF16K32 {
     static constexpr int PAD = 8;
     static constexpr bool SPLIT = false;
 };
-constexpr float kSplitLo = 2048.0f;          // 2^11
-constexpr float kSplitLoInv = 1.0f / 2048.0f;
 
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -78,8 +76,8 @@ QRX_DEV void st4(__bf16 *d, float a, float b, float c, float e) {
 QRX_DEV void st4_split(_Float16 *dh, _Float16 *dl, float a, float b, float c, float e) {
     const _Float16 ha = (_Float16)a, hb = (_Float16)b, hc = (_Float16)c, he = (_Float16)e;
     f16x4 vh = {ha, hb, hc, he};
-    f16x4 vl = {(_Float16)((a - (float)ha) * kSplitLo), (_Float16)((b - (float)hb) * kSplitLo),
-                (_Float16)((c - (float)hc) * kSplitLo), (_Float16)((e - (float)he) * kSplitLo)};
+    f16x4 vl = {(_Float16)(a - (float)ha), (_Float16)(b - (float)hb), (_Float16)(c - (float)hc),
+                (_Float16)(e - (float)he)};
     *reinterpret_cast<f16x4 *>(dh) = vh;
     *reinterpret_cast<f16x4 *>(dl) = vl;
 }

@@ -12,7 +12,7 @@
 // way for the update. Both products then stage 16-byte pieces straight into
 // double-buffered LDS tiles (one barrier per K stage); only A2, the FP32
 // operand of the projection, is converted (and column-scaled) on the way in.
-// Split FP16 keeps a second copy with the low parts lo = fl16((x - hi) 2^11).
+// Split FP16 keeps a second copy with the low parts lo = fl16(x - hi).
 //
 // Workgroups are handed to the 8 XCDs round-robin; the tile order gives each
 // XCD a contiguous range of tiles, so the tiles that share an operand block
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(GT) void proj_lp_kernel(int64_t K, int64_t M, int64
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FN; ++j) acc[i][j] += acc2[i][j] * kSplitLoInv;
+            for (int j = 0; j < FN; ++j) acc[i][j] += acc2[i][j];
     }
     float *P = part + (int64_t)blockIdx.y * M * N;
 #pragma unroll
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(GT) void update_lp_kernel(int64_t M, int64_t N, int
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FN; ++j) acc[i][j] += acc2[i][j] * kSplitLoInv;
+            for (int j = 0; j < FN; ++j) acc[i][j] += acc2[i][j];
     }
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn) {
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(256) void pack_q_kernel(const float *__restrict__ Q
         if (in) {
             const E h = (E)v;
             Qc[r + cc * ldc] = h;
-            if constexpr (SPLIT) Qcl[r + cc * ldc] = (E)((v - (float)h) * kSplitLo);
+            if constexpr (SPLIT) Qcl[r + cc * ldc] = (E)(v - (float)h);
         }
     }
     __syncthreads();
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(256) void pack_q_kernel(const float *__restrict__ Q
             const float v = T[rr][cc];
             const E h = (E)v;
             Qr[r * ldr + cc] = h;
-            if constexpr (SPLIT) Qrl[r * ldr + cc] = (E)((v - (float)h) * kSplitLo);
+            if constexpr (SPLIT) Qrl[r * ldr + cc] = (E)(v - (float)h);
         }
     }
 }

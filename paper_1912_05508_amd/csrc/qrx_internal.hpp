@@ -152,5 +152,22 @@ hipError_t launch_update_lp(hipStream_t s, int prec, int scaling, int64_t m, int
                             const uint16_t *rh, const uint16_t *rhl, int64_t ldh, float *A2,
                             int64_t lda, const float *uscale, float *colmax, float *cmpart);
 int projection_splits(int64_t m, int64_t k, int64_t n2, int prec);
+// Large-tile products (gemm_tn.hip): 256 x 256 tiles on 16-bit operands with
+// 16-byte aligned rows; tn_eligible tells whether a product of rows x cols
+// outputs can use them.
+bool tn_eligible(int64_t rows, int64_t cols, int64_t ld_a, int64_t ld_b, const void *a,
+                 const void *b);
+int tn_projection_splits(int64_t m, int64_t k, int64_t n2);
+hipError_t launch_pack_cols(hipStream_t s, int prec, int scaling, int64_t m, int64_t n2,
+                            const float *A2, int64_t lda, const float *colmax, uint16_t *bh,
+                            uint16_t *bl, int64_t ldb);
+hipError_t launch_projection_tn(hipStream_t s, int prec, int64_t m, int64_t k, int64_t n2,
+                                const uint16_t *qc, const uint16_t *qcl, int64_t ldc,
+                                const uint16_t *bh, const uint16_t *bl, int64_t ldb, float *part,
+                                int splits);
+hipError_t launch_update_tn(hipStream_t s, int prec, int scaling, int64_t m, int64_t k,
+                            int64_t n2, const uint16_t *qr, const uint16_t *qrl, int64_t ldq,
+                            const uint16_t *rh, const uint16_t *rhl, int64_t ldh, float *A2,
+                            int64_t lda, const float *uscale, float *colmax, float *cmpart);
 
 }  // namespace qrx
