@@ -6,12 +6,12 @@
 //   update A2 -= Q1 R12: A = Qr (row r of Q1, columns = K), B = Rh (column j
 //     of the packed R12, rows = K).
 // One workgroup of 8 waves computes a 256 x 256 tile (each wave 128 x 64 with
-// 16x16x32 MFMAs, FP32 accumulation) through double-buffered 64-deep LDS
-// stages, one barrier per stage; workgroups go to the XCDs in contiguous tile
+// 16x16x32 MFMAs, FP32 accumulation) through double-buffered LDS stages (64
+// deep), one barrier per stage; workgroups go to the XCDs in contiguous tile
 // ranges (rows of tiles that share an operand block run on one L2).
-// Split FP16 (x = hi + lo, lo = fl16(x - hi)) is the same product over three
-// K segments, (A_hi, B_hi), (A_hi, B_lo), (A_lo, B_hi), accumulated in the
-// same FP32 registers; the lo lo term is dropped.
+// Split FP16 (x = hi + lo, lo = fl16(x - hi)) stages the hi and lo tiles of
+// both operands (32 deep) and issues hi*hi, hi*lo and lo*hi for every fragment
+// pair into the same FP32 accumulator; the lo*lo term is dropped.
 // The projection is split over K (blockIdx.y) into FP32 partials summed in a
 // fixed order by proj_reduce; the update subtracts its tile from A2 in place
 // (scaled back by 1 / (2^14 s_j)) and writes partial column max-abs values.
@@ -20,14 +20,22 @@
 namespace qrx {
 
 namespace tn {
-constexpr int BM = 256, BN = 256, BK = 64;
+constexpr int BM = 256, BN = 256;
 constexpr int WM = 2, WN = 4, NT = WM * WN * 64;
-constexpr int LS = BK + 8;                 // LDS row stride (16-bit elements)
 constexpr int FM = BM / WM / 16, FN = BN / WN / 16;
-constexpr int QP = BK / 8;                 // 16-byte pieces per row and stage
-constexpr int PA = BM * QP / NT, PB = BN * QP / NT;
-static_assert(PA * NT == BM * QP && PB * NT == BN * QP, "loader mapping");
 constexpr int kXcds = 8;
+// Stage geometry: plain products stage A and B 64 deep; split products stage
+// A_hi, A_lo, B_hi, B_lo 32 deep (the same 160 KB of LDS, double-buffered).
+template <bool SPLIT>
+struct Geo {
+    static constexpr int BK = SPLIT ? 32 : 64;
+    static constexpr int NTILE = SPLIT ? 4 : 2;
+    static constexpr int LS = BK + 8;                 // row stride (16-bit elements)
+    static constexpr int TS = BM * LS;                // one tile
+    static constexpr int QP = BK / 8;                 // 16-byte pieces per row
+    static constexpr int PT = BM * QP / NT;           // pieces per thread and tile
+    static_assert(BM == BN && PT * NT == BM * QP, "loader mapping");
+};
 
 QRX_DEV int64_t xcd_order(int64_t b, int64_t nt) {
     if (nt % kXcds) return b;
@@ -56,20 +64,29 @@ QRX_DEV uint4 piece(const E *X, int64_t ld, int64_t r, int64_t rend, int64_t k, 
     }
     return x;
 }
+
+template <class E, class V8>
+QRX_DEV f32x4 mma(const V8 &a, const V8 &b, const f32x4 &c) {
+    if constexpr (std::is_same<E, _Float16>::value)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 }  // namespace tn
 
 // MODE 0 (projection): part[blockIdx.y][i + j M] = sum over this split's
 // stages. MODE 1 (update): A2[i + j lda] -= es_j * sum (i < M rows of A2).
-// Stages run over nseg segments of ceil(K / BK) stages each.
-template <class E, int MODE>
+// SPLIT: hi*hi + hi*lo + lo*hi per fragment pair, one FP32 accumulator.
+template <class E, int MODE, bool SPLIT>
 __global__ __launch_bounds__(tn::NT) void tn_mma_kernel(
     int64_t M, int64_t N, int64_t K, const E *__restrict__ Ah, const E *__restrict__ Al,
     int64_t lda_op, const E *__restrict__ Bh, const E *__restrict__ Bl, int64_t ldb_op,
-    int nseg, int64_t stages_per_split, float *__restrict__ out, int64_t ldo,
+    int64_t stages_per_split, float *__restrict__ out, int64_t ldo,
     const float *__restrict__ uscale, float *__restrict__ cmpart, int scaled) {
     using namespace tn;
-    __shared__ __attribute__((aligned(16))) E As[2 * BM * LS];
-    __shared__ __attribute__((aligned(16))) E Bs[2 * BN * LS];
+    using G = Geo<SPLIT>;
+    constexpr int BK = G::BK, LS = G::LS, TS = G::TS, QP = G::QP, PT = G::PT, NTILE = G::NTILE;
+    __shared__ __attribute__((aligned(16))) E L[2 * NTILE * TS];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wm = wv % WM, wn = wv / WM;
     const int64_t tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
@@ -83,10 +100,10 @@ __global__ __launch_bounds__(tn::NT) void tn_mma_kernel(
         tm = tile / tiles_n;
     }
     const int64_t i0 = tm * BM, j0 = tnn * BN;
-    const int64_t nk = (K + BK - 1) / BK;           // stages per segment
+    const int64_t nk = (K + BK - 1) / BK;
     const int64_t s0 = (int64_t)blockIdx.y * stages_per_split;
     int64_t s1 = s0 + stages_per_split;
-    if (s1 > nk * nseg) s1 = nk * nseg;
+    if (s1 > nk) s1 = nk;
 
     f32x4 acc[FM][FN];
 #pragma unroll
@@ -94,34 +111,31 @@ __global__ __launch_bounds__(tn::NT) void tn_mma_kernel(
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    uint4 ra[PA], rb[PB];
+    // tiles of a stage: plain (A, B); split (A_hi, A_lo, B_hi, B_lo)
+    uint4 rg[NTILE][PT];
     auto gload = [&](int64_t s) {
-        const int seg = (int)(s / nk);
-        const int64_t k0 = (s % nk) * BK;
-        const E *A = (seg == 2) ? Al : Ah;
-        const E *B = (seg == 1) ? Bl : Bh;
+        const int64_t k0 = s * BK;
 #pragma unroll
-        for (int p = 0; p < PA; ++p) {
-            const int e = t + p * NT, r = e / QP, q = e % QP;
-            ra[p] = piece(A, lda_op, i0 + r, M, k0 + q * 8, K);
-        }
+        for (int x = 0; x < NTILE; ++x) {
+            const bool isb = x >= NTILE / 2;
+            const E *X = isb ? ((SPLIT && x == 3) ? Bl : Bh) : ((SPLIT && x == 1) ? Al : Ah);
+            const int64_t ld = isb ? ldb_op : lda_op;
+            const int64_t base = isb ? j0 : i0, rend = isb ? N : M;
 #pragma unroll
-        for (int p = 0; p < PB; ++p) {
-            const int e = t + p * NT, r = e / QP, q = e % QP;
-            rb[p] = piece(B, ldb_op, j0 + r, N, k0 + q * 8, K);
+            for (int p = 0; p < PT; ++p) {
+                const int e = t + p * NT, r = e / QP, q = e % QP;
+                rg[x][p] = piece(X, ld, base + r, rend, k0 + q * 8, K);
+            }
         }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int p = 0; p < PA; ++p) {
-            const int e = t + p * NT, r = e / QP, q = e % QP;
-            *reinterpret_cast<uint4 *>(As + buf * BM * LS + r * LS + q * 8) = ra[p];
-        }
+        for (int x = 0; x < NTILE; ++x)
 #pragma unroll
-        for (int p = 0; p < PB; ++p) {
-            const int e = t + p * NT, r = e / QP, q = e % QP;
-            *reinterpret_cast<uint4 *>(Bs + buf * BN * LS + r * LS + q * 8) = rb[p];
-        }
+            for (int p = 0; p < PT; ++p) {
+                const int e = t + p * NT, r = e / QP, q = e % QP;
+                *reinterpret_cast<uint4 *>(L + (buf * NTILE + x) * TS + r * LS + q * 8) = rg[x][p];
+            }
     };
     using V8 = typename std::conditional<std::is_same<E, _Float16>::value, f16x8, bf16x8>::type;
     if (s0 < s1) {
@@ -133,24 +147,39 @@ __global__ __launch_bounds__(tn::NT) void tn_mma_kernel(
     for (int64_t s = s0; s < s1; ++s) {
         const int buf = (int)((s - s0) & 1);
         if (s + 1 < s1) gload(s + 1);
-        const E *a = As + buf * BM * LS + (wm * (BM / WM) + rl) * LS + kq * 8;
-        const E *b = Bs + buf * BN * LS + (wn * (BN / WN) + rl) * LS + kq * 8;
+        const E *a = L + (buf * NTILE) * TS + (wm * (BM / WM) + rl) * LS + kq * 8;
+        const E *b = L + (buf * NTILE + NTILE / 2) * TS + (wn * (BN / WN) + rl) * LS + kq * 8;
+        if constexpr (SPLIT) {
+            V8 bh[FN], bl[FN];
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 32) {
-            V8 af[FM], bf[FN];
+            for (int f = 0; f < FN; ++f) {
+                bh[f] = *reinterpret_cast<const V8 *>(b + f * 16 * LS);
+                bl[f] = *reinterpret_cast<const V8 *>(b + TS + f * 16 * LS);
+            }
 #pragma unroll
-            for (int f = 0; f < FM; ++f) af[f] = *reinterpret_cast<const V8 *>(a + f * 16 * LS + kk);
-#pragma unroll
-            for (int f = 0; f < FN; ++f) bf[f] = *reinterpret_cast<const V8 *>(b + f * 16 * LS + kk);
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
+            for (int i = 0; i < FM; ++i) {
+                const V8 ah = *reinterpret_cast<const V8 *>(a + i * 16 * LS);
+                const V8 al = *reinterpret_cast<const V8 *>(a + TS + i * 16 * LS);
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
-                    if constexpr (std::is_same<E, _Float16>::value)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[i], bf[j], acc[i][j], 0, 0, 0);
-                    else
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = mma<E>(ah, bh[j], acc[i][j]);
+                    acc[i][j] = mma<E>(ah, bl[j], acc[i][j]);
+                    acc[i][j] = mma<E>(al, bh[j], acc[i][j]);
                 }
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 32) {
+                V8 af[FM], bf[FN];
+#pragma unroll
+                for (int f = 0; f < FM; ++f) af[f] = *reinterpret_cast<const V8 *>(a + f * 16 * LS + kk);
+#pragma unroll
+                for (int f = 0; f < FN; ++f) bf[f] = *reinterpret_cast<const V8 *>(b + f * 16 * LS + kk);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) acc[i][j] = mma<E>(af[i], bf[j], acc[i][j]);
+            }
         }
         if (s + 1 < s1) lstore(buf ^ 1);
         __syncthreads();
@@ -301,19 +330,38 @@ hipError_t launch_pack_cols(hipStream_t s, int prec, int scaling, int64_t m, int
     return hipGetLastError();
 }
 
-template <class E, int MODE>
+template <class E, int MODE, bool SPLIT>
 static hipError_t tn_go(hipStream_t s, int64_t M, int64_t N, int64_t K, const uint16_t *ah,
                         const uint16_t *al, int64_t lda_op, const uint16_t *bh,
-                        const uint16_t *bl, int64_t ldb_op, int nseg, int splits, float *out,
-                        int64_t ldo, const float *uscale, float *cmpart, int scaled) {
+                        const uint16_t *bl, int64_t ldb_op, int splits, float *out, int64_t ldo,
+                        const float *uscale, float *cmpart, int scaled) {
     const int64_t tiles = ((M + tn::BM - 1) / tn::BM) * ((N + tn::BN - 1) / tn::BN);
-    const int64_t total = ((K + tn::BK - 1) / tn::BK) * nseg;
+    const int64_t total = (K + tn::Geo<SPLIT>::BK - 1) / tn::Geo<SPLIT>::BK;
     const int64_t per = (total + splits - 1) / splits;
-    hipLaunchKernelGGL((tn_mma_kernel<E, MODE>), dim3((unsigned)tiles, (unsigned)splits),
+    hipLaunchKernelGGL((tn_mma_kernel<E, MODE, SPLIT>), dim3((unsigned)tiles, (unsigned)splits),
                        dim3(tn::NT), 0, s, M, N, K, (const E *)ah, (const E *)al, lda_op,
-                       (const E *)bh, (const E *)bl, ldb_op, nseg, per, out, ldo, uscale, cmpart,
+                       (const E *)bh, (const E *)bl, ldb_op, per, out, ldo, uscale, cmpart,
                        scaled);
     return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t tn_prec(hipStream_t s, int prec, int64_t M, int64_t N, int64_t K,
+                          const uint16_t *ah, const uint16_t *al, int64_t lda_op,
+                          const uint16_t *bh, const uint16_t *bl, int64_t ldb_op, int splits,
+                          float *out, int64_t ldo, const float *uscale, float *cmpart, int scaled) {
+    switch (prec) {
+        case QRX_FP16:
+            return tn_go<_Float16, MODE, false>(s, M, N, K, ah, al, lda_op, bh, bl, ldb_op, splits,
+                                                out, ldo, uscale, cmpart, scaled);
+        case QRX_BF16:
+            return tn_go<__bf16, MODE, false>(s, M, N, K, ah, al, lda_op, bh, bl, ldb_op, splits,
+                                              out, ldo, uscale, cmpart, scaled);
+        case QRX_FP16X3:
+            return tn_go<_Float16, MODE, true>(s, M, N, K, ah, al, lda_op, bh, bl, ldb_op, splits,
+                                               out, ldo, uscale, cmpart, scaled);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // R12 partials: part[split][i + j k] = sum_r Qc[r][i] B[r][j] over the split's rows.
@@ -321,12 +369,8 @@ hipError_t launch_projection_tn(hipStream_t s, int prec, int64_t m, int64_t k, i
                                 const uint16_t *qc, const uint16_t *qcl, int64_t ldc,
                                 const uint16_t *bh, const uint16_t *bl, int64_t ldb, float *part,
                                 int splits) {
-    const int nseg = prec == QRX_FP16X3 ? 3 : 1;
-    if (prec == QRX_BF16)
-        return tn_go<__bf16, 0>(s, k, n2, m, qc, qcl, ldc, bh, bl, ldb, nseg, splits, part, k,
-                                nullptr, nullptr, 0);
-    return tn_go<_Float16, 0>(s, k, n2, m, qc, qcl, ldc, bh, bl, ldb, nseg, splits, part, k,
-                              nullptr, nullptr, 0);
+    return tn_prec<0>(s, prec, k, n2, m, qc, qcl, ldc, bh, bl, ldb, splits, part, k, nullptr,
+                      nullptr, 0);
 }
 
 hipError_t launch_colmax_reduce(hipStream_t s, int64_t n2, int64_t slots, const float *cmpart,
@@ -337,15 +381,9 @@ hipError_t launch_update_tn(hipStream_t s, int prec, int scaling, int64_t m, int
                             int64_t n2, const uint16_t *qr, const uint16_t *qrl, int64_t ldq,
                             const uint16_t *rh, const uint16_t *rhl, int64_t ldh, float *A2,
                             int64_t lda, const float *uscale, float *colmax, float *cmpart) {
-    const int nseg = prec == QRX_FP16X3 ? 3 : 1;
     float *cp = colmax ? cmpart : nullptr;
-    hipError_t e;
-    if (prec == QRX_BF16)
-        e = tn_go<__bf16, 1>(s, m, n2, k, qr, qrl, ldq, rh, rhl, ldh, nseg, 1, A2, lda, uscale,
-                             cp, scaling);
-    else
-        e = tn_go<_Float16, 1>(s, m, n2, k, qr, qrl, ldq, rh, rhl, ldh, nseg, 1, A2, lda, uscale,
-                               cp, scaling);
+    const hipError_t e = tn_prec<1>(s, prec, m, n2, k, qr, qrl, ldq, rh, rhl, ldh, 1, A2, lda,
+                                    uscale, cp, scaling);
     if (e != hipSuccess) return e;
     if (colmax) return launch_colmax_reduce(s, n2, ((m + tn::BM - 1) / tn::BM) * tn::WM, cmpart, colmax);
     return hipSuccess;
