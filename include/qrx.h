@@ -79,6 +79,11 @@ typedef struct {
                              twice, R12 accumulated; Sec. 4.1.2 remedy applied per node):
                              0 = default (off for qrx_qr_factor*, on for qrx_lls_solve),
                              1 = on, 2 = off */
+    int gemm_tiles;       /* tiles of the low-precision trailing products: 0 = 256 x 256
+                             tiles for nodes with at least 256 rows and columns of output
+                             (default), 1 = 128-row tiles only */
+    int split_target;     /* workgroups a row-split projection aims at: 0 = default (256 with
+                             256 x 256 tiles, 1024 otherwise), else 16..8192 */
 } qrx_qr_opts;
 
 /* Least-squares options; an all-zero struct selects the defaults. */
@@ -121,7 +126,8 @@ const char *qrx_status_string(int status);
 int qrx_qr_workspace_size(qrx_handle h, int64_t m, int64_t n,
                           const qrx_qr_opts *opts, size_t *bytes);
 
-/* Thin QR, A = Q R (Sec. 2.2; Alg. 2 with TSQR panels, eq. caqr).
+/* Thin QR, A = Q R (Sec. 2.2; Alg. 2, eq. recqr, with re-orthogonalised
+ * Cholesky-QR or TSQR leaf panels).
  * On entry A holds the matrix; on exit it holds Q (m x n, orthonormal columns
  * up to the precision of the mode). R receives the n x n upper-triangular
  * factor with positive diagonal; its strictly-lower part is set to zero.
@@ -201,6 +207,62 @@ int qrx_lls_solve_batched(qrx_handle h, int batch, const int64_t *m, const int64
                           const float *const *A, const int64_t *lda, const double *const *b,
                           double *const *x, void *work, size_t work_bytes,
                           const qrx_lls_opts *opts, qrx_lls_info *info, hipStream_t stream);
+
+/* ---- autotuning ---------------------------------------------------------
+ * The paper fixes its blocking parameters (cutoff 128, 32-column panels, 256-row
+ * TSQR blocks; Sec. 3.1.3); the tuner measures them per size class instead.
+ * A size class is (device architecture, precision, panel algorithm or batched,
+ * ceil(log2 m), ceil(log2 n)); batched tuning uses the largest m and n of the
+ * batch. */
+typedef struct {
+    int panel_width;      /* nb */
+    int cutoff;           /* c */
+    int gemm_tiles;       /* as in qrx_qr_opts */
+    int split_target;     /* as in qrx_qr_opts (0 = default) */
+    double ms;            /* median device time of one factorisation with these values */
+    int trials;           /* configurations timed (0 when read from the cache) */
+    int from_cache;       /* 1 = read from the cache file */
+} qrx_tune_result;
+
+/* Pick nb, c, the tile family and the projection split target for QR in the
+ * precision (and panel algorithm) of *base: a coordinate search from the
+ * defaults over nb in {32, 64} (TSQR panel: {16, 32}), c in {64, 128, 256,
+ * 512}, both tile families and split targets {128, 256, 512, 1024}, each
+ * candidate timed with HIP events over `reps` runs (1..20) of
+ * qrx_qr_factor_out on A (device, m x n, lda; not modified), median taken.
+ * With cache_path (a JSON file, created if absent; NULL = no cache) a stored
+ * entry for the size class is returned without measuring, and a new result
+ * is stored. Allocates its own scratch (Q, R and workspace) and blocks. The
+ * other fields of *base are kept as they are in every candidate.
+ * Errors: QRX_EINVAL for bad sizes / options / reps, QRX_ENOMEM, QRX_EHIP, or
+ * the first error of a candidate that fails for a reason other than an
+ * unsupported option; a cache file that cannot be read or written gives
+ * QRX_EINVAL after the measurement (out is filled). */
+int qrx_tune(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
+             const qrx_qr_opts *base, int reps, const char *cache_path,
+             qrx_tune_result *out, hipStream_t stream);
+
+/* The batched counterpart: the cutoff c in {32, 64, 128, 256} for
+ * qrx_qr_factor_batched of this batch (arrays as there; the matrices are not
+ * modified: each candidate factors copies). panel_width is 32, gemm_tiles and
+ * split_target are 0 in the result. */
+int qrx_tune_batched(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
+                     const float *const *A, const int64_t *lda, const qrx_qr_opts *base,
+                     int reps, const char *cache_path, qrx_tune_result *out,
+                     hipStream_t stream);
+
+/* Host-only access to the tuning cache (no device work, no handle): the key
+ * of a size class, "<arch>/<prec>/<kind>/m<ceil log2 m>/n<ceil log2 n>" with
+ * kind 0 = "gram" (QR, Cholesky-QR panel), 1 = "batched", 2 = "tsqr" (QR,
+ * TSQR panel), into buf (len bytes); look an entry up (QRX_OK, or 1 when the
+ * file or the key is absent); store an entry (replacing the key's old one;
+ * the file is rewritten whole through a temporary file). QRX_EINVAL for NULL
+ * or bad arguments, a short buffer, or a file that is not a cache written by
+ * this library. */
+int qrx_tune_key(const char *arch, int64_t m, int64_t n, int prec, int kind, char *buf,
+                 size_t len);
+int qrx_tune_cache_get(const char *cache_path, const char *key, qrx_tune_result *out);
+int qrx_tune_cache_put(const char *cache_path, const char *key, const qrx_tune_result *r);
 
 /* ---- timing ------------------------------------------------------------ */
 /* When enabled, every kernel launch is bracketed by HIP events on its

@@ -12,6 +12,7 @@ layouts are copied into one first.
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 from . import _lib
 from ._lib import (QRX_BF16, QRX_EHIP, QRX_EINVAL, QRX_ENOCONV, QRX_ENOMEM,  # noqa: F401
@@ -171,6 +172,38 @@ class Handle:
                                             C.byref(o), infos, _stream())
         _lib.check(rc, "qrx_lls_solve_batched")
         return xs, [infos[i].as_dict() for i in range(k)]
+
+    # -- autotuning -------------------------------------------------------------
+    def tune(self, A, prec="fp16", cache=None, reps=3, **kw):
+        """Tune nb, cutoff, tile family and projection split for QR of A's size
+        class (A column-major float32, not modified); returns the result dict
+        (qr_opts keyword arguments panel_width, cutoff, gemm_tiles, split_target,
+        plus ms, trials, from_cache)."""
+        import torch
+        m, n = A.shape
+        assert A.dtype == torch.float32 and A.is_cuda
+        A = colmajor(A)
+        o = qr_opts(prec, **kw)
+        r = _lib.qrx_tune_result()
+        path = os.fsencode(cache) if cache is not None else None
+        rc = self.lib.qrx_tune(self.h, m, n, C.c_void_p(A.data_ptr()), _ld(A), C.byref(o), int(reps),
+                               path, C.byref(r), _stream())
+        _lib.check(rc, "qrx_tune")
+        return r.as_dict()
+
+    def tune_batched(self, mats, prec="bf16", cache=None, reps=3, **kw):
+        """Tune the cutoff of the batched QR for this batch (matrices not modified)."""
+        mats = [colmajor(a) for a in mats]
+        k = len(mats)
+        m, n, lda = self._arrays(mats)
+        Ap = (C.c_void_p * k)(*[a.data_ptr() for a in mats])
+        o = qr_opts(prec, **kw)
+        r = _lib.qrx_tune_result()
+        path = os.fsencode(cache) if cache is not None else None
+        rc = self.lib.qrx_tune_batched(self.h, k, m, n, Ap, lda, C.byref(o), int(reps), path,
+                                       C.byref(r), _stream())
+        _lib.check(rc, "qrx_tune_batched")
+        return r.as_dict()
 
     # -- timing ---------------------------------------------------------------
     def timing(self, enable=True):

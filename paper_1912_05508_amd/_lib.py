@@ -22,7 +22,7 @@ class qrx_qr_opts(C.Structure):
     _fields_ = [("gemm_prec", C.c_int), ("panel_width", C.c_int), ("cutoff", C.c_int),
                 ("block_rows", C.c_int), ("no_col_scaling", C.c_int),
                 ("panel_single_pass", C.c_int), ("panel_alg", C.c_int),
-                ("node_reorth", C.c_int)]
+                ("node_reorth", C.c_int), ("gemm_tiles", C.c_int), ("split_target", C.c_int)]
 
 
 class qrx_lls_opts(C.Structure):
@@ -34,6 +34,15 @@ class qrx_lls_info(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("restarts", C.c_int),
                 ("eta_F", C.c_double), ("resid_norm", C.c_double), ("normA_F", C.c_double),
                 ("qr_ms", C.c_double), ("krylov_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class qrx_tune_result(C.Structure):
+    _fields_ = [("panel_width", C.c_int), ("cutoff", C.c_int), ("gemm_tiles", C.c_int),
+                ("split_target", C.c_int), ("ms", C.c_double), ("trials", C.c_int),
+                ("from_cache", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -70,6 +79,13 @@ _SIGS = {
                                                   C.POINTER(C.c_size_t)]),
     "qrx_lls_solve_batched": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, _P, _P, C.c_size_t,
                                         C.POINTER(qrx_lls_opts), _P, _P]),
+    "qrx_tune": (C.c_int, [_P, _I64, _I64, _P, _I64, C.POINTER(qrx_qr_opts), C.c_int, C.c_char_p,
+                           C.POINTER(qrx_tune_result), _P]),
+    "qrx_tune_batched": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, C.POINTER(qrx_qr_opts), C.c_int,
+                                   C.c_char_p, C.POINTER(qrx_tune_result), _P]),
+    "qrx_tune_key": (C.c_int, [C.c_char_p, _I64, _I64, C.c_int, C.c_int, C.c_char_p, C.c_size_t]),
+    "qrx_tune_cache_get": (C.c_int, [C.c_char_p, C.c_char_p, C.POINTER(qrx_tune_result)]),
+    "qrx_tune_cache_put": (C.c_int, [C.c_char_p, C.c_char_p, C.POINTER(qrx_tune_result)]),
     "qrx_timing_enable": (C.c_int, [_P, C.c_int]),
     "qrx_timing_reset": (C.c_int, [_P]),
     "qrx_timing_get": (C.c_int, [_P, C.POINTER(qrx_kernel_stat), C.c_int, C.POINTER(C.c_int)]),
@@ -119,8 +135,10 @@ PANEL = {"gram": 0, "tsqr": 1, "mgs": 1}
 
 
 def qr_opts(prec="fp32", panel_width=0, cutoff=0, col_scaling=True, reorth=True, panel="gram",
-            node_reorth=None):
+            node_reorth=None, gemm_tiles=0, split_target=0):
     o = qrx_qr_opts()
+    o.gemm_tiles = gemm_tiles
+    o.split_target = split_target
     o.node_reorth = 0 if node_reorth is None else (1 if node_reorth else 2)
     o.panel_alg = PANEL[panel] if isinstance(panel, str) else int(panel)
     o.gemm_prec = PREC[prec] if isinstance(prec, str) else int(prec)
@@ -140,3 +158,30 @@ def lls_opts(prec="fp32", method="lsqr", tol=1e-10, max_iter=200, use_x0=False, 
     o.max_iter = max_iter
     o.use_x0 = 1 if use_x0 else 0
     return o
+
+
+# -- tuning cache (host only) ------------------------------------------------
+TUNE_KIND = {"gram": 0, "batched": 1, "tsqr": 2}
+
+
+def tune_key(arch, m, n, prec="fp16", kind="gram"):
+    buf = C.create_string_buffer(256)
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    k = TUNE_KIND[kind] if isinstance(kind, str) else int(kind)
+    check(load().qrx_tune_key(arch.encode(), int(m), int(n), p, k, buf, 256), "qrx_tune_key")
+    return buf.value.decode()
+
+
+def tune_cache_get(path, key):
+    """The cached entry for key as a dict, or None when absent."""
+    r = qrx_tune_result()
+    rc = load().qrx_tune_cache_get(os.fsencode(path), key.encode(), C.byref(r))
+    if rc == 1:
+        return None
+    check(rc, "qrx_tune_cache_get")
+    return r.as_dict()
+
+
+def tune_cache_put(path, key, panel_width, cutoff, gemm_tiles=0, split_target=0, ms=0.0):
+    r = qrx_tune_result(panel_width, cutoff, gemm_tiles, split_target, ms, 0, 0)
+    check(load().qrx_tune_cache_put(os.fsencode(path), key.encode(), C.byref(r)), "qrx_tune_cache_put")

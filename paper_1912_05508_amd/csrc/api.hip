@@ -90,7 +90,7 @@ struct Carve {
 int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
 
 struct QrCfg {
-    int prec, nb, c, reorth, scaling, alg, node_reorth;
+    int prec, nb, c, reorth, scaling, alg, node_reorth, tiles, split_target;
 };
 
 int resolve_qr(const qrx_qr_opts *o, QrCfg &c, bool lls = false) {
@@ -115,6 +115,10 @@ int resolve_qr(const qrx_qr_opts *o, QrCfg &c, bool lls = false) {
     c.node_reorth = o->node_reorth == 1 ? 1 : (o->node_reorth == 2 ? 0 : (lls ? 1 : 0));
     c.reorth = o->panel_single_pass ? 0 : 1;
     c.scaling = o->no_col_scaling ? 0 : 1;
+    if (o->gemm_tiles < 0 || o->gemm_tiles > 1) return QRX_EINVAL;
+    if (o->split_target != 0 && (o->split_target < 16 || o->split_target > 8192)) return QRX_EINVAL;
+    c.tiles = o->gemm_tiles;
+    c.split_target = o->split_target;
     return QRX_OK;
 }
 
@@ -166,14 +170,17 @@ struct QrWork {
 // Whether a low-precision node's products take the large-tile kernels (their
 // operands are the packed copies, aligned when the node's first column is a
 // multiple of 8 and its width k is too).
-bool tn_proj(const Op &o, int64_t m) {
-    return o.prec != QRX_FP32 && m >= 256 && o.k >= 256 && o.n2 >= 256 && o.c0 % 8 == 0;
+bool tn_proj(const Op &o, int64_t m, const QrCfg &c) {
+    return c.tiles == 0 && o.prec != QRX_FP32 && m >= 256 && o.k >= 256 && o.n2 >= 256 &&
+           o.c0 % 8 == 0;
 }
-bool tn_upd(const Op &o, int64_t m) {
-    return o.prec != QRX_FP32 && m >= 256 && o.n2 >= 256 && o.c0 % 8 == 0 && o.k % 8 == 0;
+bool tn_upd(const Op &o, int64_t m, const QrCfg &c) {
+    return c.tiles == 0 && o.prec != QRX_FP32 && m >= 256 && o.n2 >= 256 && o.c0 % 8 == 0 &&
+           o.k % 8 == 0;
 }
-int node_splits(const Op &o, int64_t m) {
-    return tn_proj(o, m) ? tn_projection_splits(m, o.k, o.n2) : projection_splits(m, o.k, o.n2, o.prec);
+int node_splits(const Op &o, int64_t m, const QrCfg &c) {
+    return tn_proj(o, m, c) ? tn_projection_splits(m, o.k, o.n2, c.split_target)
+                            : projection_splits(m, o.k, o.n2, o.prec, c.split_target);
 }
 
 bool has_lowp_nodes(const QrCfg &c, const std::vector<Op> &ops) {
@@ -193,7 +200,7 @@ void carve_qr(Carve &cv, int64_t m, int64_t n, const QrCfg &c, const std::vector
     size_t part = 1;
     for (const Op &o : ops)
         if (o.kind == 1) {
-            const size_t s = node_splits(o, m);
+            const size_t s = node_splits(o, m, c);
             part = std::max(part, s * (size_t)o.k * (size_t)o.n2);
         }
     w.part = cv.take<float>(part);
@@ -229,7 +236,7 @@ void carve_qr(Carve &cv, int64_t m, int64_t n, const QrCfg &c, const std::vector
         }
         size_t a2 = 0;
         for (const Op &o : ops)
-            if (o.kind == 1 && tn_proj(o, m)) a2 = std::max(a2, (size_t)w.ldc * (size_t)o.n2);
+            if (o.kind == 1 && tn_proj(o, m, c)) a2 = std::max(a2, (size_t)w.ldc * (size_t)o.n2);
         if (a2) {
             w.a2h = cv.take<uint16_t>(a2);
             if (split) w.a2l = cv.take<uint16_t>(a2);
@@ -324,8 +331,8 @@ int run_qr(qrx_handle h, hipStream_t s, int64_t m, int64_t n, float *W, int64_t 
             float *A2 = W + (o.c0 + o.k) * ldw;
             float *R12 = R + o.c0 + (o.c0 + o.k) * ldr;
             float *cm = ws.colmax + o.c0 + o.k;
-            const int splits = node_splits(o, m);
-            const bool big_p = tn_proj(o, m), big_u = tn_upd(o, m);
+            const int splits = node_splits(o, m, c);
+            const bool big_p = tn_proj(o, m, c), big_u = tn_upd(o, m, c);
             // column max-abs of the updated A2 is read later only by scaled low-precision
             // projections inside A2 (width > cutoff) and by the TSQR panel's scaling
             float *cm_out = (c.alg == 1 || (o.n2 > c.c && o.prec != QRX_FP32 && c.scaling)) ? cm
@@ -750,9 +757,12 @@ int resolve_batched(const qrx_qr_opts *o, QrCfg &c) {
     if (o->panel_width != 0 && o->panel_width != kBPanel) return QRX_EINVAL;
     if (o->cutoff < 0 || o->block_rows < 0) return QRX_EINVAL;
     if (o->no_col_scaling < 0 || o->no_col_scaling > 1) return QRX_EINVAL;
+    if (o->gemm_tiles != 0 || o->split_target != 0) return QRX_EINVAL;
     c.prec = o->gemm_prec;
     c.alg = 0;
     c.nb = kBPanel;
+    c.tiles = 0;
+    c.split_target = 0;
     int cut = o->cutoff ? o->cutoff : 64;
     if (cut < c.nb) cut = c.nb;
     c.c = (int)round_up(cut, c.nb);
@@ -831,6 +841,10 @@ int upload_batched(hipStream_t s, Carve &cv, std::vector<BProb> &hp, const BPlan
 }
 
 }  // namespace
+
+namespace qrx {
+int handle_device(qrx_handle h) { return h ? h->device : -1; }
+}  // namespace qrx
 
 extern "C" {
 

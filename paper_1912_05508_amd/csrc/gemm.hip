@@ -297,11 +297,12 @@ static bool aligned16(const void *p) { return (((uintptr_t)p) & 15) == 0; }
 // Split-K count of the projection: about 1024 workgroups over the output tiles
 // (FP32: 128 x 128; low precision: 256 x 128 when k >= 256 and n2 >= 128,
 // else 128 x 128), at least 512 rows per split, at most 256 splits.
-int projection_splits(int64_t m, int64_t k, int64_t n2, int prec) {
+int projection_splits(int64_t m, int64_t k, int64_t n2, int prec, int target) {
     int64_t tm = 128;
     if (prec != QRX_FP32 && prec != QRX_FP16X3 && k >= 256 && n2 >= 128) tm = 256;
     const int64_t tiles = ((k + tm - 1) / tm) * ((n2 + 127) / 128);
-    int64_t want = (1024 + tiles - 1) / tiles;
+    const int64_t tgt = target > 0 ? target : 1024;   // workgroups to aim at
+    int64_t want = (tgt + tiles - 1) / tiles;
     int64_t maxs = (m + 511) / 512;
     if (want > maxs) want = maxs;
     if (want < 1) want = 1;

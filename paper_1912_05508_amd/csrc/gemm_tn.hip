@@ -298,9 +298,10 @@ bool tn_eligible(int64_t rows, int64_t cols, int64_t ld_a, int64_t ld_b, const v
     return rows >= 256 && cols >= 256 && ld_a % 8 == 0 && ld_b % 8 == 0 && a16(a) && a16(b);
 }
 
-int tn_projection_splits(int64_t m, int64_t k, int64_t n2) {
+int tn_projection_splits(int64_t m, int64_t k, int64_t n2, int target) {
     const int64_t tiles = ((k + tn::BM - 1) / tn::BM) * ((n2 + tn::BN - 1) / tn::BN);
-    int64_t want = (256 + tiles - 1) / tiles;      // one workgroup per CU
+    const int64_t tgt = target > 0 ? target : 256;   // default: one workgroup per CU
+    int64_t want = (tgt + tiles - 1) / tiles;
     const int64_t maxs = (m + 1023) / 1024;        // at least 1024 rows per split
     if (want > maxs) want = maxs;
     if (want < 1) want = 1;

@@ -16,6 +16,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace qrx {
 
+// Device index of a handle (-1 if it has none).
+int handle_device(qrx_handle h);
+
 // Exponent E with v = f 2^E, f in [0.5, 1); the power of two 2^(target - E)
 // brings max-abs v into [2^(target-1), 2^target). Zero / non-finite -> 1.
 QRX_DEV float pow2_scale(float v, int target) {
@@ -151,13 +154,14 @@ hipError_t launch_update_lp(hipStream_t s, int prec, int scaling, int64_t m, int
                             int64_t n2, const uint16_t *qr, const uint16_t *qrl, int64_t ldq,
                             const uint16_t *rh, const uint16_t *rhl, int64_t ldh, float *A2,
                             int64_t lda, const float *uscale, float *colmax, float *cmpart);
-int projection_splits(int64_t m, int64_t k, int64_t n2, int prec);
+// Row splits of a projection: about `target` workgroups (0 = default).
+int projection_splits(int64_t m, int64_t k, int64_t n2, int prec, int target);
 // Large-tile products (gemm_tn.hip): 256 x 256 tiles on 16-bit operands with
 // 16-byte aligned rows; tn_eligible tells whether a product of rows x cols
 // outputs can use them.
 bool tn_eligible(int64_t rows, int64_t cols, int64_t ld_a, int64_t ld_b, const void *a,
                  const void *b);
-int tn_projection_splits(int64_t m, int64_t k, int64_t n2);
+int tn_projection_splits(int64_t m, int64_t k, int64_t n2, int target);
 hipError_t launch_pack_cols(hipStream_t s, int prec, int scaling, int64_t m, int64_t n2,
                             const float *A2, int64_t lda, const float *colmax, uint16_t *bh,
                             uint16_t *bl, int64_t ldb);

@@ -176,3 +176,27 @@ def test_node_reorth_restores_orthogonality(qrx, prec, orth_bound, kappa_bound):
     assert orth < orth_bound
     assert s[0] / s[-1] < kappa_bound
     assert M.qr_backward_error(A, Q, R) < (2e-6 if prec == "fp32" else 4e-3)
+
+
+@pytest.mark.parametrize("prec,be_bound", [("fp16", 4e-3), ("bf16", 3e-2), ("fp16x3", 2e-6)])
+@pytest.mark.parametrize("m,n", [(4096, 1024), (3000, 768)])
+def test_lowprec_large_tiles(qrx, prec, be_bound, m, n):
+    # nodes with >= 256 rows and columns of output take the 256 x 256 tile kernels
+    # (ragged tiles at 3000 x 768: top node 384 | 384); the 128-row tile family
+    # and other projection splits compute the same products in another order
+    p = synth.scaled_config("c2", m, n, seed=1)
+    Qe, Re = G.rmgs(p.A.astype(np.float64), cutoff=128, prec=prec)
+    orth_e = M.orthogonality(Qe)
+    Rs = []
+    for kw in (dict(), dict(gemm_tiles=1), dict(split_target=128), dict(split_target=1024)):
+        Q, R, st = _run(qrx, p.A, prec=prec, cutoff=128, **kw)
+        assert st == 0
+        be = M.qr_backward_error(p.A, Q, R)
+        orth = M.orthogonality(Q)
+        print(f"{prec} {m}x{n} {kw}: be={be:.2e} orth={orth:.2e} emulated orth={orth_e:.2e}")
+        assert M.upper_triangular_ok(R)
+        assert be < be_bound
+        assert orth < 4 * orth_e + 1e-5
+        Rs.append(R)
+    for R in Rs[1:]:
+        assert np.abs(R - Rs[0]).max() / np.abs(Rs[0]).max() < 20 * be_bound
