@@ -6,8 +6,8 @@
 //   update A2 -= Q1 R12: A = Qr (row r of Q1, columns = K), B = Rh (column j
 //     of the packed R12, rows = K).
 // One workgroup of 8 waves computes a 256 x 256 tile (each wave 128 x 64 with
-// 16x16x32 MFMAs, FP32 accumulation) through double-buffered LDS stages (64
-// deep), one barrier per stage; workgroups go to the XCDs in contiguous tile
+// 16x16x32 MFMAs, FP32 accumulation) through double-buffered, XOR-swizzled LDS
+// stages (64 deep), one barrier per stage; workgroups go to the XCDs in contiguous tile
 // ranges (rows of tiles that share an operand block run on one L2).
 // Split FP16 (x = hi + lo, lo = fl16(x - hi)) stages the hi and lo tiles of
 // both operands (32 deep) and issues hi*hi, hi*lo and lo*hi for every fragment
@@ -25,16 +25,21 @@ constexpr int WM = 2, WN = 4, NT = WM * WN * 64;
 constexpr int FM = BM / WM / 16, FN = BN / WN / 16;
 constexpr int kXcds = 8;
 // Stage geometry: plain products stage A and B 64 deep; split products stage
-// A_hi, A_lo, B_hi, B_lo 32 deep (the same 160 KB of LDS, double-buffered).
+// A_hi, A_lo, B_hi, B_lo 32 deep (128 KB of LDS either way, double-buffered).
+// Rows are unpadded; the 16-byte piece q of row r is stored at piece
+// q ^ ((r / RP) mod QP), RP = rows per 256 bytes, so that the 16 rows a
+// fragment read touches in one piece column hit 16 different bank groups.
 template <bool SPLIT>
 struct Geo {
     static constexpr int BK = SPLIT ? 32 : 64;
     static constexpr int NTILE = SPLIT ? 4 : 2;
-    static constexpr int LS = BK + 8;                 // row stride (16-bit elements)
+    static constexpr int LS = BK;                     // row stride (16-bit elements)
     static constexpr int TS = BM * LS;                // one tile
     static constexpr int QP = BK / 8;                 // 16-byte pieces per row
+    static constexpr int RP = 128 / BK;               // rows per 256 bytes
     static constexpr int PT = BM * QP / NT;           // pieces per thread and tile
-    static_assert(BM == BN && PT * NT == BM * QP, "loader mapping");
+    static_assert(BM == BN && PT * NT == BM * QP && QP * RP == 16, "loader mapping");
+    QRX_DEV static int off(int r, int q) { return r * LS + ((q ^ ((r / RP) & (QP - 1))) * 8); }
 };
 
 QRX_DEV int64_t xcd_order(int64_t b, int64_t nt) {
@@ -134,7 +139,7 @@ __global__ __launch_bounds__(tn::NT) void tn_mma_kernel(
 #pragma unroll
             for (int p = 0; p < PT; ++p) {
                 const int e = t + p * NT, r = e / QP, q = e % QP;
-                *reinterpret_cast<uint4 *>(L + (buf * NTILE + x) * TS + r * LS + q * 8) = rg[x][p];
+                *reinterpret_cast<uint4 *>(L + (buf * NTILE + x) * TS + G::off(r, q)) = rg[x][p];
             }
     };
     using V8 = typename std::conditional<std::is_same<E, _Float16>::value, f16x8, bf16x8>::type;
@@ -147,19 +152,20 @@ __global__ __launch_bounds__(tn::NT) void tn_mma_kernel(
     for (int64_t s = s0; s < s1; ++s) {
         const int buf = (int)((s - s0) & 1);
         if (s + 1 < s1) gload(s + 1);
-        const E *a = L + (buf * NTILE) * TS + (wm * (BM / WM) + rl) * LS + kq * 8;
-        const E *b = L + (buf * NTILE + NTILE / 2) * TS + (wn * (BN / WN) + rl) * LS + kq * 8;
+        const E *a = L + (buf * NTILE) * TS;
+        const E *b = L + (buf * NTILE + NTILE / 2) * TS;
+        const int ar = wm * (BM / WM) + rl, br = wn * (BN / WN) + rl;
         if constexpr (SPLIT) {
             V8 bh[FN], bl[FN];
 #pragma unroll
             for (int f = 0; f < FN; ++f) {
-                bh[f] = *reinterpret_cast<const V8 *>(b + f * 16 * LS);
-                bl[f] = *reinterpret_cast<const V8 *>(b + TS + f * 16 * LS);
+                bh[f] = *reinterpret_cast<const V8 *>(b + G::off(br + f * 16, kq));
+                bl[f] = *reinterpret_cast<const V8 *>(b + TS + G::off(br + f * 16, kq));
             }
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
-                const V8 ah = *reinterpret_cast<const V8 *>(a + i * 16 * LS);
-                const V8 al = *reinterpret_cast<const V8 *>(a + TS + i * 16 * LS);
+                const V8 ah = *reinterpret_cast<const V8 *>(a + G::off(ar + i * 16, kq));
+                const V8 al = *reinterpret_cast<const V8 *>(a + TS + G::off(ar + i * 16, kq));
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
                     acc[i][j] = mma<E>(ah, bh[j], acc[i][j]);
@@ -172,9 +178,11 @@ __global__ __launch_bounds__(tn::NT) void tn_mma_kernel(
             for (int kk = 0; kk < BK; kk += 32) {
                 V8 af[FM], bf[FN];
 #pragma unroll
-                for (int f = 0; f < FM; ++f) af[f] = *reinterpret_cast<const V8 *>(a + f * 16 * LS + kk);
+                for (int f = 0; f < FM; ++f)
+                    af[f] = *reinterpret_cast<const V8 *>(a + G::off(ar + f * 16, kk / 8 + kq));
 #pragma unroll
-                for (int f = 0; f < FN; ++f) bf[f] = *reinterpret_cast<const V8 *>(b + f * 16 * LS + kk);
+                for (int f = 0; f < FN; ++f)
+                    bf[f] = *reinterpret_cast<const V8 *>(b + G::off(br + f * 16, kk / 8 + kq));
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll

@@ -218,19 +218,29 @@ QRX_DEV void chol_inv(double *S, double *Xs, double *T, int t) {
                               : ((j - W == i) ? 1.0 : 0.0);
         }
     }
-    // row q (held as M[r]) into buffer q & 1: left entries j <= q zeroed, pivot apart
+    // row q = i0 + r of this thread into buffer q & 1: left entries j <= q zeroed,
+    // the pivot in its own slot; the row is picked from M by selects
     auto put_row = [&](int q, int r) {
+        double v[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) v[c] = M[0][c];
+#pragma unroll
+        for (int rr = 1; rr < RB; ++rr)
+#pragma unroll
+            for (int c = 0; c < CB; ++c) v[c] = (r == rr) ? M[rr][c] : v[c];
         double *dst = T + (q & 1) * RL;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             const int j = j0 + c;
-            dst[j] = (j <= q) ? 0.0 : M[r][c];
-            if (j == q) dst[2 * W] = M[r][c];
+            dst[j] = (j <= q) ? 0.0 : v[c];
+            if (j == q) dst[2 * W] = v[c];
         }
     };
     if (i0 == 0) put_row(0, 0);
     __syncthreads();
     for (int k = 0; k < W; ++k) {
+        const int rk = k - i0;            // row k in this thread's block when 0 <= rk < RB
+        const bool own_k = rk >= 0 && rk < RB;
         if (wlast > k) {
             const double *row = T + (k & 1) * RL;
             const double d = row[2 * W];
@@ -247,23 +257,17 @@ QRX_DEV void chol_inv(double *S, double *Xs, double *T, int t) {
             for (int r = 0; r < RB; ++r)
 #pragma unroll
                 for (int c = 0; c < CB; ++c) M[r][c] = fma(-rr[r], rc[c], M[r][c]);
-            const int rk = k - i0;
+            if (k + 1 < W && rk + 1 >= 0 && rk + 1 < RB) put_row(k + 1, rk + 1);
+            if (own_k) {
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
-                if (rk == r) sc[r] = rinv;
-            const int rn = rk + 1;
-            if (k + 1 < W) {
-#pragma unroll
-                for (int r = 0; r < RB; ++r)
-                    if (rn == r) put_row(k + 1, r);
+                for (int r = 0; r < RB; ++r) sc[r] = (rk == r) ? rinv : sc[r];
             }
-        } else if (k - i0 >= 0 && k - i0 < RB) {
+        } else if (own_k) {
             // the wave is done, but this thread still needs its scale for row k
             const double d = T[(k & 1) * RL + 2 * W];
             const double rinv = (d > 0.0) ? rsqrt_d(d) : 0.0;
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
-                if (k - i0 == r) sc[r] = rinv;
+            for (int r = 0; r < RB; ++r) sc[r] = (rk == r) ? rinv : sc[r];
         }
         __syncthreads();
     }
