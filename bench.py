@@ -197,7 +197,9 @@ def lls_bench(h, prec, m_n, repeats, precs=("fp16x3", "fp32", "fp16")):
         i = infos[-1]
         out[pr] = {"time_to_solution_ms": 1e3 * times[len(times) // 2], "iters": i["iters"],
                    "eta_F": i["eta_F"], "status": i["status"], "qr_ms": i["qr_ms"],
-                   "krylov_ms": i["krylov_ms"]}
+                   "krylov_ms": i["krylov_ms"],
+                   # the direct solve x0 = R^{-1} Q^T b with the same factors (the start)
+                   "direct_solve_eta_F": i["eta_start"]}
     return {"workload": f"{name}: {A.shape[0]} x {A.shape[1]}, log-uniform spectrum cond 1e6, "
                         "b = A x* + 1e-8 g, LSQR right-preconditioned by R to eta_F <= 1e-10",
             **out}

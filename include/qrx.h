@@ -93,6 +93,10 @@ typedef struct {
     double tol;           /* target for eta_F (0 = 1e-10); must be >= 0 */
     int max_iter;         /* Krylov iteration cap (0 = 200, the cap of Sec. 4.2.3) */
     int use_x0;           /* 1 = x holds the starting iterate on entry */
+    int zero_start;       /* without use_x0: 0 = start from the direct solution
+                             x0 = R^{-1} Q^T b of the factorisation (Alg. 1 with the
+                             low-precision factors; default), 1 = start from x = 0. With a
+                             caller-supplied R (qrx_lls_solve_with_R) the start is x = 0. */
 } qrx_lls_opts;
 
 /* Result of a least-squares solve (host memory). */
@@ -105,6 +109,8 @@ typedef struct {
     double normA_F;       /* ||A||_F */
     double qr_ms;         /* device time of the factorisation */
     double krylov_ms;     /* device time of the iteration and checks */
+    double eta_start;     /* eta_F of the starting iterate (for the default start: the
+                             accuracy of the direct low-precision QR solve) */
 } qrx_lls_info;
 
 /* Per-kernel timing record (see qrx_timing_*). */
@@ -200,7 +206,8 @@ int qrx_lls_batched_workspace_size(qrx_handle h, int batch, const int64_t *m, co
 /* x_i = argmin ||A_i x - b_i|| (b_i FP64 of length m[i], x_i FP64 of length
  * n[i]) by the batched QR followed by R-preconditioned LSQR with FP64 vectors,
  * certified with a double-double residual (eta_F <= tol, as qrx_lls_solve).
- * LSQR only (method 0) and no starting iterate (use_x0 = 0). A_i and b_i are
+ * LSQR only (method 0) and no starting iterate (use_x0 = 0); the iteration
+ * starts from x = 0 (zero_start is ignored, eta_start is 0). A_i and b_i are
  * not modified. info[i] as for qrx_lls_solve; qr_ms and krylov_ms are the
  * device times of the whole batch's two phases. */
 int qrx_lls_solve_batched(qrx_handle h, int batch, const int64_t *m, const int64_t *n,

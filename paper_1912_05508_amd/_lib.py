@@ -27,13 +27,13 @@ class qrx_qr_opts(C.Structure):
 
 class qrx_lls_opts(C.Structure):
     _fields_ = [("qr", qrx_qr_opts), ("method", C.c_int), ("tol", C.c_double),
-                ("max_iter", C.c_int), ("use_x0", C.c_int)]
+                ("max_iter", C.c_int), ("use_x0", C.c_int), ("zero_start", C.c_int)]
 
 
 class qrx_lls_info(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("restarts", C.c_int),
                 ("eta_F", C.c_double), ("resid_norm", C.c_double), ("normA_F", C.c_double),
-                ("qr_ms", C.c_double), ("krylov_ms", C.c_double)]
+                ("qr_ms", C.c_double), ("krylov_ms", C.c_double), ("eta_start", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -150,8 +150,10 @@ def qr_opts(prec="fp32", panel_width=0, cutoff=0, col_scaling=True, reorth=True,
     return o
 
 
-def lls_opts(prec="fp32", method="lsqr", tol=1e-10, max_iter=200, use_x0=False, **qr_kw):
+def lls_opts(prec="fp32", method="lsqr", tol=1e-10, max_iter=200, use_x0=False, zero_start=False,
+             **qr_kw):
     o = qrx_lls_opts()
+    o.zero_start = 1 if zero_start else 0
     o.qr = qr_opts(prec, **qr_kw)
     o.method = {"lsqr": 0, "cgls": 1}[method] if isinstance(method, str) else int(method)
     o.tol = tol

@@ -478,6 +478,7 @@ void carve_kr(Carve &cv, int64_t m, int64_t n, KrWork &k) {
 struct KrCfg {
     int method, max_iter;
     double tol;
+    bool direct;   // start from x0 = R^{-1} Q^T b when Q is at hand
 };
 
 int resolve_lls(const qrx_lls_opts *o, KrCfg &k) {
@@ -488,6 +489,8 @@ int resolve_lls(const qrx_lls_opts *o, KrCfg &k) {
     if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return QRX_EINVAL;
     if (o->max_iter < 0) return QRX_EINVAL;
     if (o->use_x0 < 0 || o->use_x0 > 1) return QRX_EINVAL;
+    if (o->zero_start < 0 || o->zero_start > 1) return QRX_EINVAL;
+    k.direct = o->use_x0 == 0 && o->zero_start == 0;
     k.method = o->method;
     k.tol = o->tol > 0.0 ? o->tol : 1e-10;
     k.max_iter = o->max_iter ? o->max_iter : 200;
@@ -516,7 +519,7 @@ int certify(qrx_handle h, hipStream_t s, int64_t m, int64_t n, int64_t np, const
     QRX_TRY(kr_norm(s, k.ssq, nblocks(n), k.st, S_ZNORM, 1));
     QRX_TRY(kr_axpby(s, np, k.st, -2, -1, k.x, -1, 1.0, nullptr, k.vt2, k.ssq));
     QRX_TRY(kr_norm(s, k.ssq, nblocks(np), k.st, S_XNORM, 1));
-    QRX_TRY(kr_eta(s, k.st, tol));
+    QRX_TRY(kr_eta(s, k.st, tol, compat_scale(m, n, tol)));
     r.end("certify", 2.0 * 2.0 * m * n, 8.0 * m * n + 24.0 * m);
     return QRX_OK;
 }
@@ -530,8 +533,8 @@ int certify(qrx_handle h, hipStream_t s, int64_t m, int64_t n, int64_t np, const
 // returned. Blocks until done.
 int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A, int64_t lda,
                const float *R, int64_t ldr, const double *b, double *x_user, bool use_x0,
-               const KrCfg &cfg, KrWork &k, qrx_lls_info *info, double normA_host,
-               double rho) {
+               const float *Q, int64_t ldq, const KrCfg &cfg, KrWork &k, qrx_lls_info *info,
+               double normA_host, double rho) {
     const int64_t np = round_up(n, kTrsvBlock);
     const double tol = cfg.tol;
     double *st = k.st;
@@ -544,7 +547,16 @@ int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A
     }
     // the padded tails [n, np) of every n-vector must stay exactly zero
     for (double *vec : {k.x, k.xbest, k.v, k.t, k.d, k.z, k.y, k.vt}) QRX_TRY(kr_zero(s, np, vec));
-    if (use_x0) QRX_TRY(hipMemcpyAsync(k.x, x_user, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (use_x0) {
+        QRX_TRY(hipMemcpyAsync(k.x, x_user, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else if (cfg.direct && Q && R) {
+        // the direct solution of Alg. 1 with the computed factors: x0 = R^{-1} (Q^T b)
+        Rec r(h, s);
+        QRX_TRY(kr_gemv_t(s, m, n, Q, ldq, b, k.part_t));
+        QRX_TRY(kr_combine_n(s, n, k.part_t, k.splits_t, k.z, k.ssq));
+        QRX_TRY(kr_trmv(s, np, k.X, k.z, k.x, k.tpart, 0));
+        r.end("direct_start", 2.0 * m * n + (double)np * (np + 1), 4.0 * m * n + 8.0 * m + 4.0 * np * (np + 1));
+    }
     for (int i = 0; i < S_COUNT; ++i) QRX_TRY(kr_set(s, st, i, 0.0));
     QRX_TRY(kr_set(s, st, S_NORMA, normA_host));
     QRX_TRY(kr_set(s, st, S_GAMMA_TOL, 1.0));
@@ -592,6 +604,7 @@ int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A
 
     double score = 0.0;
     if ((rc = certify_now(score))) return rc;
+    info->eta_start = hs[S_ETA];
     double best = score, best_eta = hs[S_ETA], best_rn = hs[S_RNORM];
     QRX_TRY(kr_copy(s, np, k.x, k.xbest));
     auto keep_if_better = [&](double sc) -> int {
@@ -1085,8 +1098,8 @@ static int lls_common(qrx_handle h, int64_t m, int64_t n, const float *A, int64_
             for (double v : css) mx = std::max(mx, v);
             rho = std::sqrt(mx);
         }
-        rc = run_krylov(h, stream, m, n, A, lda, R, ldR, b, x, opts && opts->use_x0, kc, kw, info,
-                        normA, rho);
+        rc = run_krylov(h, stream, m, n, A, lda, R, ldR, b, x, opts && opts->use_x0,
+                        with_qr ? W : nullptr, ldw, kc, kw, info, normA, rho);
         if (rc) return rc;
     }
     hipEventRecord(e2, stream);

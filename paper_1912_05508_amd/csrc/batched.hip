@@ -420,9 +420,11 @@ QRX_DEV void wg_gemv_t(const BProb &p, const double *u, double *z, int t) {
 }
 
 // Certification of x: q = b - A x (double-double), z = A^T q; returns the score
-// min(eta_F, ||r|| / (||A||_F ||x|| + ||b||)) and sets eta, rnorm.
+// min(eta_F, cscale ||r|| / (||A||_F ||x|| + ||b||)) (see compat_scale) and sets
+// eta, rnorm.
 QRX_DEV double wg_certify(const BProb &p, const double *x, double *z, double *q, double normA,
-                          double bnorm, double &eta, double &rnorm, double *sh, int t) {
+                          double bnorm, double &eta, double &rnorm, double *sh, int t,
+                          double tol) {
     double ss = 0.0;
     for (int64_t r = t; r < p.m; r += BT) {
         double h = p.b[r], l = 0.0;
@@ -442,7 +444,7 @@ QRX_DEV double wg_certify(const BProb &p, const double *x, double *z, double *q,
     xx = bsum(xx, sh);
     eta = (rnorm > 0.0 && normA > 0.0) ? sqrt(zz) / (normA * rnorm) : 0.0;
     const double den = normA * sqrt(xx) + bnorm;
-    const double s1 = den > 0.0 ? rnorm / den : 0.0;
+    const double s1 = den > 0.0 ? compat_scale(p.m, p.n, tol) * (rnorm / den) : 0.0;
     return fmin(eta, s1);
 }
 
@@ -490,7 +492,7 @@ __global__ __launch_bounds__(BT) void blsqr_kernel(const BProb *__restrict__ pro
     int iters = 0, restarts = 0, stall = 0, status = QRX_ENOCONV;
     for (int outer = 0;; ++outer) {
         // certify the current x; q = residual, z = A^T q
-        const double score = wg_certify(p, V.x, V.z, p.q, normA, bnorm, eta, rnorm, sh, t);
+        const double score = wg_certify(p, V.x, V.z, p.q, normA, bnorm, eta, rnorm, sh, t, tol);
         if (score < best) {
             if (score < 0.5 * best) stall = 0; else ++stall;
             best = score;

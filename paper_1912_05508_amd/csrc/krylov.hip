@@ -247,13 +247,13 @@ __global__ __launch_bounds__(KT) void lsqr_xd_kernel(int64_t n, const double *__
 __global__ void lsqr_shift_kernel(double *st) { st[S_DCOEF] = st[S_DCOEF_NEXT]; }
 
 // eta_F = ||z|| / (||A||_F ||r||) from the certification pass, and the
-// compatible-system ratio ||r|| / (||A||_F ||x|| + ||b||); the score is the
-// smaller of the two (converged when score <= tol).
-__global__ void eta_kernel(double *st, double tol) {
+// compatible-system ratio ||r|| / (||A||_F ||x|| + ||b||) times cscale (see
+// compat_scale); the score is the smaller of the two (converged when score <= tol).
+__global__ void eta_kernel(double *st, double tol, double cscale) {
     double nr = st[S_RNORM], nz = st[S_ZNORM], na = st[S_NORMA];
     double e = (nr > 0.0 && na > 0.0) ? nz / (na * nr) : 0.0;
     double den = na * st[S_XNORM] + st[S_BNORM];
-    double s1 = den > 0.0 ? nr / den : 0.0;
+    double s1 = den > 0.0 ? cscale * (nr / den) : 0.0;
     st[S_ETA] = e;
     st[S_SCORE] = fmin(e, s1);
     st[S_CONV] = (fmin(e, s1) <= tol) ? 1.0 : 0.0;
@@ -397,8 +397,8 @@ hipError_t kr_lsqr_shift(hipStream_t s, double *st) {
     hipLaunchKernelGGL(lsqr_shift_kernel, dim3(1), dim3(1), 0, s, st);
     return hipGetLastError();
 }
-hipError_t kr_eta(hipStream_t s, double *st, double tol) {
-    hipLaunchKernelGGL(eta_kernel, dim3(1), dim3(1), 0, s, st, tol);
+hipError_t kr_eta(hipStream_t s, double *st, double tol, double cscale) {
+    hipLaunchKernelGGL(eta_kernel, dim3(1), dim3(1), 0, s, st, tol, cscale);
     return hipGetLastError();
 }
 hipError_t kr_lsqr_restart(hipStream_t s, double *st, int phase) {

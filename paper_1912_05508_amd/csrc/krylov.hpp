@@ -47,7 +47,7 @@ hipError_t kr_lsqr_scalar(hipStream_t s, double *st, double tol);
 hipError_t kr_lsqr_xd(hipStream_t s, int64_t n, const double *st, const double *t, double *d,
                       double *x, double *v, int first);
 hipError_t kr_lsqr_shift(hipStream_t s, double *st);
-hipError_t kr_eta(hipStream_t s, double *st, double tol);
+hipError_t kr_eta(hipStream_t s, double *st, double tol, double cscale);
 hipError_t kr_lsqr_restart(hipStream_t s, double *st, int phase);
 hipError_t kr_cgls_alpha(hipStream_t s, double *st);
 hipError_t kr_cgls_beta(hipStream_t s, double *st, double tol);

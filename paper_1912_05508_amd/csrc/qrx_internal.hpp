@@ -19,6 +19,16 @@ namespace qrx {
 // Device index of a handle (-1 if it has none).
 int handle_device(qrx_handle h);
 
+// The compatible-system ratio ||r|| / (||A||_F ||x|| + ||b||) certifies a
+// solution at tol for square systems, where eta_F is undefined (r is rounding
+// noise); for m > n only at the rounding level of the residual, which is
+// where the least-squares residual itself vanishes (a consistent system).
+// Returned: the factor that scales the ratio onto the tol scale.
+__host__ __device__ inline double compat_scale(int64_t m, int64_t n, double tol) {
+    const double lim = 1e3 * 1.1102230246251565e-16;
+    return (m == n || tol <= lim) ? 1.0 : tol / lim;
+}
+
 // Exponent E with v = f 2^E, f in [0.5, 1); the power of two 2^(target - E)
 // brings max-abs v into [2^(target-1), 2^target). Zero / non-finite -> 1.
 QRX_DEV float pow2_scale(float v, int target) {

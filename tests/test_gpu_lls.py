@@ -63,7 +63,7 @@ def _loguniform(m, n, cond, seed=0, noise="rel1e-6"):
 @pytest.mark.parametrize("prec", ["fp32", "fp16x3"])
 @pytest.mark.parametrize("method", ["lsqr", "cgls"])
 def test_fp32_quality_paths_cond1e6_to_1e10(qrx, method, prec):
-    # FP32 products, or split FP16 products (hi*hi + 2^-11 (hi*lo + lo*hi)),
+    # FP32 products, or split FP16 products (hi*hi + hi*lo + lo*hi),
     # with node re-orthogonalisation give an R that preconditions a
     # kappa = 1e6 problem to ~1: a handful of iterations.
     A, b = _loguniform(2048, 256, 1e6)
@@ -173,3 +173,26 @@ def test_deterministic(qrx):
     x1, i1 = _solve(qrx, A, b, prec="fp16", cutoff=32, max_iter=5000)
     x2, i2 = _solve(qrx, A, b, prec="fp16", cutoff=32, max_iter=5000)
     assert np.array_equal(x1, x2) and i1["iters"] == i2["iters"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_direct_start(qrx, prec):
+    # the default start is the direct solution x0 = R^{-1} Q^T b of the computed
+    # factors (Alg. 1 with them); tol = 1 certifies that start as it is
+    A, b = _loguniform(2048, 256, 1e4, seed=7)
+    x0, i0 = _solve(qrx, A, b, prec=prec, cutoff=64, tol=1.0)
+    assert i0["iters"] == 0 and i0["status"] == 0
+    eta0 = M.eta_F(A, b, x0)
+    print(prec, "direct solve eta", eta0, i0["eta_start"])
+    assert abs(i0["eta_start"] - eta0) <= 1e-2 * eta0
+    # its accuracy is that of the low-precision QR (eta ~ kappa u at most)
+    u = 6e-8 if prec == "fp32" else 4.9e-4
+    assert eta0 < 1e4 * u
+    # from it, or from zero, the iteration reaches the same target
+    xd, idr = _solve(qrx, A, b, prec=prec, cutoff=64, tol=1e-10, max_iter=5000)
+    xz, izr = _solve(qrx, A, b, prec=prec, cutoff=64, tol=1e-10, max_iter=5000, zero_start=True)
+    assert idr["status"] == 0 and izr["status"] == 0
+    assert M.eta_F(A, b, xd) <= 1.05e-10 and M.eta_F(A, b, xz) <= 1.05e-10
+    assert abs(izr["eta_start"] - M.eta_F(A, b, np.zeros(256))) <= 1e-2 * izr["eta_start"]
+    assert idr["eta_start"] < izr["eta_start"]
+    assert idr["iters"] <= izr["iters"]
