@@ -74,28 +74,47 @@ __global__ __launch_bounds__(KT) void gemv_t_kernel(int64_t m, int64_t n,
     for (int i = threadIdx.x; i < GT_ROWS; i += KT) us[i] = (i < cnt) ? u[rs + i] : 0.0;
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int q = 0; q < GT_COLS / 4; ++q) {
-        const int64_t j = (int64_t)blockIdx.x * GT_COLS + wv * (GT_COLS / 4) + q;
-        if (j >= n) break;
-        const float *a = A + j * lda + rs;
-        double acc = 0.0;
-        if (vec) {
-            for (int i = lane * 4; i < cnt; i += 256) {
-                if (i + 3 < cnt) {
-                    float4 e = *reinterpret_cast<const float4 *>(a + i);
-                    acc = fma((double)e.x, us[i], acc);
-                    acc = fma((double)e.y, us[i + 1], acc);
-                    acc = fma((double)e.z, us[i + 2], acc);
-                    acc = fma((double)e.w, us[i + 3], acc);
-                } else {
-                    for (int k = 0; k < 4 && i + k < cnt; ++k) acc = fma((double)a[i + k], us[i + k], acc);
+    constexpr int CW = GT_COLS / 4;   // columns per wave, swept together (one u read each)
+    const int64_t j0 = (int64_t)blockIdx.x * GT_COLS + wv * CW;
+    const float *a[CW];
+    bool jin[CW];
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+        jin[q] = j0 + q < n;
+        a[q] = A + (jin[q] ? j0 + q : n - 1) * lda + rs;   // out of range: read a valid column
+    }
+    double acc[CW];
+#pragma unroll
+    for (int q = 0; q < CW; ++q) acc[q] = 0.0;
+    if (vec) {
+        for (int i = lane * 4; i < cnt; i += 256) {
+            if (i + 3 < cnt) {
+                float4 e[CW];
+#pragma unroll
+                for (int q = 0; q < CW; ++q) e[q] = *reinterpret_cast<const float4 *>(a[q] + i);
+                const double u0 = us[i], u1 = us[i + 1], u2 = us[i + 2], u3 = us[i + 3];
+#pragma unroll
+                for (int q = 0; q < CW; ++q) {
+                    acc[q] = fma((double)e[q].x, u0, acc[q]);
+                    acc[q] = fma((double)e[q].y, u1, acc[q]);
+                    acc[q] = fma((double)e[q].z, u2, acc[q]);
+                    acc[q] = fma((double)e[q].w, u3, acc[q]);
                 }
+            } else {
+                for (int k = 0; k < 4 && i + k < cnt; ++k)
+#pragma unroll
+                    for (int q = 0; q < CW; ++q) acc[q] = fma((double)a[q][i + k], us[i + k], acc[q]);
             }
-        } else {
-            for (int i = lane; i < cnt; i += 64) acc = fma((double)a[i], us[i], acc);
         }
-        acc = wave_sum_d(acc);
-        if (lane == 0) part[s * n + j] = acc;
+    } else {
+        for (int i = lane; i < cnt; i += 64)
+#pragma unroll
+            for (int q = 0; q < CW; ++q) acc[q] = fma((double)a[q][i], us[i], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+        const double v = wave_sum_d(acc[q]);
+        if (lane == 0 && jin[q]) part[s * n + j0 + q] = v;
     }
 }
 

@@ -51,19 +51,21 @@ __global__ __launch_bounds__(IB) void inv_diag_kernel(int64_t n, const float *__
     for (int i = 0; i < IB; ++i) X[(o + i) + (o + c) * ldx] = Xs[i + c * (IB + 1)];
 }
 
-// C (M x N, ldc) = alpha * A B, FP64 accumulation, all dimensions multiples of
-// 64. A is FP32 or FP64 (element (i, k) at A[i + k*lda], zero where i >= arl
-// or k >= acl); B is FP64 (B[k + j*ldb]). TRI = 1: B is upper triangular (k <= j
-// contributes); TRI = 2: A is upper triangular (k >= i contributes).
-// Workgroup: 64 x 64 tile, thread 4 x 4 outputs, K stages of 16 through LDS.
-template <class TA, int TRI>
+// C (M x N, ldc) = alpha * A B, FP64 accumulation, M and N multiples of BT, K
+// a multiple of 16. A is FP32 or FP64 (element (i, k) at A[i + k*lda], zero
+// where i >= arl or k >= acl); B is FP64 (B[k + j*ldb]). TRI = 1: B is upper
+// triangular (k <= j contributes); TRI = 2: A is upper triangular (k >= i
+// contributes). Workgroup: BT x BT tile, 16 x 16 threads with TM x TM outputs
+// each (TM = BT / 16), K stages of 16 through LDS.
+template <class TA, int TRI, int BT>
 __global__ __launch_bounds__(TT) void tri_gemm_kernel(int64_t M, int64_t N, int64_t K,
                                                       const TA *__restrict__ A, int64_t lda,
                                                       int64_t arl, int64_t acl,
                                                       const double *__restrict__ B, int64_t ldb,
                                                       double *__restrict__ C, int64_t ldc,
                                                       double alpha) {
-    constexpr int BT = 64, BK = 16, LS = BT + 4;
+    constexpr int BK = 16, LS = BT + 4, TM = BT / 16;
+    constexpr int AQ = BT * BK / TT;               // A (and B) elements each thread stages
     __shared__ __align__(16) double As[BK * LS];   // As[k][i]
     __shared__ __align__(16) double Bs[BK * LS];   // Bs[k][j]
     const int t = threadIdx.x;
@@ -72,51 +74,54 @@ __global__ __launch_bounds__(TT) void tri_gemm_kernel(int64_t M, int64_t N, int6
     const int64_t kb = (TRI == 2) ? i0 : 0;
     const int64_t ke = (TRI == 1) ? ((j0 + BT < K) ? j0 + BT : K) : K;
     const int ti = t % 16, tj = t / 16;
-    const int ar = t % 64, akq = t / 64;          // A loads: row ar, k = akq*4 + q
-    const int bk = t % 16, bjq = t / 16;          // B loads: k = bk, column bjq*4 + q
-    double pa[4], pb[4];
+    const int ar = t % BT, akq = t / BT;          // A loads: row ar, k = akq * AQ + q
+    const int bk = t % 16, bjq = t / 16;          // B loads: k = bk, column bjq * AQ + q
+    double pa[AQ], pb[AQ];
     auto load = [&](int64_t k0) {
+        // the triangle's zero side is never read (the strictly lower part of X is not
+        // stored): it is taken as zero here
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t i = i0 + ar, k = k0 + akq * 4 + q;
-            pa[q] = (i < arl && k < acl) ? (double)A[i + k * lda] : 0.0;
-            pb[q] = B[(k0 + bk) + (j0 + bjq * 4 + q) * ldb];
+        for (int q = 0; q < AQ; ++q) {
+            const int64_t i = i0 + ar, k = k0 + akq * AQ + q;
+            pa[q] = (i < arl && k < acl && (TRI != 2 || k >= i)) ? (double)A[i + k * lda] : 0.0;
+            const int64_t kb2 = k0 + bk, jb = j0 + bjq * AQ + q;
+            pb[q] = (TRI != 1 || kb2 <= jb) ? B[kb2 + jb * ldb] : 0.0;
         }
     };
-    double acc[4][4];
+    double acc[TM][TM];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < TM; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+        for (int y = 0; y < TM; ++y) acc[x][y] = 0.0;
     if (kb < ke) load(kb);
     for (int64_t k0 = kb; k0 < ke; k0 += BK) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            As[(akq * 4 + q) * LS + ar] = pa[q];
-            Bs[bk * LS + bjq * 4 + q] = pb[q];
+        for (int q = 0; q < AQ; ++q) {
+            As[(akq * AQ + q) * LS + ar] = pa[q];
+            Bs[bk * LS + bjq * AQ + q] = pb[q];
         }
         __syncthreads();
         if (k0 + BK < ke) load(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; ++kk) {
-            double a[4], b[4];
+            double a[TM], b[TM];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = As[kk * LS + ti * 4 + q];
-                b[q] = Bs[kk * LS + tj * 4 + q];
+            for (int q = 0; q < TM; ++q) {
+                a[q] = As[kk * LS + ti * TM + q];
+                b[q] = Bs[kk * LS + tj * TM + q];
             }
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
+            for (int x = 0; x < TM; ++x)
 #pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+                for (int y = 0; y < TM; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
         }
     }
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
+    for (int y = 0; y < TM; ++y)
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
-            C[(i0 + ti * 4 + x) + (j0 + tj * 4 + y) * ldc] = alpha * acc[x][y];
+        for (int x = 0; x < TM; ++x)
+            C[(i0 + ti * TM + x) + (j0 + tj * TM + y) * ldc] = alpha * acc[x][y];
 }
 
 // ---- applications -----------------------------------------------------------
@@ -186,9 +191,16 @@ template <class TA, int TRI>
 static hipError_t tri_gemm(hipStream_t s, int64_t M, int64_t N, int64_t K, const TA *A,
                            int64_t lda, int64_t arl, int64_t acl, const double *B, int64_t ldb,
                            double *C, int64_t ldc, double alpha) {
+    if (M % 128 == 0 && N % 128 == 0 && (M / 128) * (N / 128) >= 256) {
+        // 128 x 128 tiles (8 x 8 per thread: half the LDS reads per FMA) when they fill the chip
+        const unsigned tiles = (unsigned)((M / 128) * (N / 128));
+        hipLaunchKernelGGL((tri_gemm_kernel<TA, TRI, 128>), dim3(tiles), dim3(TT), 0, s, M, N, K,
+                           A, lda, arl, acl, B, ldb, C, ldc, alpha);
+        return hipGetLastError();
+    }
     const unsigned tiles = (unsigned)((M / 64) * (N / 64));
-    hipLaunchKernelGGL((tri_gemm_kernel<TA, TRI>), dim3(tiles), dim3(TT), 0, s, M, N, K, A, lda,
-                       arl, acl, B, ldb, C, ldc, alpha);
+    hipLaunchKernelGGL((tri_gemm_kernel<TA, TRI, 64>), dim3(tiles), dim3(TT), 0, s, M, N, K, A,
+                       lda, arl, acl, B, ldb, C, ldc, alpha);
     return hipGetLastError();
 }
 
