@@ -51,11 +51,11 @@ def qr_flops(m, n):
 # are the ones the counters were taken on (SHA-1 below); otherwise null.
 MEASURED_TRAFFIC = {
     "gram_panel": {
-        "bytes_per_launch": 60.07e6,
+        "bytes_per_launch": 60.08e6,
         "profile": "profiles/gram_panel_32768x4096_hbm_traffic.txt",
         "sources": {
-            "paper_1912_05508_amd/csrc/gram.hip": "cb6cecd7d0dbb882a3d8a1492e23001c8953c46e",
-            "paper_1912_05508_amd/csrc/gram_common.hpp": "b8492c08d20bc1c535e68baca1f470c3e0889ac7",
+            "paper_1912_05508_amd/csrc/gram.hip": "9767ab43d2a4d2bc25b950874b92942964a257e7",
+            "paper_1912_05508_amd/csrc/gram_common.hpp": "62c3846f798752417729d058dac5a3843afbf235",
         },
     },
 }
