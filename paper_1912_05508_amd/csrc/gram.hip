@@ -22,7 +22,8 @@
 //   gram_pass<Q>    Q = fl32(Q1 X2) in place
 // A sweep stages 64-row chunks of the panel in LDS as FP64; a workgroup owns a
 // contiguous run of chunks and prefetches the next chunk into registers while
-// it computes on the current one. With one sweep (no re-orthogonalisation)
+// it computes on the current one. 64-column panels compute their Gram blocks
+// and Q formation on the FP64 matrix cores. With one sweep (no re-orthogonalisation)
 // the panel is gram_pass<G>, gram_chol (R1 into the R block), gram_pass<Q>.
 #include "gram_common.hpp"
 
@@ -33,6 +34,122 @@ using gram::GT;
 using gram::upk;
 constexpr int CT = 512;          // threads per reduce/Cholesky workgroup
 constexpr int kMaxParts = 512;   // Gram partials (one per sweep workgroup)
+
+// ---------------------------------------------------------------------------
+// 64-column sweeps on the FP64 matrix cores (v_mfma_f64_16x16x4f64: A operand
+// lane l holds A[l % 16][l / 16], B operand B[l / 16][l % 16], result register
+// v of lane l holds D[4 v + l / 16][l % 16]).
+// Gram: the 10 upper 16 x 16 blocks (I, J) of rows^T rows are split over the 4
+// waves (3, 3, 2, 2 blocks), each over all rows of the chunk in steps of 4.
+// Q formation: wave Rb forms rows 16 Rb .. 16 Rb + 15 of rows X, its 4 column
+// blocks over K up to the block's last column (X is upper triangular).
+// ---------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+QRX_DEV d4 mfma64(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// block pairs of wave wv: (I, J) = pair(wv, p) for p < npairs(wv)
+QRX_DEV int npairs(int wv) { return wv < 2 ? 3 : 2; }
+QRX_DEV void pair_of(int wv, int p, int &I, int &J) {
+    // 0: (0,0) (0,1) (0,2)   1: (0,3) (1,1) (1,2)   2: (1,3) (2,2)   3: (2,3) (3,3)
+    const int code = wv * 3 + p;
+    const int Is[12] = {0, 0, 0, 0, 1, 1, 1, 2, 0, 2, 3, 0};
+    const int Js[12] = {0, 1, 2, 3, 1, 2, 3, 2, 0, 3, 3, 0};
+    I = Is[code];
+    J = Js[code];
+}
+
+template <bool DO_Q, bool DO_G>
+QRX_DEV void sweep64(float *__restrict__ P, int64_t ld, int64_t m, int w, int64_t ch0,
+                     int64_t ch1, const double *Xs, double *C, d4 (&acc)[3], int t) {
+    using L = gram::Lds<64>;
+    constexpr int LDC = L::LDC, XLD = L::XLD;
+    constexpr int LPT = CH * 64 / GT;
+    const int lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int li = lane & 15, lk = lane >> 4;
+    const int np = npairs(wv);
+    int PI[3], PJ[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) pair_of(wv, p < np ? p : 0, PI[p], PJ[p]);
+    float pre[LPT];
+    auto load = [&](int64_t ch) {
+#pragma unroll
+        for (int s = 0; s < LPT; ++s) {
+            const int e = t + GT * s;
+            const int rr = e % CH, cc = e / CH;
+            const int64_t r = ch * CH + rr;
+            pre[s] = (r < m && cc < w) ? P[r + cc * ld] : 0.0f;
+        }
+    };
+    if (ch0 < ch1) load(ch0);
+    for (int64_t ch = ch0; ch < ch1; ++ch) {
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < LPT; ++s) {
+            const int e = t + GT * s;
+            C[(e % CH) * LDC + e / CH] = (double)pre[s];
+        }
+        __syncthreads();
+        if (ch + 1 < ch1) load(ch + 1);
+        if constexpr (DO_Q) {
+            const int Rb = wv;
+            d4 q[4];
+#pragma unroll
+            for (int Jb = 0; Jb < 4; ++Jb) {
+                q[Jb] = d4{0.0, 0.0, 0.0, 0.0};
+                for (int k4 = 0; k4 < 4 * (Jb + 1); ++k4) {
+                    const double a = C[(16 * Rb + li) * LDC + 4 * k4 + lk];
+                    const double b = Xs[(4 * k4 + lk) * XLD + 16 * Jb + li];
+                    q[Jb] = mfma64(a, b, q[Jb]);
+                }
+            }
+            __syncthreads();   // every wave has read its rows of the chunk
+#pragma unroll
+            for (int Jb = 0; Jb < 4; ++Jb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    C[(16 * Rb + 4 * v + lk) * LDC + 16 * Jb + li] = (double)(float)q[Jb][v];
+            __syncthreads();
+            // Q1 rows back to P, coalesced along the columns
+#pragma unroll
+            for (int s = 0; s < LPT; ++s) {
+                const int e = t + GT * s;
+                const int rr = e % CH, cc = e / CH;
+                const int64_t r = ch * CH + rr;
+                if (r < m && cc < w) P[r + cc * ld] = (float)C[rr * LDC + cc];
+            }
+        }
+        if constexpr (DO_G) {
+            for (int k4 = 0; k4 < CH / 4; ++k4) {
+                const double *row = C + (4 * k4 + lk) * LDC + li;
+#pragma unroll
+                for (int p = 0; p < 3; ++p)
+                    if (p < np) acc[p] = mfma64(row[16 * PI[p]], row[16 * PJ[p]], acc[p]);
+            }
+        }
+    }
+}
+
+// this wave's Gram blocks into out[upk(i, j)], i <= j
+QRX_DEV void gram_store64(const d4 (&acc)[3], double *out, int t) {
+    const int lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int np = npairs(wv);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        if (p >= np) continue;
+        int I, J;
+        pair_of(wv, p, I, J);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * I + 4 * v + (lane >> 4), j = 16 * J + (lane & 15);
+            if (i <= j) out[upk(i, j)] = acc[p][v];
+        }
+    }
+}
 
 // One sweep over this workgroup's row chunks of P (m x w, column-major, ld).
 // DO_Q: rows <- fl32(rows X) with X upper triangular (W x W, FP64, column-
@@ -53,14 +170,23 @@ __global__ __launch_bounds__(GT) void gram_pass_kernel(float *__restrict__ P, in
     const int64_t ch0 = (int64_t)blockIdx.x * chunks_per;
     const int64_t ch1 = (ch0 + chunks_per < nch) ? ch0 + chunks_per : nch;
     if constexpr (DO_Q) gram::load_x<W>(X, Xs, t);
-    double acc[4][4];
+    if constexpr (W == 64) {
+        d4 acc[3];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+        for (int p = 0; p < 3; ++p) acc[p] = d4{0.0, 0.0, 0.0, 0.0};
+        sweep64<DO_Q, DO_G>(P, ld, m, w, ch0, ch1, Xs, C, acc, t);
+        if constexpr (DO_G) gram_store64(acc, part + (int64_t)blockIdx.x * (W * (W + 1) / 2), t);
+        (void)red;
+    } else {
+        double acc[4][4];
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-    gram::sweep<W, DO_Q, DO_G>(P, ld, m, w, ch0, ch1, Xs, C, acc, t);
-    if constexpr (DO_G)
-        gram::gram_store<W>(acc, red, part + (int64_t)blockIdx.x * (W * (W + 1) / 2), t);
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+        gram::sweep<W, DO_Q, DO_G>(P, ld, m, w, ch0, ch1, Xs, C, acc, t);
+        if constexpr (DO_G)
+            gram::gram_store<W>(acc, red, part + (int64_t)blockIdx.x * (W * (W + 1) / 2), t);
+    }
 }
 
 // G[e] = sum over the partials: a workgroup owns 64 entries (one per lane),
@@ -88,7 +214,8 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
     constexpr int NW = CT / 64;
     constexpr int RB = 16;
     constexpr int NQ = (W * W + CT - 1) / CT;   // entries of a W x W matrix per thread
-    constexpr int U = (NW * 64 > 4 * W + 4) ? NW * 64 : 4 * W + 4;   // partial sums, then pivot rows
+    constexpr int TP = (W == 64 && CT == 512) ? 2 * (8 * W + 4) : 4 * W + 4;   // pivot rows
+    constexpr int U = (NW * 64 > TP) ? NW * 64 : TP;   // partial sums, then pivot rows
     __shared__ double S[W * LS];       // G, then R (upper)
     __shared__ double Xs[W * LS];      // R^{-1}, then Rprev
     __shared__ double Ub[U];           // partial sums, then pivot rows of the elimination

@@ -186,7 +186,8 @@ QRX_DEV void gram_store(double (&acc)[4][4], double *red, double *out, int t) {
 // diagonal zeroed, so that rows <= k, whose entry in that row is zero, are
 // left unchanged without a branch. Waves whose rows are all <= k skip the
 // step; one barrier per step. Entries left of the diagonal take finite values
-// that are never read. T is LDS scratch of 4W + 4 doubles.
+// that are never read. T is LDS scratch of 4W + 4 doubles (2 (8W + 4) for
+// W = 64 with 512 threads, which takes the four-pivot variant).
 // ---------------------------------------------------------------------------
 // 1 / sqrt(d) for d > 0: hardware estimate plus one Newton step.
 QRX_DEV double rsqrt_d(double d) {
@@ -194,8 +195,112 @@ QRX_DEV double rsqrt_d(double d) {
     return y * fma(-0.5 * d * y, y, 1.5);
 }
 
+// v in lane l, as a wave-uniform value (two v_readlane).
+QRX_DEV double readlane_d(double v, int l) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)bits, l);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The same elimination for W = 64 and 512 threads, four pivots per barrier.
+// A wave owns eight whole rows (two columns per lane). For the block of pivots
+// kk..kk+3 the owning wave eliminates within its four pivot rows in registers
+// (pivots and multipliers read across lanes), then publishes the four updated
+// rows, with their left entries up to kk+3 zeroed; after one
+// barrier every wave subtracts the rank-4 term from its rows below the block.
+// The reciprocal pivots are published with the rows.
+// T is LDS scratch of 2 (8W + 4) doubles.
+QRX_DEV void chol_inv64_b4(double *S, double *Xs, double *T, int t) {
+    constexpr int W = 64, LS = W + 1, RB = 8, CB = 2, NCB = 2 * W / CB, RL = 8 * W + 4;
+    const int lane = t & 63;
+    const int i0 = (t / NCB) * RB, j0 = (t % NCB) * CB;   // one row block per wave
+    double M[RB][CB], sc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        sc[r] = 0.0;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int i = i0 + r, j = j0 + c;
+            M[r][c] = (j < W) ? ((i <= j) ? S[i + j * LS] : S[j + i * LS])
+                              : ((j - W == i) ? 1.0 : 0.0);
+        }
+    }
+    __syncthreads();
+    // pivot rows base..base+3 of this wave's registers (base 0 or 4)
+    auto eliminate = [&](auto base_c, int kk) {
+        constexpr int B = decltype(base_c)::value;
+        double *dst = T + ((kk / 4) & 1) * RL;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int p = kk + q;                     // pivot column: lane p / 2, slot q & 1
+            const double d = readlane_d(M[B + q][q & 1], p >> 1);
+            const double rinv = (d > 0.0) ? rsqrt_d(d) : 0.0;
+            const double dinv = rinv * rinv;
+            sc[B + q] = rinv;
+#pragma unroll
+            for (int r2 = q + 1; r2 < 4; ++r2) {
+                const double f = readlane_d(M[B + r2][q & 1], p >> 1) * dinv;
+#pragma unroll
+                for (int c = 0; c < CB; ++c) M[B + r2][c] = fma(-f, M[B + q][c], M[B + r2][c]);
+            }
+            if (lane == (p >> 1)) dst[8 * W + q] = dinv;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int j = j0 + c;
+                dst[q * 2 * W + j] = (j <= kk + 3) ? 0.0 : M[B + q][c];
+            }
+    };
+    const int wlast = __builtin_amdgcn_readfirstlane(i0 + RB - 1);
+    const int wfirst = __builtin_amdgcn_readfirstlane(i0);
+    for (int kk = 0; kk < W; kk += 4) {
+        if (kk == wfirst) eliminate(std::integral_constant<int, 0>{}, kk);
+        else if (kk == wfirst + 4) eliminate(std::integral_constant<int, 4>{}, kk);
+        __syncthreads();
+        if (wlast > kk + 3) {
+            const double *row = T + ((kk / 4) & 1) * RL;
+            double rc[4][CB], rr[4][RB];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double dinv = row[8 * W + q];   // 1 / pivot (0 for a bad pivot)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) rc[q][c] = row[q * 2 * W + j0 + c] * dinv;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) rr[q][r] = row[q * 2 * W + i0 + r];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) M[r][c] = fma(-rr[q][r], rc[q][c], M[r][c]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int i = i0 + r, j = j0 + c;
+            const double v = M[r][c] * sc[r];
+            if (j < W) {
+                if (i <= j) S[i + j * LS] = v;
+            } else {
+                const int a = j - W;   // X[a][i] = (R^{-T})[i][a]
+                Xs[a + i * LS] = (a <= i) ? v : 0.0;
+            }
+        }
+    __syncthreads();
+}
+
 template <int W, int NT>
 QRX_DEV void chol_inv(double *S, double *Xs, double *T, int t) {
+    if constexpr (W == 64 && NT == 512) {
+        chol_inv64_b4(S, Xs, T, t);
+        return;
+    }
     constexpr int LS = W + 1;
     constexpr int E = 2 * W * W / NT;      // entries per thread
     constexpr int CB = E >= 2 ? 2 : 1;
