@@ -961,7 +961,8 @@ static int qr_common(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t
     Carve cv(work);
     QrWork ws;
     carve_qr(cv, m, n, c, ops, ws);
-    QRX_TRY(hipMemsetAsync(ws.flags, 0, 4 * sizeof(int), stream));
+    // status flags cleared by a kernel (the call stays safe to record in a HIP graph)
+    QRX_TRY(launch_fill_f32(stream, reinterpret_cast<float *>(ws.flags), 4, 0.0f));
     {
         Rec r(h, stream);
         const bool copy = (Q != A);
@@ -1061,7 +1062,8 @@ static int lls_common(qrx_handle h, int64_t m, int64_t n, const float *A, int64_
     hipEventCreate(&e1);
     hipEventCreate(&e2);
     hipEventRecord(e0, stream);
-    QRX_TRY(hipMemsetAsync(ws.flags, 0, 4 * sizeof(int), stream));
+    // status flags cleared by a kernel (the call stays safe to record in a HIP graph)
+    QRX_TRY(launch_fill_f32(stream, reinterpret_cast<float *>(ws.flags), 4, 0.0f));
     {
         Rec r(h, stream);
         QRX_TRY(launch_scan(stream, m, n, A, lda, W, ldw, ws.colmax, ws.colss, ws.flags));
