@@ -128,15 +128,50 @@ __global__ __launch_bounds__(256) void proj_reduce_kernel(int64_t M, int64_t N,
     const int64_t j = blockIdx.x;
     __shared__ float smax[4];
     __shared__ float us_s;
+    __shared__ float gsum[256];
     const float unscale = lowp_scaled ? 1.0f / (16384.0f * pow2_scale(colmax[j], 14)) : 1.0f;
-    float mx = 0.0f;
-    for (int64_t i = threadIdx.x; i < M; i += 256) {
+    const int64_t MN = M * N;
+    const float *pj = part + j * M;
+    // sum of splits [q0, q1) for row i, eight loads in flight, added in split order
+    auto ssum = [&](int64_t i, int q0, int q1) {
         float s = 0.0f;
-        for (int q = 0; q < splits; ++q) s += part[(int64_t)q * M * N + i + j * M];
-        s *= unscale;
-        R12[i + j * ldr] = s;
-        if (Racc) Racc[i + j * ldacc] += s;
-        mx = fmaxf(mx, fabsf(s));
+        int q = q0;
+        for (; q + 8 <= q1; q += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = pj[(int64_t)(q + u) * MN + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; q < q1; ++q) s += pj[(int64_t)q * MN + i];
+        return s;
+    };
+    float mx = 0.0f;
+    if (M <= 128 && splits > 1) {
+        // short columns: G groups of threads sum consecutive ranges of the splits,
+        // then the group sums are added in group order
+        const int G = 256 / (int)M, gi = threadIdx.x / (int)M, i = threadIdx.x % (int)M;
+        const int per = (splits + G - 1) / G;
+        if (gi < G) {
+            const int q0 = gi * per, q1 = (q0 + per < splits) ? q0 + per : splits;
+            gsum[gi * M + i] = ssum(i, q0 < splits ? q0 : splits, q1);
+        }
+        __syncthreads();
+        if (gi == 0) {
+            float s = gsum[i];
+            for (int g = 1; g < G; ++g) s += gsum[g * M + i];
+            s *= unscale;
+            R12[i + j * ldr] = s;
+            if (Racc) Racc[i + j * ldacc] += s;
+            mx = fabsf(s);
+        }
+    } else {
+        for (int64_t i = threadIdx.x; i < M; i += 256) {
+            float s = ssum(i, 0, splits) * unscale;
+            R12[i + j * ldr] = s;
+            if (Racc) Racc[i + j * ldacc] += s;
+            mx = fmaxf(mx, fabsf(s));
+        }
     }
     mx = wave_max_f(mx);
     if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = mx;
@@ -296,14 +331,14 @@ static bool aligned16(const void *p) { return (((uintptr_t)p) & 15) == 0; }
 
 // Split-K count of the projection: about 1024 workgroups over the output tiles
 // (FP32: 128 x 128; low precision: 256 x 128 when k >= 256 and n2 >= 128,
-// else 128 x 128), at least 512 rows per split, at most 256 splits.
+// else 128 x 128), at least 256 rows per split, at most 256 splits.
 int projection_splits(int64_t m, int64_t k, int64_t n2, int prec, int target) {
     int64_t tm = 128;
     if (prec != QRX_FP32 && prec != QRX_FP16X3 && k >= 256 && n2 >= 128) tm = 256;
     const int64_t tiles = ((k + tm - 1) / tm) * ((n2 + 127) / 128);
     const int64_t tgt = target > 0 ? target : 1024;   // workgroups to aim at
     int64_t want = (tgt + tiles - 1) / tiles;
-    int64_t maxs = (m + 511) / 512;
+    int64_t maxs = (m + 255) / 256;                     // at least 256 rows per split
     if (want > maxs) want = maxs;
     if (want < 1) want = 1;
     if (want > 256) want = 256;
@@ -377,7 +412,7 @@ hipError_t launch_colmax_reduce(hipStream_t s, int64_t n2, int64_t slots, const 
 }
 
 // Slots of partial column maxima the update may write (max over tile shapes).
-int64_t update_cmpart_slots(int64_t m) { return ((m + 127) / 128) * 2 + ((m + 255) / 256) * 4; }
+int64_t update_cmpart_slots(int64_t m) { return ((m + 63) / 64) * 4; }
 
 template <class Tr>
 static hipError_t upd_dispatch(hipStream_t s, int64_t m, int64_t k, int64_t n2, const float *Q1,
@@ -386,9 +421,14 @@ static hipError_t upd_dispatch(hipStream_t s, int64_t m, int64_t k, int64_t n2, 
     if (n2 >= 128)
         return upd_go<Tr, 128, 128, 2, 2>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax,
                                           cmpart, scaling);
-    if (n2 > 32)
-        return upd_go<Tr, 256, 64, 4, 1>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax,
+    if (n2 > 32) {
+        // 128-row tiles when 256-row tiles would not cover the chip twice
+        if ((m + 255) / 256 >= 512)
+            return upd_go<Tr, 256, 64, 4, 1>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax,
+                                             cmpart, scaling);
+        return upd_go<Tr, 128, 64, 4, 1>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax,
                                          cmpart, scaling);
+    }
     return upd_go<Tr, 256, 32, 4, 1>(s, m, k, n2, Q1, A2, lda, R12, ldr, uscale, colmax, cmpart,
                                      scaling);
 }

@@ -164,6 +164,7 @@ struct KLoader {
     static constexpr int CPC = BK / 4;         // float4 per column
     static constexpr int COLS_PER_PASS = GT / CPC;
     static constexpr int NR = C / COLS_PER_PASS;
+    static_assert(NR >= 1 && NR * COLS_PER_PASS == C, "K loader mapping");
     float4 v[NR];
     QRX_DEV void load(const float *X, int64_t ld, int64_t k0, int64_t kend, int64_t c0,
                       int64_t cend, bool vec, int t) {
@@ -218,6 +219,7 @@ struct MLoader {
     static constexpr int RB = BM / 4;                 // 4-row groups
     static constexpr int NBLK = RB * (BK / 4);
     static constexpr int NB4 = NBLK / GT;
+    static_assert(NB4 >= 1 && NB4 * GT == NBLK, "M loader mapping");
     float4 v[NB4][4];
     QRX_DEV void load(const float *X, int64_t ld, int64_t r0, int64_t rend, int64_t i0,
                       int64_t iend, bool vec, int t) {
