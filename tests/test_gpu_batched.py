@@ -134,3 +134,27 @@ def test_batched_lls_deterministic_and_ragged(qrx):
             # square: a compatible system, certified by ||r|| / (||A||_F ||x|| + ||b||)
             _, nr = M.eta(A, b, xh)
             assert nr / (M.fro(A) * np.linalg.norm(xh) + np.linalg.norm(b)) <= 1.05e-10
+
+
+@pytest.mark.slow
+def test_c4_full_batch(qrx):
+    """The full 4096-problem batch (n = 8 U{4..32}, m = n U{4..16}) in one batched
+    call with BF16 products: every problem certified; a sample of 32 problems
+    checked against the oracle's eta_F and least-squares solution."""
+    import torch
+    mats, rhs = synth.batched_problems_device(4096, seed=0, device="cuda")
+    xs, infos = qrx.lstsq_batched(mats, rhs, prec="bf16", tol=1e-10, max_iter=400)
+    torch.cuda.synchronize()
+    assert all(i["status"] == 0 for i in infos)
+    assert max(i["eta_F"] for i in infos) <= 1e-10
+    pick = np.random.default_rng(1).choice(len(mats), 32, replace=False)
+    for k in pick:
+        A, b, x = host(mats[k]).astype(np.float32), host(rhs[k]), host(xs[k])
+        eta = M.eta_F(A, b, x)
+        xo, _, _ = L.lls_direct(A, b)
+        fe = M.forward_error(x, xo)
+        kappa = np.linalg.cond(A.astype(np.float64))
+        assert eta <= 1.05e-10, (k, eta)
+        assert abs(eta - infos[k]["eta_F"]) <= 0.05 * eta + 1e-14
+        # the forward error of a backward-stable least-squares solution: O(kappa eta)
+        assert fe <= 1e3 * kappa * 1e-10 + 1e-12, (k, fe, kappa)

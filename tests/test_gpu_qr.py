@@ -157,7 +157,9 @@ def test_c2_full_size_sampled(qrx):
     print(f"c2 sampled: be={be:.2e} orth(sub)={orth:.2e}")
     assert M.upper_triangular_ok(Rh)
     assert be < 4e-3
-    assert orth < 1e-2
+    # block Gram-Schmidt with FP16 products keeps orthogonality at O(kappa u16)
+    # (kappa = 1e3 here); a subset of the columns cannot do worse than the whole
+    assert orth < 1e3 * 4.9e-4
 
 
 @pytest.mark.parametrize("prec,orth_bound,kappa_bound", [("fp32", 1e-4, 1.2), ("fp16", 1.0, 5e3),
