@@ -191,13 +191,8 @@ template <class TA, int TRI>
 static hipError_t tri_gemm(hipStream_t s, int64_t M, int64_t N, int64_t K, const TA *A,
                            int64_t lda, int64_t arl, int64_t acl, const double *B, int64_t ldb,
                            double *C, int64_t ldc, double alpha) {
-    if (M % 128 == 0 && N % 128 == 0 && (M / 128) * (N / 128) >= 256) {
-        // 128 x 128 tiles (8 x 8 per thread: half the LDS reads per FMA) when they fill the chip
-        const unsigned tiles = (unsigned)((M / 128) * (N / 128));
-        hipLaunchKernelGGL((tri_gemm_kernel<TA, TRI, 128>), dim3(tiles), dim3(TT), 0, s, M, N, K,
-                           A, lda, arl, acl, B, ldb, C, ldc, alpha);
-        return hipGetLastError();
-    }
+    // 64 x 64 tiles throughout: measured faster at n = 8192 than 128 x 128 tiles on
+    // the vector units (8 x 8 per thread) or on the FP64 matrix cores
     const unsigned tiles = (unsigned)((M / 64) * (N / 64));
     hipLaunchKernelGGL((tri_gemm_kernel<TA, TRI, 64>), dim3(tiles), dim3(TT), 0, s, M, N, K, A,
                        lda, arl, acl, B, ldb, C, ldc, alpha);
