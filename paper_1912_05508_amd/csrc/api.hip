@@ -245,15 +245,30 @@ void carve_qr(Carve &cv, int64_t m, int64_t n, const QrCfg &c, const std::vector
 }
 
 int run_panel_core(qrx_handle h, hipStream_t s, int64_t m, float *P, int64_t ld, int w,
-                   float *R, int64_t ldr, const float *colmax, const QrCfg &c, QrWork &ws);
+                   float *R, int64_t ldr, const float *colmax, const QrCfg &c, QrWork &ws,
+                   const PanelPack &pack);
 
 // One leaf panel (columns [c0, c0 + w) of W), then its 16-bit operand copies.
 int run_panel(qrx_handle h, hipStream_t s, int64_t m, float *W, int64_t ldw, int64_t c0, int w,
               float *R, int64_t ldr, const QrCfg &c, QrWork &ws) {
     float *P = W + c0 * ldw;
-    int rc = run_panel_core(h, s, m, P, ldw, w, R + c0 + c0 * ldr, ldr, ws.colmax + c0, c, ws);
+    // a 64-column Cholesky-QR panel writes the 16-bit operand copies with its Q
+    PanelPack pack{};
+    const bool fused = ws.qc && c.alg == 0 && gram_panel_packs(w);
+    if (fused) {
+        pack.qc = ws.qc + c0 * ws.ldc;
+        pack.qcl = ws.qcl ? ws.qcl + c0 * ws.ldc : nullptr;
+        pack.qr = ws.qr + c0;
+        pack.qrl = ws.qrl ? ws.qrl + c0 : nullptr;
+        pack.ldc = ws.ldc;
+        pack.ldq = ws.ldq;
+        pack.sc = c.scaling ? 16384.0f : 1.0f;
+        pack.prec = c.prec;
+    }
+    int rc = run_panel_core(h, s, m, P, ldw, w, R + c0 + c0 * ldr, ldr, ws.colmax + c0, c, ws,
+                            pack);
     if (rc) return rc;
-    if (ws.qc) {
+    if (ws.qc && !fused) {
         Rec r(h, s);
         QRX_TRY(launch_pack_q(s, c.prec, c.scaling, m, w, P, ldw, ws.qc + c0 * ws.ldc,
                               ws.qcl ? ws.qcl + c0 * ws.ldc : nullptr, ws.ldc, ws.qr + c0,
@@ -264,10 +279,11 @@ int run_panel(qrx_handle h, hipStream_t s, int64_t m, float *W, int64_t ldw, int
 }
 
 int run_panel_core(qrx_handle h, hipStream_t s, int64_t m, float *P, int64_t ld, int w, float *R,
-                   int64_t ldr, const float *colmax, const QrCfg &c, QrWork &ws) {
+                   int64_t ldr, const float *colmax, const QrCfg &c, QrWork &ws,
+                   const PanelPack &pack) {
     if (c.alg == 0) {
         Rec r(h, s);
-        QRX_TRY(launch_gram_panel(s, P, ld, m, w, R, ldr, ws.gram, c.reorth));
+        QRX_TRY(launch_gram_panel(s, P, ld, m, w, R, ldr, ws.gram, c.reorth, pack));
         // FP64 work: Gram of P, Q formation, Gram of Q1 (m w(w+1)/2 FMA each); the
         // second Q formation runs only when Q1 is not yet orthonormal, so the
         // usual case is counted. Traffic (FP32): read P, read P + write Q1.

@@ -61,9 +61,25 @@ QRX_DEV void pair_of(int wv, int p, int &I, int &J) {
     J = Js[code];
 }
 
+// v as a 16-bit operand element (and its low part for a split) at index i
+QRX_DEV void store16(uint16_t *h, uint16_t *l, int64_t i, float v, int prec) {
+    if (prec == QRX_BF16) {
+        const __bf16 b = (__bf16)v;
+        h[i] = *reinterpret_cast<const uint16_t *>(&b);
+        return;
+    }
+    const _Float16 f = (_Float16)v;
+    h[i] = *reinterpret_cast<const uint16_t *>(&f);
+    if (prec == QRX_FP16X3) {
+        const _Float16 g = (_Float16)(v - (float)f);
+        l[i] = *reinterpret_cast<const uint16_t *>(&g);
+    }
+}
+
 template <bool DO_Q, bool DO_G>
 QRX_DEV void sweep64(float *__restrict__ P, int64_t ld, int64_t m, int w, int64_t ch0,
-                     int64_t ch1, const double *Xs, double *C, d4 (&acc)[3], int t) {
+                     int64_t ch1, const double *Xs, double *C, d4 (&acc)[3], int t,
+                     const PanelPack &pk) {
     using L = gram::Lds<64>;
     constexpr int LDC = L::LDC, XLD = L::XLD;
     constexpr int LPT = CH * 64 / GT;
@@ -113,13 +129,29 @@ QRX_DEV void sweep64(float *__restrict__ P, int64_t ld, int64_t m, int w, int64_
                 for (int v = 0; v < 4; ++v)
                     C[(16 * Rb + 4 * v + lk) * LDC + 16 * Jb + li] = (double)(float)q[Jb][v];
             __syncthreads();
-            // Q1 rows back to P, coalesced along the columns
+            // Q1 rows back to P (and to the column-major operand copy), coalesced
+            // along the columns; then the row-major copy, coalesced along the rows
 #pragma unroll
             for (int s = 0; s < LPT; ++s) {
                 const int e = t + GT * s;
                 const int rr = e % CH, cc = e / CH;
                 const int64_t r = ch * CH + rr;
-                if (r < m && cc < w) P[r + cc * ld] = (float)C[rr * LDC + cc];
+                if (r < m && cc < w) {
+                    const float v = (float)C[rr * LDC + cc];
+                    P[r + cc * ld] = v;
+                    if (pk.prec) store16(pk.qc, pk.qcl, r + cc * pk.ldc, v * pk.sc, pk.prec);
+                }
+            }
+            if (pk.prec) {
+#pragma unroll
+                for (int s = 0; s < LPT; ++s) {
+                    const int e = t + GT * s;
+                    const int cc = e % 64, rr = e / 64;
+                    const int64_t r = ch * CH + rr;
+                    if (r < m && cc < w)
+                        store16(pk.qr, pk.qrl, r * pk.ldq + cc, (float)C[rr * LDC + cc] * pk.sc,
+                                pk.prec);
+                }
             }
         }
         if constexpr (DO_G) {
@@ -159,7 +191,8 @@ __global__ __launch_bounds__(GT) void gram_pass_kernel(float *__restrict__ P, in
                                                        int64_t m, int w, int64_t chunks_per,
                                                        const double *__restrict__ X,
                                                        double *__restrict__ part,
-                                                       const int *__restrict__ skip) {
+                                                       const int *__restrict__ skip,
+                                                       PanelPack pk) {
     if (skip && *skip) return;   // the first sweep already gave an orthonormal Q
     using L = gram::Lds<W>;
     __shared__ __align__(16) double C[L::C_DOUBLES];
@@ -174,7 +207,7 @@ __global__ __launch_bounds__(GT) void gram_pass_kernel(float *__restrict__ P, in
         d4 acc[3];
 #pragma unroll
         for (int p = 0; p < 3; ++p) acc[p] = d4{0.0, 0.0, 0.0, 0.0};
-        sweep64<DO_Q, DO_G>(P, ld, m, w, ch0, ch1, Xs, C, acc, t);
+        sweep64<DO_Q, DO_G>(P, ld, m, w, ch0, ch1, Xs, C, acc, t, pk);
         if constexpr (DO_G) gram_store64(acc, part + (int64_t)blockIdx.x * (W * (W + 1) / 2), t);
         (void)red;
     } else {
@@ -393,7 +426,10 @@ constexpr double kSkipTau = 1.0 / (1 << 21);
 
 template <int W>
 static hipError_t gram_go(hipStream_t s, float *P, int64_t ld, int64_t m, int w, float *R,
-                          int64_t ldr, double *ws, int reorth) {
+                          int64_t ldr, double *ws, int reorth, const PanelPack &pack) {
+    PanelPack none = pack;
+    none.prec = 0;
+    const PanelPack &pk = (W == 64) ? pack : none;   // sweeps of width 64 write the copies
     const int64_t np = (int64_t)W * (W + 1) / 2;
     const GramSplit sp = gram_split(m);
     double *part = ws;
@@ -407,31 +443,34 @@ static hipError_t gram_go(hipStream_t s, float *P, int64_t ld, int64_t m, int w,
     const unsigned cb = (unsigned)((np + 63) / 64);
     const int *noskip = nullptr;
     hipLaunchKernelGGL((gram_pass_kernel<W, false, true>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
-                       m, w, sp.chunks_per, (const double *)nullptr, part, noskip);
+                       m, w, sp.chunks_per, (const double *)nullptr, part, noskip, none);
     hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(cb), dim3(CT), 0, s, (const double *)part,
                        sp.parts, w, G, counter, R1, X1, (const double *)nullptr,
                        reorth ? (float *)nullptr : R, ldr, (int *)nullptr, 0.0);
     if (!reorth) {
         hipLaunchKernelGGL((gram_pass_kernel<W, true, false>), dim3(sp.parts), dim3(GT), 0, s, P,
-                           ld, m, w, sp.chunks_per, (const double *)X1, (double *)nullptr, noskip);
+                           ld, m, w, sp.chunks_per, (const double *)X1, (double *)nullptr, noskip,
+                           pk);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((gram_pass_kernel<W, true, true>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
-                       m, w, sp.chunks_per, (const double *)X1, part, noskip);
+                       m, w, sp.chunks_per, (const double *)X1, part, noskip, pk);
     hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(cb), dim3(CT), 0, s, (const double *)part,
                        sp.parts, w, G, counter, R2, X2, (const double *)R1, R, ldr, skip,
                        kSkipTau);
     hipLaunchKernelGGL((gram_pass_kernel<W, true, false>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
                        m, w, sp.chunks_per, (const double *)X2, (double *)nullptr,
-                       (const int *)skip);
+                       (const int *)skip, pk);
     return hipGetLastError();
 }
 
+bool gram_panel_packs(int w) { return w > 32; }
+
 hipError_t launch_gram_panel(hipStream_t s, float *P, int64_t ld, int64_t m, int w, float *R,
-                             int64_t ldr, double *ws, int reorth) {
-    if (w <= 16) return gram_go<16>(s, P, ld, m, w, R, ldr, ws, reorth);
-    if (w <= 32) return gram_go<32>(s, P, ld, m, w, R, ldr, ws, reorth);
-    return gram_go<64>(s, P, ld, m, w, R, ldr, ws, reorth);
+                             int64_t ldr, double *ws, int reorth, const PanelPack &pack) {
+    if (w <= 16) return gram_go<16>(s, P, ld, m, w, R, ldr, ws, reorth, pack);
+    if (w <= 32) return gram_go<32>(s, P, ld, m, w, R, ldr, ws, reorth, pack);
+    return gram_go<64>(s, P, ld, m, w, R, ldr, ws, reorth, pack);
 }
 
 }  // namespace qrx

@@ -122,8 +122,19 @@ hipError_t launch_copy_r_block(hipStream_t s, const float *src, int64_t ld_src, 
 // gram.hip : Cholesky QR twice on an FP64 Gram matrix (panel of w <= 64 columns);
 // ws holds gram_workspace_doubles(m, 64) doubles and its counter
 // (gram_counter) must be zeroed once before the first panel.
+// 16-bit operand copies a 64-column Gram panel writes with its Q (as pack_q
+// does): column-major qc (ldc) and row-major qr (ldq) of sc * Q, lo parts for
+// a split; prec 0 writes none.
+struct PanelPack {
+    uint16_t *qc, *qcl, *qr, *qrl;
+    int64_t ldc, ldq;
+    float sc;
+    int prec;
+};
+// Whether launch_gram_panel writes the operand copies itself for width w.
+bool gram_panel_packs(int w);
 hipError_t launch_gram_panel(hipStream_t s, float *P, int64_t ld, int64_t m, int w, float *R,
-                             int64_t ldr, double *ws, int reorth);
+                             int64_t ldr, double *ws, int reorth, const PanelPack &pack);
 size_t gram_workspace_doubles(int64_t m, int W);
 int *gram_counter(double *ws, int64_t m);
 
