@@ -337,7 +337,7 @@ int run_panel_core(qrx_handle h, hipStream_t s, int64_t m, float *P, int64_t ld,
 // column max-abs of W on entry.
 int run_qr(qrx_handle h, hipStream_t s, int64_t m, int64_t n, float *W, int64_t ldw, float *R,
            int64_t ldr, const QrCfg &c, const std::vector<Op> &ops, QrWork &ws) {
-    if (c.alg == 0) QRX_TRY(launch_fill_f32(s, (float *)gram_counter(ws.gram, m), 1, 0.0f));
+    if (c.alg == 0) QRX_TRY(launch_fill_f32(s, (float *)gram_counter(ws.gram, m), kGramCounterInts, 0.0f));
     for (const Op &o : ops) {
         if (o.kind == 0) {
             int rc = run_panel(h, s, m, W, ldw, o.c0, (int)o.k, R, ldr, c, ws);

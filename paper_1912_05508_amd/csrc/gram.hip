@@ -34,6 +34,8 @@ using gram::GT;
 using gram::upk;
 constexpr int CT = 512;          // threads per reduce/Cholesky workgroup
 constexpr int kMaxParts = 512;   // Gram partials (one per sweep workgroup)
+constexpr int kMaxSlices = 16;   // first-level reduction workgroups per column block
+constexpr int kSliceParts = 32;  // partials summed by one of them
 
 // ---------------------------------------------------------------------------
 // 64-column sweeps on the FP64 matrix cores (v_mfma_f64_16x16x4f64: A operand
@@ -129,21 +131,27 @@ QRX_DEV void sweep64(float *__restrict__ P, int64_t ld, int64_t m, int w, int64_
                 for (int v = 0; v < 4; ++v)
                     C[(16 * Rb + 4 * v + lk) * LDC + 16 * Jb + li] = (double)(float)q[Jb][v];
             __syncthreads();
-            // Q1 rows back to P (and to the column-major operand copy), coalesced
-            // along the columns; then the row-major copy, coalesced along the rows
+            // Q1 rows back to P, coalesced along the columns
 #pragma unroll
             for (int s = 0; s < LPT; ++s) {
                 const int e = t + GT * s;
                 const int rr = e % CH, cc = e / CH;
                 const int64_t r = ch * CH + rr;
-                if (r < m && cc < w) {
-                    const float v = (float)C[rr * LDC + cc];
-                    P[r + cc * ld] = v;
-                    if (pk.prec) store16(pk.qc, pk.qcl, r + cc * pk.ldc, v * pk.sc, pk.prec);
-                }
+                if (r < m && cc < w) P[r + cc * ld] = (float)C[rr * LDC + cc];
             }
             if (pk.prec) {
-#pragma unroll
+                // the operand copies: column-major coalesced along the columns,
+                // row-major along the rows (few in flight: registers are scarce here)
+#pragma unroll 1
+                for (int s = 0; s < LPT; ++s) {
+                    const int e = t + GT * s;
+                    const int rr = e % CH, cc = e / CH;
+                    const int64_t r = ch * CH + rr;
+                    if (r < m && cc < w)
+                        store16(pk.qc, pk.qcl, r + cc * pk.ldc,
+                                (float)C[rr * LDC + cc] * pk.sc, pk.prec);
+                }
+#pragma unroll 1
                 for (int s = 0; s < LPT; ++s) {
                     const int e = t + GT * s;
                     const int cc = e % 64, rr = e / 64;
@@ -187,7 +195,7 @@ QRX_DEV void gram_store64(const d4 (&acc)[3], double *out, int t) {
 // DO_Q: rows <- fl32(rows X) with X upper triangular (W x W, FP64, column-
 // major). DO_G: part[blockIdx] = upper triangle of (rows)^T (rows), FP64.
 template <int W, bool DO_Q, bool DO_G>
-__global__ __launch_bounds__(GT) void gram_pass_kernel(float *__restrict__ P, int64_t ld,
+__global__ __launch_bounds__(GT, 2) void gram_pass_kernel(float *__restrict__ P, int64_t ld,
                                                        int64_t m, int w, int64_t chunks_per,
                                                        const double *__restrict__ X,
                                                        double *__restrict__ part,
@@ -219,6 +227,52 @@ __global__ __launch_bounds__(GT) void gram_pass_kernel(float *__restrict__ P, in
         gram::sweep<W, DO_Q, DO_G>(P, ld, m, w, ch0, ch1, Xs, C, acc, t);
         if constexpr (DO_G)
             gram::gram_store<W>(acc, red, part + (int64_t)blockIdx.x * (W * (W + 1) / 2), t);
+    }
+}
+
+// First level of the Gram reduction when there are many partials: workgroup
+// (x, y) sums entries 64x .. 64x + 63 of the partials y, y + NS, y + 2 NS, ...
+// (NS = gridDim.y) into lvl[y]; its 8 waves sum interleaved subsets and the 8
+// sums are added in a fixed order (deterministic). A kernel of its own: the
+// sums reach gram_chol through the kernel boundary, with no fence.
+template <int W>
+__global__ __launch_bounds__(CT) void gram_reduce_kernel(const double *__restrict__ part,
+                                                         int nparts, double *__restrict__ lvl) {
+    constexpr int NP = W * (W + 1) / 2;
+    constexpr int NW = CT / 64;
+    constexpr int RB = 8;
+    __shared__ double Ub[NW * 64];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    const int e = blockIdx.x * 64 + lane;
+    const int NS = gridDim.y, slice = blockIdx.y;
+    const int K = (nparts - slice + NS - 1) / NS;   // partials slice + k NS, k < K
+    double s = 0.0;
+    if (e < NP) {
+        int k = wv;
+        for (; k + (RB - 1) * NW < K; k += RB * NW) {
+            double v[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) v[q] = part[(int64_t)(slice + (k + q * NW) * NS) * NP + e];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) s += v[q];
+        }
+        double v[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int kq = k + q * NW;
+            v[q] = kq < K ? part[(int64_t)(slice + kq * NS) * NP + e] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < RB; ++q) s += v[q];
+    }
+    Ub[wv * 64 + lane] = s;
+    __syncthreads();
+    if (wv == 0 && e < NP) {
+        double g = Ub[lane];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) g += Ub[q * 64 + lane];
+        lvl[(int64_t)slice * NP + e] = g;
     }
 }
 
@@ -408,16 +462,24 @@ static GramSplit gram_split(int64_t m) {
     return {(int)parts, per};
 }
 
-// Workspace (doubles): parts * W(W+1)/2 + W(W+1)/2 + 4 W^2, then one double
-// holding two ints: the completion counter of gram_chol and the skip flag of
-// the second sweep.
+// first-level workgroups per column block for nparts partials
+static int gram_slices(int nparts) {
+    const int s = (nparts + kSliceParts - 1) / kSliceParts;
+    return s < 1 ? 1 : (s > kMaxSlices ? kMaxSlices : s);
+}
+
+// Workspace (doubles): parts * W(W+1)/2 (partials) + W(W+1)/2 (G) + 4 W^2
+// (R1, X1, R2, X2) + kMaxSlices * W(W+1)/2 (slice sums), then kGramCounterInts
+// ints: the completion counter of gram_chol and the skip flag of the second
+// sweep (the rest spare).
 size_t gram_workspace_doubles(int64_t m, int W) {
     const size_t np = (size_t)W * (W + 1) / 2;
-    return (size_t)gram_split(m).parts * np + np + 4 * (size_t)W * W + 1;
+    return (size_t)gram_split(m).parts * np + np + 4 * (size_t)W * W + kMaxSlices * np +
+           kGramCounterInts / 2;
 }
 
 int *gram_counter(double *ws, int64_t m) {
-    return reinterpret_cast<int *>(ws + gram_workspace_doubles(m, 64) - 1);
+    return reinterpret_cast<int *>(ws + gram_workspace_doubles(m, 64) - kGramCounterInts / 2);
 }
 
 // Re-orthogonalisation is skipped when every entry of Q1^T Q1 is within this
@@ -438,15 +500,26 @@ static hipError_t gram_go(hipStream_t s, float *P, int64_t ld, int64_t m, int w,
     double *X1 = R1 + W * W;
     double *R2 = X1 + W * W;
     double *X2 = R2 + W * W;
+    double *lvl = X2 + W * W;
     int *counter = gram_counter(ws, m);
     int *skip = counter + 1;
     const unsigned cb = (unsigned)((np + 63) / 64);
+    const int ns = gram_slices(sp.parts);
+    // partials as gram_chol reads them: the slice sums when there are many
+    const double *cpart = ns > 1 ? lvl : part;
+    const int cparts = ns > 1 ? ns : sp.parts;
+    auto reduce = [&] {
+        if (ns > 1)
+            hipLaunchKernelGGL(gram_reduce_kernel<W>, dim3(cb, ns), dim3(CT), 0, s,
+                               (const double *)part, sp.parts, lvl);
+    };
     const int *noskip = nullptr;
     hipLaunchKernelGGL((gram_pass_kernel<W, false, true>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
                        m, w, sp.chunks_per, (const double *)nullptr, part, noskip, none);
-    hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(cb), dim3(CT), 0, s, (const double *)part,
-                       sp.parts, w, G, counter, R1, X1, (const double *)nullptr,
-                       reorth ? (float *)nullptr : R, ldr, (int *)nullptr, 0.0);
+    reduce();
+    hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(cb), dim3(CT), 0, s, cpart, cparts, w, G,
+                       counter, R1, X1, (const double *)nullptr, reorth ? (float *)nullptr : R,
+                       ldr, (int *)nullptr, 0.0);
     if (!reorth) {
         hipLaunchKernelGGL((gram_pass_kernel<W, true, false>), dim3(sp.parts), dim3(GT), 0, s, P,
                            ld, m, w, sp.chunks_per, (const double *)X1, (double *)nullptr, noskip,
@@ -455,9 +528,9 @@ static hipError_t gram_go(hipStream_t s, float *P, int64_t ld, int64_t m, int w,
     }
     hipLaunchKernelGGL((gram_pass_kernel<W, true, true>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
                        m, w, sp.chunks_per, (const double *)X1, part, noskip, pk);
-    hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(cb), dim3(CT), 0, s, (const double *)part,
-                       sp.parts, w, G, counter, R2, X2, (const double *)R1, R, ldr, skip,
-                       kSkipTau);
+    reduce();
+    hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(cb), dim3(CT), 0, s, cpart, cparts, w, G,
+                       counter, R2, X2, (const double *)R1, R, ldr, skip, kSkipTau);
     hipLaunchKernelGGL((gram_pass_kernel<W, true, false>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
                        m, w, sp.chunks_per, (const double *)X2, (double *)nullptr,
                        (const int *)skip, pk);

@@ -135,6 +135,7 @@ struct PanelPack {
 bool gram_panel_packs(int w);
 hipError_t launch_gram_panel(hipStream_t s, float *P, int64_t ld, int64_t m, int w, float *R,
                              int64_t ldr, double *ws, int reorth, const PanelPack &pack);
+constexpr int kGramCounterInts = 64;   // ints at gram_counter, all 0 before the first panel
 size_t gram_workspace_doubles(int64_t m, int W);
 int *gram_counter(double *ws, int64_t m);
 
