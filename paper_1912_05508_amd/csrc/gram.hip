@@ -12,19 +12,24 @@
 // whole range an FP32 panel can carry. A zero (or negative) pivot leaves the
 // column of Q zero with R_kk = 0 (reported as singular when it reaches R).
 //
-// Three sweeps over the rows and two small kernels per panel:
+// Three sweeps over the rows and two small steps per panel:
 //   gram_pass<G>    Gram partials of P over row chunks
-//   gram_chol       fixed-order sum of the partials; the last workgroup to
-//                   finish factors G1 -> R1, X1 = R1^{-1}
+//   gram_reduce     fixed-order sums of the partials in a few slices (many
+//                   workgroups; skipped when there are only a few partials)
+//   gram_chol       one workgroup: adds the slices, factors G1 -> R1,
+//                   X1 = R1^{-1}
 //   gram_pass<Q,G>  Q1 = fl32(P X1) written in place, and the Gram partials of
 //                   the rounded Q1 rows while they are still in LDS
-//   gram_chol       G2 -> R2, X2, and R = R2 R1 (FP32) into the R block
+//   gram_reduce, gram_chol   G2 -> R2, X2, and R = R2 R1 (FP32) into the R block
 //   gram_pass<Q>    Q = fl32(Q1 X2) in place
+// The reductions pass their sums on through kernel boundaries, with no
+// device-wide fences or counters.
 // A sweep stages 64-row chunks of the panel in LDS as FP64; a workgroup owns a
 // contiguous run of chunks and prefetches the next chunk into registers while
 // it computes on the current one. 64-column panels compute their Gram blocks
 // and Q formation on the FP64 matrix cores. With one sweep (no re-orthogonalisation)
-// the panel is gram_pass<G>, gram_chol (R1 into the R block), gram_pass<Q>.
+// the panel is gram_pass<G>, gram_reduce, gram_chol (R1 into the R block),
+// gram_pass<Q>.
 #include "gram_common.hpp"
 
 namespace qrx {
@@ -34,8 +39,9 @@ using gram::GT;
 using gram::upk;
 constexpr int CT = 512;          // threads per reduce/Cholesky workgroup
 constexpr int kMaxParts = 512;   // Gram partials (one per sweep workgroup)
-constexpr int kMaxSlices = 16;   // first-level reduction workgroups per column block
-constexpr int kSliceParts = 32;  // partials summed by one of them
+constexpr int kMaxSlices = 8;    // first-level reduction workgroups per column block
+constexpr int kSliceParts = 64;  // partials summed by one of them (8 per wave)
+constexpr int kDirectParts = 8;  // at most this many partials go to gram_chol unreduced
 
 // ---------------------------------------------------------------------------
 // 64-column sweeps on the FP64 matrix cores (v_mfma_f64_16x16x4f64: A operand
@@ -194,19 +200,73 @@ QRX_DEV void gram_store64(const d4 (&acc)[3], double *out, int t) {
 // One sweep over this workgroup's row chunks of P (m x w, column-major, ld).
 // DO_Q: rows <- fl32(rows X) with X upper triangular (W x W, FP64, column-
 // major). DO_G: part[blockIdx] = upper triangle of (rows)^T (rows), FP64.
+// R = Ra Rb for the panel's R block: both upper triangular (W x W, FP64,
+// column-major, zero below the diagonal); Rfinal gets the w x w FP32 result
+// (lower part zero), column stride ldr. Ra and Rb are staged in A and B (LDS).
+struct RProd {
+    const double *Ra, *Rb;
+    float *Rfinal;
+    int64_t ldr;
+};
+
+template <int W>
+QRX_DEV void r_product(const RProd &rp, int w, double *A, double *B, int t) {
+    constexpr int TW = W / 4;
+    for (int idx = t; idx < W * W; idx += GT) {
+        A[idx] = rp.Ra[idx];
+        B[idx] = rp.Rb[idx];
+    }
+    __syncthreads();
+    for (int tile = t; tile < TW * TW; tile += GT) {
+        const int i0 = 4 * (tile % TW), j0 = 4 * (tile / TW);
+        double v[4][4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[p][q] = 0.0;
+        for (int l = i0; l <= j0 + 3; ++l) {   // Ra[i][l] = 0 for l < i, Rb[l][j] = 0 for l > j
+            double a[4], b[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) a[p] = A[(i0 + p) + l * W];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[q] = B[l + (j0 + q) * W];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[p][q] = fma(a[p], b[q], v[p][q]);
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + p, j = j0 + q;
+                if (i < w && j < w) rp.Rfinal[i + (int64_t)j * rp.ldr] = (float)v[p][q];
+            }
+    }
+}
+
+// The final sweep (DO_Q only) may carry the R product: one extra workgroup,
+// the last, computes it while the others sweep.
 template <int W, bool DO_Q, bool DO_G>
 __global__ __launch_bounds__(GT, 2) void gram_pass_kernel(float *__restrict__ P, int64_t ld,
                                                        int64_t m, int w, int64_t chunks_per,
                                                        const double *__restrict__ X,
                                                        double *__restrict__ part,
                                                        const int *__restrict__ skip,
-                                                       PanelPack pk) {
+                                                       PanelPack pk, RProd rp) {
     if (skip && *skip) return;   // the first sweep already gave an orthonormal Q
     using L = gram::Lds<W>;
     __shared__ __align__(16) double C[L::C_DOUBLES];
     __shared__ __align__(16) double Xs[DO_Q ? L::X_DOUBLES : 2];
     __shared__ __align__(16) double red[DO_G ? L::RED_DOUBLES : 2];
     const int t = threadIdx.x;
+    if constexpr (DO_Q && !DO_G) {
+        static_assert(L::C_DOUBLES >= W * W && L::X_DOUBLES >= W * W, "R product staging");
+        if (rp.Rfinal && blockIdx.x == gridDim.x - 1) {
+            r_product<W>(rp, w, C, Xs, t);
+            return;
+        }
+    }
     const int64_t nch = (m + CH - 1) / CH;
     const int64_t ch0 = (int64_t)blockIdx.x * chunks_per;
     const int64_t ch1 = (ch0 + chunks_per < nch) ? ch0 + chunks_per : nch;
@@ -276,80 +336,65 @@ __global__ __launch_bounds__(CT) void gram_reduce_kernel(const double *__restric
     }
 }
 
-// G[e] = sum over the partials: a workgroup owns 64 entries (one per lane),
-// its 8 waves sum interleaved subsets of the partials and the 8 sums are added
-// in a fixed order (deterministic). The last workgroup to finish then factors
-// G = R^T R with gram::chol_inv and writes R and X = R^{-1} (FP64, W x W,
-// column-major). If Rfinal is set, it also writes the panel's R block (FP32,
-// ldr): R Rprev when Rprev is set, else R.
+// One workgroup: G = the sum of nparts partials (a few, after gram_reduce),
+// added in partial order, then G = R^T R by gram::chol_inv, writing R and
+// X = R^{-1} (FP64, W x W, column-major). If Rfinal is set, it also writes the
+// panel's R block (FP32, ldr): R when Rprev is null; R Rprev when Rprev is set
+// and prod is nonzero (prod 0 leaves that product to the final sweep).
 // With skip set (second sweep: G is the Gram matrix of the rounded Q1), a G
 // within tau of the identity in every entry means Q1 is already orthonormal
 // to working accuracy: then R = Rprev is written, *skip = 1 and the final
 // sweep does nothing; otherwise *skip = 0 and the factorisation proceeds.
-// *counter must be 0 on entry; the last workgroup leaves it 0.
 template <int W>
 __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict__ part, int nparts,
-                                                       int w, double *__restrict__ G,
-                                                       int *__restrict__ counter,
-                                                       double *__restrict__ Rout,
+                                                       int w, double *__restrict__ Rout,
                                                        double *__restrict__ Xout,
                                                        const double *__restrict__ Rprev,
                                                        float *__restrict__ Rfinal, int64_t ldr,
-                                                       int *__restrict__ skip, double tau) {
+                                                       int *__restrict__ skip, double tau,
+                                                       int prod) {
     constexpr int NP = W * (W + 1) / 2;
     constexpr int LS = W + 1;
     constexpr int NW = CT / 64;
-    constexpr int RB = 16;
+    constexpr int PB = 4;                        // partials per round (PB * NQ loads in flight)
     constexpr int NQ = (W * W + CT - 1) / CT;   // entries of a W x W matrix per thread
     constexpr int TP = (W == 64 && CT == 512) ? 2 * (8 * W + 4) : 4 * W + 4;   // pivot rows
-    constexpr int U = (NW * 64 > TP) ? NW * 64 : TP;   // partial sums, then pivot rows
+    constexpr int U = (NW > TP) ? NW : TP;      // wave maxima, then pivot rows
     __shared__ double S[W * LS];       // G, then R (upper)
     __shared__ double Xs[W * LS];      // R^{-1}, then Rprev
-    __shared__ double Ub[U];           // partial sums, then pivot rows of the elimination
-    __shared__ int last;
+    __shared__ double Ub[U];           // wave maxima, then pivot rows of the elimination
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
-    const int e = blockIdx.x * 64 + lane;
+    double gv[NQ];
+    int off[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int idx = t + q * CT, i = idx % W, j = idx / W;
+        gv[q] = 0.0;
+        off[q] = (idx < W * W && i <= j && j < w) ? upk(i, j) : -1;
+    }
     {
-        // wave wv sums partials wv, wv + NW, ... in that order, with RB loads in
-        // flight per step (the partials come from every XCD: each round trip is long)
-        double s = 0.0;
-        if (e < NP) {
-            int b = wv;
-            for (; b + (RB - 1) * NW < nparts; b += RB * NW) {
-                double v[RB];
+        int p = 0;
+        for (; p + PB <= nparts; p += PB) {
+            double v[PB][NQ];
 #pragma unroll
-                for (int q = 0; q < RB; ++q) v[q] = part[(int64_t)(b + q * NW) * NP + e];
+            for (int b = 0; b < PB; ++b)
 #pragma unroll
-                for (int q = 0; q < RB; ++q) s += v[q];
-            }
-            for (; b < nparts; b += NW) s += part[(int64_t)b * NP + e];
+                for (int q = 0; q < NQ; ++q)
+                    v[b][q] = off[q] >= 0 ? part[(int64_t)(p + b) * NP + off[q]] : 0.0;
+#pragma unroll
+            for (int b = 0; b < PB; ++b)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) gv[q] += v[b][q];
         }
-        Ub[wv * 64 + lane] = s;
-    }
-    __syncthreads();
-    if (wv == 0 && e < NP) {
-        double s = Ub[lane];
+        for (; p < nparts; ++p)
 #pragma unroll
-        for (int q = 1; q < NW; ++q) s += Ub[q * 64 + lane];
-        G[e] = s;
+            for (int q = 0; q < NQ; ++q)
+                if (off[q] >= 0) gv[q] += part[(int64_t)p * NP + off[q]];
     }
-    __threadfence();
-    __syncthreads();
-    if (t == 0) last = (atomicAdd(counter, 1) == (int)gridDim.x - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (t == 0) atomicExch(counter, 0);
 
     double dev = 0.0;
     {
-        double gv[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {   // every load issued before the first use
-            const int idx = t + q * CT, i = idx % W, j = idx / W;
-            gv[q] = (idx < W * W && i <= j && j < w) ? G[upk(i, j)] : 0.0;
-        }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int idx = t + q * CT, i = idx % W, j = idx / W;
@@ -395,7 +440,7 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
         Rout[idx] = up ? S[i + j * LS] : 0.0;
         Xout[idx] = up ? Xs[i + j * LS] : 0.0;
     }
-    if (!Rfinal) return;
+    if (!Rfinal || (Rprev && !prod)) return;
     if (Rprev) {
         double rv[NQ];
 #pragma unroll
@@ -462,19 +507,19 @@ static GramSplit gram_split(int64_t m) {
     return {(int)parts, per};
 }
 
-// first-level workgroups per column block for nparts partials
+// first-level workgroups per column block for nparts partials (0: none)
 static int gram_slices(int nparts) {
+    if (nparts <= kDirectParts) return 0;
     const int s = (nparts + kSliceParts - 1) / kSliceParts;
-    return s < 1 ? 1 : (s > kMaxSlices ? kMaxSlices : s);
+    return s > kMaxSlices ? kMaxSlices : s;
 }
 
-// Workspace (doubles): parts * W(W+1)/2 (partials) + W(W+1)/2 (G) + 4 W^2
-// (R1, X1, R2, X2) + kMaxSlices * W(W+1)/2 (slice sums), then kGramCounterInts
-// ints: the completion counter of gram_chol and the skip flag of the second
-// sweep (the rest spare).
+// Workspace (doubles): parts * W(W+1)/2 (partials) + 4 W^2 (R1, X1, R2, X2)
+// + kMaxSlices * W(W+1)/2 (slice sums), then kGramCounterInts ints: the skip
+// flag of the second sweep at index 1 (the rest spare).
 size_t gram_workspace_doubles(int64_t m, int W) {
     const size_t np = (size_t)W * (W + 1) / 2;
-    return (size_t)gram_split(m).parts * np + np + 4 * (size_t)W * W + kMaxSlices * np +
+    return (size_t)gram_split(m).parts * np + 4 * (size_t)W * W + kMaxSlices * np +
            kGramCounterInts / 2;
 }
 
@@ -495,45 +540,45 @@ static hipError_t gram_go(hipStream_t s, float *P, int64_t ld, int64_t m, int w,
     const int64_t np = (int64_t)W * (W + 1) / 2;
     const GramSplit sp = gram_split(m);
     double *part = ws;
-    double *G = part + (size_t)sp.parts * np;
-    double *R1 = G + np;
+    double *R1 = part + (size_t)sp.parts * np;
     double *X1 = R1 + W * W;
     double *R2 = X1 + W * W;
     double *X2 = R2 + W * W;
     double *lvl = X2 + W * W;
-    int *counter = gram_counter(ws, m);
-    int *skip = counter + 1;
+    int *skip = gram_counter(ws, m) + 1;
     const unsigned cb = (unsigned)((np + 63) / 64);
     const int ns = gram_slices(sp.parts);
     // partials as gram_chol reads them: the slice sums when there are many
-    const double *cpart = ns > 1 ? lvl : part;
-    const int cparts = ns > 1 ? ns : sp.parts;
+    const double *cpart = ns ? lvl : part;
+    const int cparts = ns ? ns : sp.parts;
     auto reduce = [&] {
-        if (ns > 1)
+        if (ns)
             hipLaunchKernelGGL(gram_reduce_kernel<W>, dim3(cb, ns), dim3(CT), 0, s,
                                (const double *)part, sp.parts, lvl);
     };
     const int *noskip = nullptr;
     hipLaunchKernelGGL((gram_pass_kernel<W, false, true>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
-                       m, w, sp.chunks_per, (const double *)nullptr, part, noskip, none);
+                       m, w, sp.chunks_per, (const double *)nullptr, part, noskip, none, RProd{});
     reduce();
-    hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(cb), dim3(CT), 0, s, cpart, cparts, w, G,
-                       counter, R1, X1, (const double *)nullptr, reorth ? (float *)nullptr : R,
-                       ldr, (int *)nullptr, 0.0);
+    hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(1), dim3(CT), 0, s, cpart, cparts, w, R1, X1,
+                       (const double *)nullptr, reorth ? (float *)nullptr : R, ldr,
+                       (int *)nullptr, 0.0, 0);
     if (!reorth) {
         hipLaunchKernelGGL((gram_pass_kernel<W, true, false>), dim3(sp.parts), dim3(GT), 0, s, P,
                            ld, m, w, sp.chunks_per, (const double *)X1, (double *)nullptr, noskip,
-                           pk);
+                           pk, RProd{});
         return hipGetLastError();
     }
     hipLaunchKernelGGL((gram_pass_kernel<W, true, true>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
-                       m, w, sp.chunks_per, (const double *)X1, part, noskip, pk);
+                       m, w, sp.chunks_per, (const double *)X1, part, noskip, pk, RProd{});
     reduce();
-    hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(cb), dim3(CT), 0, s, cpart, cparts, w, G,
-                       counter, R2, X2, (const double *)R1, R, ldr, skip, kSkipTau);
-    hipLaunchKernelGGL((gram_pass_kernel<W, true, false>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
-                       m, w, sp.chunks_per, (const double *)X2, (double *)nullptr,
-                       (const int *)skip, pk);
+    hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(1), dim3(CT), 0, s, cpart, cparts, w, R2, X2,
+                       (const double *)R1, R, ldr, skip, kSkipTau, 0);
+    // R = R2 R1 by one more workgroup of the final sweep
+    const RProd rp{R2, R1, R, ldr};
+    hipLaunchKernelGGL((gram_pass_kernel<W, true, false>), dim3(sp.parts + 1), dim3(GT), 0, s, P,
+                       ld, m, w, sp.chunks_per, (const double *)X2, (double *)nullptr,
+                       (const int *)skip, pk, rp);
     return hipGetLastError();
 }
 

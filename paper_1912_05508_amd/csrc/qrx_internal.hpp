@@ -120,8 +120,8 @@ hipError_t launch_copy_r_block(hipStream_t s, const float *src, int64_t ld_src, 
                                float *R, int64_t ldr, const float *colmax);
 
 // gram.hip : Cholesky QR twice on an FP64 Gram matrix (panel of w <= 64 columns);
-// ws holds gram_workspace_doubles(m, 64) doubles and its counter
-// (gram_counter) must be zeroed once before the first panel.
+// ws holds gram_workspace_doubles(m, 64) doubles; its flag area (gram_counter)
+// is zeroed once before the first panel.
 // 16-bit operand copies a 64-column Gram panel writes with its Q (as pack_q
 // does): column-major qc (ldc) and row-major qr (ldq) of sc * Q, lo parts for
 // a split; prec 0 writes none.
