@@ -108,10 +108,14 @@ def roofline_of(stats):
                   "avg_launch_ms": avg_ms, "launches": s["launches"]}
 
 
+# extra QR options of every leg (--panel-width)
+QR_KW = {}
+
+
 def time_qr(h, A, Q, R, st, prec, steps, warmup, cutoff, timing=False):
     import torch
     for _ in range(warmup):
-        h.qr_out(A, Q, R, st, prec=prec, cutoff=cutoff)
+        h.qr_out(A, Q, R, st, prec=prec, cutoff=cutoff, **QR_KW)
     torch.cuda.synchronize()
     if timing:
         h.timing_reset()
@@ -119,7 +123,7 @@ def time_qr(h, A, Q, R, st, prec, steps, warmup, cutoff, timing=False):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        h.qr_out(A, Q, R, st, prec=prec, cutoff=cutoff)
+        h.qr_out(A, Q, R, st, prec=prec, cutoff=cutoff, **QR_KW)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     stats = None
@@ -187,7 +191,7 @@ def lls_bench(h, prec, m_n, repeats, precs=("fp16x3", "fp32", "fp16")):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             x, info = h.lstsq(A, b, prec=pr, tol=1e-10, max_iter=20000, cutoff=128,
-                              node_reorth=True)
+                              node_reorth=True, **QR_KW)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             infos.append(info)
@@ -254,6 +258,8 @@ def main():
     ap.add_argument("--m", type=int, default=32768)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--cutoff", type=int, default=128)
+    ap.add_argument("--panel-width", type=int, default=0,
+                    help="leaf panel width (0: the library default)")
     ap.add_argument("--lls", action="store_true", help="(kept for compatibility: lls is a default leg)")
     ap.add_argument("--lls-size", default=None, help="override the LLS workload size, e.g. 16384x2048")
     ap.add_argument("--lls-precs", default="fp16x3,fp32,fp16")
@@ -266,6 +272,8 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.panel_width:
+        QR_KW["panel_width"] = args.panel_width
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the multi-GPU row "
                                    "sharding is designed but not built", "n_gpus": args.gpus}))
@@ -303,7 +311,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"c2: QR of {m} x {n} A = U diag(s) V^T, s geometric 1..1e-3 "
                                f"(seed 0); {args.prec.upper()} MFMA trailing products with FP32 "
-                               f"accumulation, cutoff {args.cutoff}, 64-column panels (Cholesky QR "
+                               f"accumulation, cutoff {args.cutoff}, {args.panel_width or 64}-column panels (Cholesky QR "
                                f"on an FP64 Gram matrix, re-orthogonalised when needed)",
                    "m": m, "n": n, "flops_per_step": flops, "parallelism": "single GPU"},
     }

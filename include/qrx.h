@@ -65,8 +65,10 @@ typedef enum { QRX_FP32 = 0, QRX_FP16 = 1, QRX_BF16 = 2, QRX_FP16X3 = 3 } qrx_pr
 /* QR options; an all-zero struct selects the defaults. */
 typedef struct {
     int gemm_prec;        /* qrx_prec for recursion nodes wider than `cutoff` */
-    int panel_width;      /* nb: leaf panel width; 1..64 for the Gram panel (0 = 64),
-                             1..32 for the TSQR panel (0 = 32; Sec. 3.1.3 uses 32) */
+    int panel_width;      /* nb: leaf panel width; 1..128 for the Gram panel (0 = 64;
+                             65..128 factor the panel as two 64-column blocks of one
+                             Cholesky QR), 1..32 for the TSQR panel (0 = 32; Sec. 3.1.3
+                             uses 32) */
     int cutoff;           /* c: nodes of width <= c use FP32 products (0 = 128, the
                              cutoff of Alg. 2); rounded up to a multiple of nb */
     int block_rows;       /* b: TSQR block rows, only 256 is supported (0 = 256; Sec. 3.1.3) */

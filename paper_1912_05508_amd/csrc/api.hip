@@ -99,7 +99,7 @@ int resolve_qr(const qrx_qr_opts *o, QrCfg &c, bool lls = false) {
     if (!o) o = &z;
     if (o->gemm_prec < 0 || o->gemm_prec > 3) return QRX_EINVAL;
     if (o->panel_alg < 0 || o->panel_alg > 1) return QRX_EINVAL;
-    const int max_nb = o->panel_alg == 1 ? 32 : 64;
+    const int max_nb = o->panel_alg == 1 ? 32 : 128;
     if (o->panel_width < 0 || o->panel_width > max_nb) return QRX_EINVAL;
     if (o->cutoff < 0) return QRX_EINVAL;
     if (o->block_rows != 0 && o->block_rows != kPanelThreads) return QRX_EINVAL;
@@ -217,7 +217,7 @@ void carve_qr(Carve &cv, int64_t m, int64_t n, const QrCfg &c, const std::vector
     for (size_t l = 1; l < nblk.size(); ++l) st += (size_t)nblk[l - 1] * 32 * 32 + 64;
     w.stack_floats = st;
     w.stack_base = cv.take<float>(c.alg == 1 ? st + 1 : 1);
-    w.gram = cv.take<double>(c.alg == 0 ? gram_workspace_doubles(m, 64) : 1);
+    w.gram = cv.take<double>(c.alg == 0 ? gram_workspace_doubles(m, c.nb > 64 ? 128 : 64) : 1);
     w.qc = w.qcl = w.qr = w.qrl = w.rh = w.rhl = w.a2h = w.a2l = nullptr;
     w.ldc = round_up(m, 8);
     w.ldq = round_up(n, 8);
@@ -337,7 +337,7 @@ int run_panel_core(qrx_handle h, hipStream_t s, int64_t m, float *P, int64_t ld,
 // column max-abs of W on entry.
 int run_qr(qrx_handle h, hipStream_t s, int64_t m, int64_t n, float *W, int64_t ldw, float *R,
            int64_t ldr, const QrCfg &c, const std::vector<Op> &ops, QrWork &ws) {
-    if (c.alg == 0) QRX_TRY(launch_fill_f32(s, (float *)gram_counter(ws.gram, m), kGramCounterInts, 0.0f));
+    if (c.alg == 0) QRX_TRY(launch_fill_f32(s, (float *)gram_counter(ws.gram), kGramCounterInts, 0.0f));
     for (const Op &o : ops) {
         if (o.kind == 0) {
             int rc = run_panel(h, s, m, W, ldw, o.c0, (int)o.k, R, ldr, c, ws);

@@ -32,6 +32,8 @@
 // gram_pass<Q>.
 #include "gram_common.hpp"
 
+#include <algorithm>
+
 namespace qrx {
 
 using gram::CH;
@@ -514,18 +516,36 @@ static int gram_slices(int nparts) {
     return s > kMaxSlices ? kMaxSlices : s;
 }
 
-// Workspace (doubles): parts * W(W+1)/2 (partials) + 4 W^2 (R1, X1, R2, X2)
-// + kMaxSlices * W(W+1)/2 (slice sums), then kGramCounterInts ints: the skip
-// flag of the second sweep at index 1 (the rest spare).
-size_t gram_workspace_doubles(int64_t m, int W) {
-    const size_t np = (size_t)W * (W + 1) / 2;
-    return (size_t)gram_split(m).parts * np + 4 * (size_t)W * W + kMaxSlices * np +
-           kGramCounterInts / 2;
+// 128-column panels: at most this many partials (two chunks per sweep workgroup
+// at m = 32768; a partial is 66 KB)
+constexpr int kLeafParts = 256;
+
+static GramSplit leaf_split(int64_t m) {
+    const int64_t nch = (m + CH - 1) / CH;
+    int64_t parts = nch < kLeafParts ? nch : kLeafParts;
+    if (parts < 1) parts = 1;
+    const int64_t per = (nch + parts - 1) / parts;
+    parts = (nch + per - 1) / per;
+    if (parts < 1) parts = 1;
+    return {(int)parts, per};
 }
 
-int *gram_counter(double *ws, int64_t m) {
-    return reinterpret_cast<int *>(ws + gram_workspace_doubles(m, 64) - kGramCounterInts / 2);
+// Workspace (doubles): kGramCounterInts ints of flags (the skip flag of the
+// second sweep at index 1, the rest spare), then parts * W(W+1)/2 (partials),
+// 4 W^2 (R1, X1, R2, X2) and kMaxSlices * W(W+1)/2 (slice sums). Sized for
+// panels up to wmax columns (64 or 128).
+size_t gram_workspace_doubles(int64_t m, int wmax) {
+    size_t n = 0;
+    for (int W : {64, 128}) {
+        if (W > wmax) break;
+        const size_t np = (size_t)W * (W + 1) / 2;
+        const size_t parts = W == 128 ? leaf_split(m).parts : gram_split(m).parts;
+        n = std::max(n, parts * np + 4 * (size_t)W * W + kMaxSlices * np);
+    }
+    return kGramCounterInts / 2 + n;
 }
+
+int *gram_counter(double *ws) { return reinterpret_cast<int *>(ws); }
 
 // Re-orthogonalisation is skipped when every entry of Q1^T Q1 is within this
 // of the identity (a few FP32 rounding units: a second sweep could not do better).
@@ -539,13 +559,13 @@ static hipError_t gram_go(hipStream_t s, float *P, int64_t ld, int64_t m, int w,
     const PanelPack &pk = (W == 64) ? pack : none;   // sweeps of width 64 write the copies
     const int64_t np = (int64_t)W * (W + 1) / 2;
     const GramSplit sp = gram_split(m);
-    double *part = ws;
+    double *part = ws + kGramCounterInts / 2;
     double *R1 = part + (size_t)sp.parts * np;
     double *X1 = R1 + W * W;
     double *R2 = X1 + W * W;
     double *X2 = R2 + W * W;
     double *lvl = X2 + W * W;
-    int *skip = gram_counter(ws, m) + 1;
+    int *skip = gram_counter(ws) + 1;
     const unsigned cb = (unsigned)((np + 63) / 64);
     const int ns = gram_slices(sp.parts);
     // partials as gram_chol reads them: the slice sums when there are many
@@ -582,13 +602,557 @@ static hipError_t gram_go(hipStream_t s, float *P, int64_t ld, int64_t m, int w,
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// 128-column panels: one Cholesky QR over a whole 128-column leaf of the
+// recursion, its halves A | B (64 columns each) kept as blocks.
+//   G = [A B]^T [A B] in one sweep; R_AA = chol(G_AA), R_AB = R_AA^{-T} G_AB,
+//   R_BB = chol(G_BB - R_AB^T R_AB); X = R^{-1} has X_AA = R_AA^{-1},
+//   X_BB = R_BB^{-1}, X_AB = -X_AA R_AB X_BB; Q = [A B] X in one more sweep.
+// This is Cholesky QR of the 128 columns (the same R as two 64-column panels
+// with the B half projected onto and updated by Q_A in between, in exact
+// arithmetic), with one Gram matrix and one elimination chain per sweep pair
+// instead of two, and no separate projection and update for the B half.
+// Sweeps: 8 waves per workgroup on 64-row chunks. LDS: the chunk as two FP64
+// halves, and for Q formation X_AB (full) and X_AA, X_BB in one array: X_AA
+// above the diagonal shifted one column right, X_BB transposed on and below
+// the diagonal (reads outside a triangle are masked to zero).
+// ---------------------------------------------------------------------------
+namespace leaf {
+constexpr int W = 128, H = 64, NT = 512, LD = 66;
+constexpr int NP = W * (W + 1) / 2;   // 8256 Gram entries
+constexpr int LPT = CH * W / NT;      // chunk elements per thread
+constexpr int NPAIR = 36;             // upper 16 x 16 block pairs of a 128 x 128 Gram
+constexpr int MAXP = 5;               // pairs per wave: p = wave + 8 q
+constexpr int CD = CH * LD;           // doubles of one LDS block
+
+// block pair p (0 <= p < 36) of the upper triangle: (I, J), I <= J, by columns
+QRX_DEV void pair(int p, int &I, int &J) {
+    int j = 0;
+    while ((j + 1) * (j + 2) / 2 <= p) ++j;
+    J = j;
+    I = p - j * (j + 1) / 2;
+}
+
+// X (W x W, FP64, column-major, zero below the diagonal) into the LDS blocks
+QRX_DEV void load_x(const double *__restrict__ X, double *XT, double *XAB, int t) {
+#pragma unroll 2
+    for (int idx = t; idx < H * H; idx += NT) {
+        const int k = idx % H, j = idx / H;
+        const double aa = X[k + j * W], ab = X[k + (H + j) * W], bb = X[(H + k) + (H + j) * W];
+        XAB[k * LD + j] = ab;
+        if (k <= j) {
+            XT[k * LD + j + 1] = aa;
+            XT[j * LD + k] = bb;
+        }
+    }
+}
+
+// One sweep over row chunks [ch0, ch1) of P (m x w, 64 < w <= 128). DO_Q: rows
+// <- fl32(rows X) (X in XT, XAB), written back to P and, when pk.prec is set,
+// to the 16-bit operand copies. DO_G: acc += this wave's Gram blocks of the
+// (rounded) rows. The next chunk is prefetched into registers.
+template <bool DO_Q, bool DO_G>
+QRX_DEV void sweep(float *__restrict__ P, int64_t ld, int64_t m, int w, int64_t ch0, int64_t ch1,
+                   const double *XT, const double *XAB, double *CA, double *CB,
+                   d4 (&acc)[MAXP], int t, const PanelPack &pk) {
+    const int lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int li = lane & 15, lk = lane >> 4;
+    int PI[MAXP], PJ[MAXP];   // this wave's Gram block pairs
+#pragma unroll
+    for (int qq = 0; qq < MAXP; ++qq) pair(wv + 8 * qq < NPAIR ? wv + 8 * qq : 0, PI[qq], PJ[qq]);
+    float pre[LPT];
+    // element s of this thread: row e % CH, column e / CH = wave + 8 s (A half for s < 8)
+    auto load = [&](int64_t ch) {
+#pragma unroll
+        for (int s = 0; s < LPT; ++s) {
+            const int e = t + NT * s;
+            const int rr = e % CH, cc = e / CH;
+            const int64_t r = ch * CH + rr;
+            pre[s] = (r < m && cc < w) ? P[r + cc * ld] : 0.0f;
+        }
+    };
+    if (ch0 < ch1) load(ch0);
+    for (int64_t ch = ch0; ch < ch1; ++ch) {
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < LPT; ++s) {
+            const int e = t + NT * s;
+            const int rr = e % CH, cc = e / CH;
+            if (s < LPT / 2) CA[rr * LD + cc] = (double)pre[s];
+            else CB[rr * LD + cc - H] = (double)pre[s];
+        }
+        __syncthreads();
+        if (ch + 1 < ch1) load(ch + 1);
+        if constexpr (DO_Q) {
+            // rows 16 Rb .. 16 Rb + 15; part 0: Q_A (4 column blocks) and Q_B block 3,
+            // part 1: Q_B blocks 0..2 (72 MFMAs each)
+            const int Rb = wv & 3, part = wv >> 2;
+            const double *rowA = CA + (16 * Rb + li) * LD, *rowB = CB + (16 * Rb + li) * LD;
+            d4 q[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) q[b] = d4{0.0, 0.0, 0.0, 0.0};
+            if (part == 0) {
+#pragma unroll
+                for (int Jb = 0; Jb < 4; ++Jb) {
+                    const int j = 16 * Jb + li;
+#pragma unroll 2
+                    for (int k4 = 0; k4 < 4 * Jb; ++k4)
+                        q[Jb] = mfma64(rowA[4 * k4 + lk], XT[(4 * k4 + lk) * LD + j + 1], q[Jb]);
+#pragma unroll
+                    for (int k4 = 4 * Jb; k4 < 4 * Jb + 4; ++k4) {
+                        const int k = 4 * k4 + lk;
+                        q[Jb] = mfma64(rowA[k], k <= j ? XT[k * LD + j + 1] : 0.0, q[Jb]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int Jb = 0; Jb < 3; ++Jb) {
+                    const int j = 16 * Jb + li;
+#pragma unroll 2
+                    for (int k4 = 0; k4 < 16; ++k4)
+                        q[Jb] = mfma64(rowA[4 * k4 + lk], XAB[(4 * k4 + lk) * LD + j], q[Jb]);
+#pragma unroll 2
+                    for (int k4 = 0; k4 < 4 * Jb; ++k4)
+                        q[Jb] = mfma64(rowB[4 * k4 + lk], XT[j * LD + 4 * k4 + lk], q[Jb]);
+#pragma unroll
+                    for (int k4 = 4 * Jb; k4 < 4 * Jb + 4; ++k4) {
+                        const int k = 4 * k4 + lk;
+                        q[Jb] = mfma64(rowB[k], k <= j ? XT[j * LD + k] : 0.0, q[Jb]);
+                    }
+                }
+            }
+            d4 qb3 = d4{0.0, 0.0, 0.0, 0.0};
+            if (part == 0) {
+                const int j = 48 + li;
+#pragma unroll 2
+                for (int k4 = 0; k4 < 16; ++k4)
+                    qb3 = mfma64(rowA[4 * k4 + lk], XAB[(4 * k4 + lk) * LD + j], qb3);
+#pragma unroll 2
+                for (int k4 = 0; k4 < 16; ++k4) {
+                    const int k = 4 * k4 + lk;   // k <= 63 < j + 1 except on the diagonal block
+                    qb3 = mfma64(rowB[k], k <= j ? XT[j * LD + k] : 0.0, qb3);
+                }
+            }
+            __syncthreads();   // every wave has read its rows of the chunk
+            double *outq = part == 0 ? CA : CB;
+#pragma unroll
+            for (int Jb = 0; Jb < 4; ++Jb) {
+                if (part == 1 && Jb == 3) break;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    outq[(16 * Rb + 4 * v + lk) * LD + 16 * Jb + li] = (double)(float)q[Jb][v];
+            }
+            if (part == 0) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    CB[(16 * Rb + 4 * v + lk) * LD + 48 + li] = (double)(float)qb3[v];
+            }
+            __syncthreads();
+            // Q rows back to P, coalesced along the columns
+#pragma unroll
+            for (int s = 0; s < LPT; ++s) {
+                const int e = t + NT * s;
+                const int rr = e % CH, cc = e / CH;
+                const int64_t r = ch * CH + rr;
+                const double v = (s < LPT / 2) ? CA[rr * LD + cc] : CB[rr * LD + cc - H];
+                if (r < m && cc < w) P[r + cc * ld] = (float)v;
+            }
+            if (pk.prec) {
+#pragma unroll 1
+                for (int s = 0; s < LPT; ++s) {
+                    const int e = t + NT * s;
+                    const int rr = e % CH, cc = e / CH;
+                    const int64_t r = ch * CH + rr;
+                    const double v = (s < LPT / 2) ? CA[rr * LD + cc] : CB[rr * LD + cc - H];
+                    if (r < m && cc < w)
+                        store16(pk.qc, pk.qcl, r + cc * pk.ldc, (float)v * pk.sc, pk.prec);
+                }
+#pragma unroll 1
+                for (int s = 0; s < LPT; ++s) {
+                    const int e = t + NT * s;
+                    const int cc = e % W, rr = e / W;
+                    const int64_t r = ch * CH + rr;
+                    const double v = cc < H ? CA[rr * LD + cc] : CB[rr * LD + cc - H];
+                    if (r < m && cc < w)
+                        store16(pk.qr, pk.qrl, r * pk.ldq + cc, (float)v * pk.sc, pk.prec);
+                }
+            }
+        }
+        if constexpr (DO_G) {
+#pragma unroll 2
+            for (int k4 = 0; k4 < CH / 4; ++k4) {
+                const double *ra = CA + (4 * k4 + lk) * LD + li;
+                const double *rb = CB + (4 * k4 + lk) * LD + li;
+#pragma unroll
+                for (int qq = 0; qq < MAXP; ++qq) {
+                    if (wv + 8 * qq >= NPAIR) break;
+                    const int I = PI[qq], J = PJ[qq];
+                    const double a = I < 4 ? ra[16 * I] : rb[16 * (I - 4)];
+                    const double b = J < 4 ? ra[16 * J] : rb[16 * (J - 4)];
+                    acc[qq] = mfma64(a, b, acc[qq]);
+                }
+            }
+        }
+    }
+}
+
+// this wave's Gram blocks into out[upk(i, j)], i <= j
+QRX_DEV void gram_store(const d4 (&acc)[MAXP], double *out, int t) {
+    const int lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+#pragma unroll
+    for (int qq = 0; qq < MAXP; ++qq) {
+        const int p = wv + 8 * qq;
+        if (p >= NPAIR) break;
+        int I, J;
+        pair(p, I, J);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * I + 4 * v + (lane >> 4), j = 16 * J + (lane & 15);
+            if (i <= j) out[upk(i, j)] = acc[qq][v];
+        }
+    }
+}
+
+// R = Ra Rb (both W x W upper triangular, FP64, column-major) into Rfinal
+// (FP32, ldr, w x w), through LDS in two 64-deep slabs: A = Ra[:, kb..kb+63]
+// (column-major, ld W), B = Rb[kb..kb+63, :] (column-major, ld H).
+QRX_DEV void r_product(const RProd &rp, int w, double *L, int t) {
+    double *A = L, *B = L + W * H;
+    const int i0 = 4 * (t % 32), j0 = 8 * (t / 32);
+    double v[4][8];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[p][q] = 0.0;
+    for (int kb = 0; kb < W; kb += H) {
+        __syncthreads();
+        for (int idx = t; idx < W * H; idx += NT) {
+            A[idx] = rp.Ra[(idx % W) + (int64_t)(kb + idx / W) * W];
+            B[idx] = rp.Rb[(kb + idx % H) + (int64_t)(idx / H) * W];
+        }
+        __syncthreads();
+        const int lo = i0 > kb ? i0 : kb;
+        const int hi = (j0 + 7 < kb + H - 1) ? j0 + 7 : kb + H - 1;
+        for (int l = lo; l <= hi; ++l) {
+            double a[4], b[8];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) a[p] = A[(i0 + p) + (l - kb) * W];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) b[q] = B[(l - kb) + (j0 + q) * H];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[p][q] = fma(a[p], b[q], v[p][q]);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = i0 + p, j = j0 + q;
+            if (i < w && j < w) rp.Rfinal[i + (int64_t)j * rp.ldr] = (float)v[p][q];
+        }
+}
+}  // namespace leaf
+
+// One sweep of a 128-column panel over this workgroup's chunks (as
+// gram_pass_kernel); the final sweep may carry the R product in one extra
+// workgroup, the last.
+template <bool DO_Q, bool DO_G>
+__global__ __launch_bounds__(leaf::NT, DO_Q ? 2 : 4) void gram_leaf_pass_kernel(
+    float *__restrict__ P, int64_t ld, int64_t m, int w, int64_t chunks_per,
+    const double *__restrict__ X, double *__restrict__ part, const int *__restrict__ skip,
+    PanelPack pk, RProd rp) {
+    using namespace leaf;
+    if (skip && *skip) return;   // the first sweep already gave an orthonormal Q
+    __shared__ __align__(16) double L[(DO_Q ? 4 : 2) * CD];
+    double *CA = L, *CB = L + CD, *XT = L + 2 * CD, *XAB = L + 3 * CD;
+    const int t = threadIdx.x;
+    if constexpr (DO_Q && !DO_G) {
+        static_assert(4 * CD >= 2 * W * H, "R product staging");
+        if (rp.Rfinal && blockIdx.x == gridDim.x - 1) {
+            r_product(rp, w, L, t);
+            return;
+        }
+    }
+    const int64_t nch = (m + CH - 1) / CH;
+    const int64_t ch0 = (int64_t)blockIdx.x * chunks_per;
+    const int64_t ch1 = (ch0 + chunks_per < nch) ? ch0 + chunks_per : nch;
+    if constexpr (DO_Q) load_x(X, XT, XAB, t);
+    d4 acc[MAXP];
+#pragma unroll
+    for (int qq = 0; qq < MAXP; ++qq) acc[qq] = d4{0.0, 0.0, 0.0, 0.0};
+    sweep<DO_Q, DO_G>(P, ld, m, w, ch0, ch1, XT, XAB, CA, CB, acc, t, pk);
+    if constexpr (DO_G) gram_store(acc, part + (int64_t)blockIdx.x * NP, t);
+}
+
+// One workgroup: G (128 x 128, the sum of nparts partials in partial order),
+// then the blocked factorisation and inverse described above, writing R and X
+// (FP64, 128 x 128, column-major, zero below the diagonal) and, if Rfinal is
+// set and Rprev is null, the panel's R block (FP32, ldr). With skip set the
+// orthogonality check of gram_chol_kernel runs first: on success R = Rprev
+// goes to Rfinal; otherwise the product R Rprev is left to the final sweep.
+__global__ __launch_bounds__(CT) void gram_chol_leaf_kernel(const double *__restrict__ part,
+                                                            int nparts, int w,
+                                                            double *__restrict__ Rout,
+                                                            double *__restrict__ Xout,
+                                                            const double *__restrict__ Rprev,
+                                                            float *__restrict__ Rfinal,
+                                                            int64_t ldr, int *__restrict__ skip,
+                                                            double tau) {
+    using leaf::H;
+    using leaf::NP;
+    using leaf::W;
+    constexpr int LS = H + 1;
+    constexpr int NW = CT / 64;
+    constexpr int NQ = (NP + CT - 1) / CT;   // packed entries per thread
+    constexpr int PB = 2;
+    __shared__ double S[H * LS];     // G_AA -> R_AA, then X_BB
+    __shared__ double Xs[H * LS];    // X_AA
+    __shared__ double GAB[H * LS];   // G_AB -> R_AB
+    __shared__ double GBB[H * LS];   // G_BB -> S_BB -> R_BB, then R_AB X_BB
+    __shared__ double Ub[2 * (8 * H + 4)];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    const bool rfin = Rfinal && !Rprev;   // R block written here (single pass)
+    double gv[NQ];
+    int ii[NQ], jj[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int e = t + q * CT;
+        int j = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while (j * (j + 1) / 2 > e) --j;
+        while ((j + 1) * (j + 2) / 2 <= e) ++j;
+        jj[q] = j;
+        ii[q] = e - j * (j + 1) / 2;
+        gv[q] = 0.0;
+    }
+    {
+        int p = 0;
+        for (; p + PB <= nparts; p += PB) {
+            double v[PB][NQ];
+#pragma unroll
+            for (int b = 0; b < PB; ++b)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int e = t + q * CT;
+                    v[b][q] = e < NP ? part[(int64_t)(p + b) * NP + e] : 0.0;
+                }
+#pragma unroll
+            for (int b = 0; b < PB; ++b)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) gv[q] += v[b][q];
+        }
+        for (; p < nparts; ++p)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int e = t + q * CT;
+                if (e < NP) gv[q] += part[(int64_t)p * NP + e];
+            }
+    }
+    double dev = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int e = t + q * CT;
+        if (e >= NP) continue;
+        const int i = ii[q], j = jj[q];
+        if (j < H) S[i + j * LS] = gv[q];
+        else if (i < H) GAB[i + (j - H) * LS] = gv[q];
+        else GBB[(i - H) + (j - H) * LS] = gv[q];
+        if (j < w) {
+            const double e2 = fabs(gv[q] - (i == j ? 1.0 : 0.0));
+            dev = fmax(dev, (e2 == e2) ? e2 : 1e300);   // a NaN entry never passes
+        }
+    }
+    if (skip) {
+#pragma unroll
+        for (int o2 = 32; o2 > 0; o2 >>= 1) dev = fmax(dev, __shfl_xor(dev, o2));
+        if (lane == 0) Ub[wv] = dev;
+        __syncthreads();
+        double mx = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) mx = fmax(mx, Ub[q]);
+        const bool done = mx <= tau;   // NaN compares false: factorise
+        if (t == 0) *skip = done ? 1 : 0;
+        if (done) {
+            for (int idx = t; idx < W * W; idx += CT) {
+                const int i = idx % W, j = idx / W;
+                if (i < w && j < w) Rfinal[i + (int64_t)j * ldr] = (float)Rprev[idx];
+            }
+            return;
+        }
+    }
+    __syncthreads();
+    // R_AA, X_AA
+    gram::chol_inv<H, CT>(S, Xs, Ub, t);
+    for (int idx = t; idx < H * H; idx += CT) {
+        const int i = idx % H, j = idx / H;
+        const bool up = i <= j;
+        const double r = up ? S[i + j * LS] : 0.0;
+        Rout[i + j * W] = r;
+        Xout[i + j * W] = up ? Xs[i + j * LS] : 0.0;
+        Rout[(H + i) + j * W] = 0.0;
+        Xout[(H + i) + j * W] = 0.0;
+        if (rfin) {
+            if (i < w && j < w) Rfinal[i + (int64_t)j * ldr] = (float)r;
+            if (H + i < w && j < w) Rfinal[(H + i) + (int64_t)j * ldr] = 0.0f;
+        }
+    }
+    // 2 x 4 tiles of a 64 x 64 block per thread
+    const int i0 = 2 * (t % 32), j0 = 4 * (t / 32);
+    double v[2][4];
+    auto zero = [&] {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[p][q] = 0.0;
+    };
+    // R_AB = X_AA^T G_AB (X_AA[k][i] = 0 for k > i)
+    zero();
+    for (int k = 0; k <= i0 + 1; ++k) {
+        const double a0 = Xs[k + i0 * LS], a1 = Xs[k + (i0 + 1) * LS];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double b = GAB[k + (j0 + q) * LS];
+            v[0][q] = fma(a0, b, v[0][q]);
+            v[1][q] = fma(a1, b, v[1][q]);
+        }
+    }
+    __syncthreads();   // every read of G_AB is done
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + p, j = j0 + q;
+            GAB[i + j * LS] = v[p][q];
+            Rout[i + (H + j) * W] = v[p][q];
+            if (rfin && i < w && H + j < w) Rfinal[i + (int64_t)(H + j) * ldr] = (float)v[p][q];
+        }
+    __syncthreads();
+    // S_BB = G_BB - R_AB^T R_AB (upper part; each thread its own entries)
+    zero();
+    for (int k = 0; k < H; ++k) {
+        const double a0 = GAB[k + i0 * LS], a1 = GAB[k + (i0 + 1) * LS];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double b = GAB[k + (j0 + q) * LS];
+            v[0][q] = fma(a0, b, v[0][q]);
+            v[1][q] = fma(a1, b, v[1][q]);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + p, j = j0 + q;
+            if (i <= j) GBB[i + j * LS] -= v[p][q];
+        }
+    __syncthreads();
+    // R_BB (in GBB), X_BB (in S: R_AA is already out)
+    gram::chol_inv<H, CT>(GBB, S, Ub, t);
+    for (int idx = t; idx < H * H; idx += CT) {
+        const int i = idx % H, j = idx / H;
+        const bool up = i <= j;
+        const double r = up ? GBB[i + j * LS] : 0.0;
+        Rout[(H + i) + (H + j) * W] = r;
+        Xout[(H + i) + (H + j) * W] = up ? S[i + j * LS] : 0.0;
+        if (rfin && H + i < w && H + j < w) Rfinal[(H + i) + (int64_t)(H + j) * ldr] = (float)r;
+    }
+    // Y = R_AB X_BB (X_BB[k][j] = 0 for k > j)
+    zero();
+    for (int k = 0; k <= j0 + 3; ++k) {
+        const double a0 = GAB[i0 + k * LS], a1 = GAB[(i0 + 1) + k * LS];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double b = S[k + (j0 + q) * LS];
+            v[0][q] = fma(a0, b, v[0][q]);
+            v[1][q] = fma(a1, b, v[1][q]);
+        }
+    }
+    __syncthreads();   // every read of R_BB is done
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) GBB[(i0 + p) + (j0 + q) * LS] = v[p][q];
+    __syncthreads();
+    // X_AB = -X_AA Y (X_AA[i][k] = 0 for k < i)
+    zero();
+    for (int k = i0; k < H; ++k) {
+        const double a0 = Xs[i0 + k * LS], a1 = Xs[(i0 + 1) + k * LS];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double b = GBB[k + (j0 + q) * LS];
+            v[0][q] = fma(a0, b, v[0][q]);
+            v[1][q] = fma(a1, b, v[1][q]);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xout[(i0 + p) + (H + j0 + q) * W] = -v[p][q];
+}
+
+static hipError_t leaf_go(hipStream_t s, float *P, int64_t ld, int64_t m, int w, float *R,
+                          int64_t ldr, double *ws, int reorth, const PanelPack &pk) {
+    using leaf::NP;
+    using leaf::NT;
+    using leaf::W;
+    const GramSplit sp = leaf_split(m);
+    double *part = ws + kGramCounterInts / 2;
+    double *R1 = part + (size_t)sp.parts * NP;
+    double *X1 = R1 + W * W;
+    double *R2 = X1 + W * W;
+    double *X2 = R2 + W * W;
+    double *lvl = X2 + W * W;
+    int *skip = gram_counter(ws) + 1;
+    const unsigned cb = (unsigned)((NP + 63) / 64);
+    const int ns = gram_slices(sp.parts);
+    const double *cpart = ns ? lvl : part;
+    const int cparts = ns ? ns : sp.parts;
+    auto reduce = [&] {
+        if (ns)
+            hipLaunchKernelGGL(gram_reduce_kernel<W>, dim3(cb, ns), dim3(CT), 0, s,
+                               (const double *)part, sp.parts, lvl);
+    };
+    PanelPack none = pk;
+    none.prec = 0;
+    const int *noskip = nullptr;
+    hipLaunchKernelGGL((gram_leaf_pass_kernel<false, true>), dim3(sp.parts), dim3(NT), 0, s, P, ld,
+                       m, w, sp.chunks_per, (const double *)nullptr, part, noskip, none, RProd{});
+    reduce();
+    hipLaunchKernelGGL(gram_chol_leaf_kernel, dim3(1), dim3(CT), 0, s, cpart, cparts, w, R1, X1,
+                       (const double *)nullptr, reorth ? (float *)nullptr : R, ldr,
+                       (int *)nullptr, 0.0);
+    if (!reorth) {
+        hipLaunchKernelGGL((gram_leaf_pass_kernel<true, false>), dim3(sp.parts), dim3(NT), 0, s,
+                           P, ld, m, w, sp.chunks_per, (const double *)X1, (double *)nullptr,
+                           noskip, pk, RProd{});
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((gram_leaf_pass_kernel<true, true>), dim3(sp.parts), dim3(NT), 0, s, P, ld,
+                       m, w, sp.chunks_per, (const double *)X1, part, noskip, pk, RProd{});
+    reduce();
+    hipLaunchKernelGGL(gram_chol_leaf_kernel, dim3(1), dim3(CT), 0, s, cpart, cparts, w, R2, X2,
+                       (const double *)R1, R, ldr, skip, kSkipTau);
+    // R = R2 R1 by one more workgroup of the final sweep
+    const RProd rp{R2, R1, R, ldr};
+    hipLaunchKernelGGL((gram_leaf_pass_kernel<true, false>), dim3(sp.parts + 1), dim3(NT), 0, s,
+                       P, ld, m, w, sp.chunks_per, (const double *)X2, (double *)nullptr,
+                       (const int *)skip, pk, rp);
+    return hipGetLastError();
+}
+
 bool gram_panel_packs(int w) { return w > 32; }
 
 hipError_t launch_gram_panel(hipStream_t s, float *P, int64_t ld, int64_t m, int w, float *R,
                              int64_t ldr, double *ws, int reorth, const PanelPack &pack) {
     if (w <= 16) return gram_go<16>(s, P, ld, m, w, R, ldr, ws, reorth, pack);
     if (w <= 32) return gram_go<32>(s, P, ld, m, w, R, ldr, ws, reorth, pack);
-    return gram_go<64>(s, P, ld, m, w, R, ldr, ws, reorth, pack);
+    if (w <= 64) return gram_go<64>(s, P, ld, m, w, R, ldr, ws, reorth, pack);
+    if (w <= 128) return leaf_go(s, P, ld, m, w, R, ldr, ws, reorth, pack);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace qrx

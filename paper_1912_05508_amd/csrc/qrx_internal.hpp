@@ -119,9 +119,9 @@ hipError_t launch_tsqr_qform(hipStream_t s, float *P, int64_t ld, int64_t m, int
 hipError_t launch_copy_r_block(hipStream_t s, const float *src, int64_t ld_src, int w,
                                float *R, int64_t ldr, const float *colmax);
 
-// gram.hip : Cholesky QR twice on an FP64 Gram matrix (panel of w <= 64 columns);
-// ws holds gram_workspace_doubles(m, 64) doubles; its flag area (gram_counter)
-// is zeroed once before the first panel.
+// gram.hip : Cholesky QR twice on an FP64 Gram matrix (panel of w <= 128 columns);
+// ws holds gram_workspace_doubles(m, wmax) doubles for panels up to wmax (64 or
+// 128) columns; its flag area (gram_counter) is zeroed once before the first panel.
 // 16-bit operand copies a 64-column Gram panel writes with its Q (as pack_q
 // does): column-major qc (ldc) and row-major qr (ldq) of sc * Q, lo parts for
 // a split; prec 0 writes none.
@@ -136,8 +136,8 @@ bool gram_panel_packs(int w);
 hipError_t launch_gram_panel(hipStream_t s, float *P, int64_t ld, int64_t m, int w, float *R,
                              int64_t ldr, double *ws, int reorth, const PanelPack &pack);
 constexpr int kGramCounterInts = 64;   // ints at gram_counter, all 0 before the first panel
-size_t gram_workspace_doubles(int64_t m, int W);
-int *gram_counter(double *ws, int64_t m);
+size_t gram_workspace_doubles(int64_t m, int wmax);
+int *gram_counter(double *ws);
 
 // gemm.hip : trailing products of one recursion node.
 //   projection: Part[s] (k x n2, ld k) = Q1^T A2 over row split s.

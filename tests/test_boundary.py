@@ -82,7 +82,7 @@ def test_qr_bad_pointers_and_options(lib, host_handle):
     assert lib.qrx_qr_factor(host_handle, 10, 3, None, 10, FAKE, 3, None, 0, None, None, None) == L.QRX_EINVAL
     assert lib.qrx_qr_factor(host_handle, 10, 3, FAKE, 10, None, 3, None, 0, None, None, None) == L.QRX_EINVAL
     for field, val, panel in (("gemm_prec", 4, "gram"), ("gemm_prec", -1, "gram"),
-                              ("panel_width", 65, "gram"), ("panel_width", 33, "tsqr"),
+                              ("panel_width", 129, "gram"), ("panel_width", 33, "tsqr"),
                               ("cutoff", -4, "gram"), ("block_rows", 128, "gram"),
                               ("no_col_scaling", 2, "gram"), ("panel_alg", 2, "gram"),
                               ("gemm_tiles", 2, "gram"), ("split_target", 8, "gram"),

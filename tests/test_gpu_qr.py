@@ -31,7 +31,8 @@ def _run(qrx, A, prec="fp32", ld=None, **kw):
     return host(Q), host(R), int(st.item())
 
 
-@pytest.mark.parametrize("panel,nb", [("gram", 0), ("gram", 16), ("gram", 32), ("tsqr", 0)])
+@pytest.mark.parametrize("panel,nb", [("gram", 0), ("gram", 16), ("gram", 32), ("gram", 100),
+                                      ("gram", 128), ("tsqr", 0)])
 @pytest.mark.parametrize("m,n,ld", [(64, 64, None), (100, 1, None), (257, 33, 260), (300, 33, 303),
                                     (1000, 100, None), (1024, 256, None), (2500, 300, None),
                                     (513, 96, 515)])
@@ -52,6 +53,41 @@ def test_fp32_qr_parity(qrx, m, n, ld, panel, nb):
     # kappa (Sec. 3.2.1); MGS2 inside the panels keeps it at O(u) there
     assert orth < max(1e-5, 20 * kappa * 6e-8)
     assert rerr < 20 * kappa * 6e-8
+
+
+@pytest.mark.parametrize("prec,be_bound", [("fp32", 2e-6), ("fp16", 4e-3), ("fp16x3", 2e-6)])
+def test_leaf128_matches_two_64_panels(qrx, prec, be_bound):
+    # A 128-column Gram panel is one Cholesky QR of the leaf: the same R as two
+    # 64-column panels with the projection and update in between (exact
+    # arithmetic). Both settings must meet the same bounds, with orthogonality
+    # within a small factor of each other (c2 recipe, 2048 x 384, cutoff 128).
+    p = synth.scaled_config("c2", 2048, 384, seed=1)
+    Q1, R1, st1 = _run(qrx, p.A, prec=prec, cutoff=128, panel_width=128)
+    Q2, R2, st2 = _run(qrx, p.A, prec=prec, cutoff=128, panel_width=64)
+    assert st1 == 0 and st2 == 0
+    be1, be2 = M.qr_backward_error(p.A, Q1, R1), M.qr_backward_error(p.A, Q2, R2)
+    o1, o2 = M.orthogonality(Q1), M.orthogonality(Q2)
+    print(f"{prec}: nb 128 be={be1:.2e} orth={o1:.2e}; nb 64 be={be2:.2e} orth={o2:.2e}")
+    assert M.upper_triangular_ok(R1)
+    assert be1 < be_bound
+    assert o1 < 4 * o2 + 1e-6
+
+
+def test_leaf128_ill_conditioned_reorthogonalises(qrx):
+    # kappa = 1e6 (log-uniform spectrum): the first sweep of a 128-column panel
+    # leaves Q1 far from orthonormal (kappa^2 u64 ~ 1e-4), so the second sweep
+    # and the R2 R1 product run; FP32 products keep the factorisation at FP32
+    # accuracy and orthogonality at O(kappa u32) (Sec. 3.2.1)
+    g = np.random.default_rng(5)
+    A = synth.svd_matrix(g, 2048, 256, synth.spectrum("loguniform", 256, 1e6, g))
+    Q, R, st = _run(qrx, A, prec="fp32", panel_width=128)
+    assert st == 0
+    be = M.qr_backward_error(A, Q, R)
+    orth = M.orthogonality(Q)
+    print(f"be={be:.2e} orth={orth:.2e}")
+    assert M.upper_triangular_ok(R)
+    assert be < 2e-6
+    assert orth < 20 * 1e6 * 6e-8
 
 
 def test_fp32_qr_c1_full_size(qrx):
@@ -133,10 +169,11 @@ def test_closed_forms(qrx):
     assert np.max(np.abs(R - np.eye(50))) < 1e-5
 
 
-def test_deterministic(qrx):
+@pytest.mark.parametrize("nb", [0, 128])
+def test_deterministic(qrx, nb):
     p = synth.scaled_config("c2", 2048, 256, seed=3)
-    a = _run(qrx, p.A, prec="fp16", cutoff=64)
-    b = _run(qrx, p.A, prec="fp16", cutoff=64)
+    a = _run(qrx, p.A, prec="fp16", cutoff=max(64, nb), panel_width=nb)
+    b = _run(qrx, p.A, prec="fp16", cutoff=max(64, nb), panel_width=nb)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
