@@ -235,7 +235,7 @@ typedef struct {
 
 /* Pick nb, c, the tile family and the projection split target for QR in the
  * precision (and panel algorithm) of *base: a coordinate search from the
- * defaults over nb in {32, 64} (TSQR panel: {16, 32}), c in {64, 128, 256,
+ * defaults over nb in {32, 64, 128} (TSQR panel: {16, 32}), c in {64, 128, 256,
  * 512}, both tile families and split targets {128, 256, 512, 1024}, each
  * candidate timed with HIP events over `reps` runs (1..20) of
  * qrx_qr_factor_out on A (device, m x n, lda; not modified), median taken.

@@ -171,11 +171,11 @@ struct QrWork {
 // operands are the packed copies, aligned when the node's first column is a
 // multiple of 8 and its width k is too).
 bool tn_proj(const Op &o, int64_t m, const QrCfg &c) {
-    return c.tiles == 0 && o.prec != QRX_FP32 && m >= 256 && o.k >= 256 && o.n2 >= 256 &&
+    return c.tiles == 0 && o.prec != QRX_FP32 && m >= 256 && o.k >= 512 && o.n2 >= 512 &&
            o.c0 % 8 == 0;
 }
 bool tn_upd(const Op &o, int64_t m, const QrCfg &c) {
-    return c.tiles == 0 && o.prec != QRX_FP32 && m >= 256 && o.n2 >= 256 && o.c0 % 8 == 0 &&
+    return c.tiles == 0 && o.prec != QRX_FP32 && m >= 256 && o.n2 >= 512 && o.c0 % 8 == 0 &&
            o.k % 8 == 0;
 }
 int node_splits(const Op &o, int64_t m, const QrCfg &c) {

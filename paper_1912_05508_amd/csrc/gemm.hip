@@ -332,16 +332,38 @@ static bool aligned16(const void *p) { return (((uintptr_t)p) & 15) == 0; }
 // Split-K count of the projection: about 1024 workgroups over the output tiles
 // (FP32: 128 x 128; low precision: 256 x 128 when k >= 256 and n2 >= 128,
 // else 128 x 128), at least 256 rows per split, at most 256 splits.
+// Output tile of a node's projection kernel: the dispatchers below (FP32 here,
+// 16-bit in gemm_lp.hip) use the same rule.
+void projection_tile(int64_t k, int64_t n2, int prec, int &tm, int &tn) {
+    if (prec == QRX_FP32) {
+        tm = tn = (k >= 128 && n2 >= 128) ? 128 : 64;
+        return;
+    }
+    if (prec != QRX_FP16X3 && k >= 512 && n2 >= 128) {
+        tm = 256;
+        tn = 128;
+    } else if (k >= 256 && n2 >= 128) {
+        tm = tn = 128;
+    } else {
+        tm = tn = 64;
+    }
+}
+
+// Split-K count of a projection: about `target` workgroups (default 512), at
+// least 128 rows per split, at most 256 splits and at most 16 MB of FP32
+// partials (each split writes a k x n2 block that proj_reduce reads back).
 int projection_splits(int64_t m, int64_t k, int64_t n2, int prec, int target) {
-    int64_t tm = 128;
-    if (prec != QRX_FP32 && prec != QRX_FP16X3 && k >= 256 && n2 >= 128) tm = 256;
-    const int64_t tiles = ((k + tm - 1) / tm) * ((n2 + 127) / 128);
-    const int64_t tgt = target > 0 ? target : 1024;   // workgroups to aim at
+    int tm, tn;
+    projection_tile(k, n2, prec, tm, tn);
+    const int64_t tiles = ((k + tm - 1) / tm) * ((n2 + tn - 1) / tn);
+    const int64_t tgt = target > 0 ? target : 512;
     int64_t want = (tgt + tiles - 1) / tiles;
-    int64_t maxs = (m + 255) / 256;                     // at least 256 rows per split
+    const int64_t maxs = (m + 127) / 128;
+    const int64_t cap = (int64_t)(16 << 20) / (4 * (k > 0 ? k : 1) * (n2 > 0 ? n2 : 1));
     if (want > maxs) want = maxs;
-    if (want < 1) want = 1;
+    if (want > cap) want = cap;
     if (want > 256) want = 256;
+    if (want < 1) want = 1;
     return (int)want;
 }
 

@@ -354,12 +354,13 @@ static hipError_t projlp_dispatch(hipStream_t s, int64_t m, int64_t k, int64_t n
                                   const uint16_t *qc, const uint16_t *qcl, int64_t ldc,
                                   const float *A2, int64_t lda, const float *colmax, float *part,
                                   int splits, int scaling) {
+    // the tile rule of projection_tile
     if constexpr (!Tr::SPLIT) {
-        if (k >= 256 && n2 >= 128)
+        if (k >= 512 && n2 >= 128)
             return projlp_go<Tr, 256, 128, 2, 2>(s, m, k, n2, qc, qcl, ldc, A2, lda, colmax, part,
                                                  splits, scaling);
     }
-    if (k >= 128 && n2 >= 128)
+    if (k >= 256 && n2 >= 128)
         return projlp_go<Tr, 128, 128, 2, 2>(s, m, k, n2, qc, qcl, ldc, A2, lda, colmax, part,
                                              splits, scaling);
     return projlp_go<Tr, 64, 64, 2, 2>(s, m, k, n2, qc, qcl, ldc, A2, lda, colmax, part, splits,

@@ -310,7 +310,7 @@ int tn_projection_splits(int64_t m, int64_t k, int64_t n2, int target) {
     const int64_t tiles = ((k + tn::BM - 1) / tn::BM) * ((n2 + tn::BN - 1) / tn::BN);
     const int64_t tgt = target > 0 ? target : 256;   // default: one workgroup per CU
     int64_t want = (tgt + tiles - 1) / tiles;
-    const int64_t maxs = (m + 1023) / 1024;        // at least 1024 rows per split
+    const int64_t maxs = (m + 511) / 512;          // at least 512 rows per split
     if (want > maxs) want = maxs;
     if (want < 1) want = 1;
     if (want > 64) want = 64;

@@ -266,7 +266,7 @@ int qrx_tune(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
     // candidate values; cutoffs below n so that the precision asked for is used
     const bool tsqr = b0.panel_alg == 1;
     std::vector<std::vector<int>> lists(4);
-    lists[0] = tsqr ? std::vector<int>{16, 32} : std::vector<int>{32, 64};
+    lists[0] = tsqr ? std::vector<int>{16, 32} : std::vector<int>{32, 64, 128};
     for (int c : {64, 128, 256, 512})
         if (c < n || b0.gemm_prec == QRX_FP32) lists[1].push_back(c);
     lists[2] = {0, 1};
