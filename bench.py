@@ -11,7 +11,9 @@ Legs (--legs, all by default): qr (the timed step above), fp32 (the same QR
 with FP32 MFMA products), lls (time to eta_F <= 1e-10 on the 65536 x 8192
 log-uniform workload, condition 1e6, for split-FP16, FP32 and FP16 trailing
 products), batched (4096 uneven problems in one batched call), cpu (the FP64
-oracle on a bounded sample of the QR workload, on the host cores). The
+oracle on a bounded sample of the QR workload, on the host cores). Opt-in:
+sweep (the paper's eight matrix types at --sweep-sizes: QR backward error and
+orthogonality per precision, LSQR iterations at the first size). The
 dominant kernel's roofline figure comes from HIP events recorded around every
 launch on the launch stream during the timed region; its HBM traffic is the
 rocprofv3 counter measurement while the kernel's sources are unchanged.
@@ -209,6 +211,70 @@ def lls_bench(h, prec, m_n, repeats, precs=("fp16x3", "fp32", "fp16")):
             **out}
 
 
+def sweep_metrics(A, Q, R):
+    """Full ||A - QR||_F / ||A||_F and ||I - Q^T Q||_F / n in FP64 (torch, not the oracle)."""
+    import torch
+    n = A.shape[1]
+    Q64 = Q.double()
+    A64 = A.double()
+    nA = torch.linalg.norm(A64)
+    A64 -= Q64 @ torch.triu(R.double())
+    be = float(torch.linalg.norm(A64) / nA)
+    del A64
+    G = Q64.t() @ Q64
+    G.diagonal().sub_(1.0)
+    return be, float(torch.linalg.norm(G)) / n
+
+
+def sweep_bench(h, sizes, precs, lls_size, lls_precs):
+    """The paper's eight matrix types (Sec. 4.2): QR backward error and
+    orthogonality per precision at each size, and LSQR iterations to
+    eta_F <= 1e-10 at lls_size (b = A x* + 1e-6 relative noise)."""
+    import numpy as np
+    import torch
+    import synth
+    out = []
+    for (m, n) in sizes:
+        for i, (kind, cond) in enumerate(synth.PAPER_TYPES):
+            g = np.random.default_rng(1000 + i)
+            t0 = time.perf_counter()
+            A = synth.paper_family(g, kind, m, n, cond or 1e3, device="cuda")
+            torch.cuda.synchronize()
+            rec = {"type": kind, "cond": cond, "m": m, "n": n,
+                   "gen_s": round(time.perf_counter() - t0, 2)}
+            Q = torch.empty((n, m), dtype=torch.float32, device="cuda").t()
+            R = torch.empty((n, n), dtype=torch.float32, device="cuda").t()
+            st = torch.zeros(1, dtype=torch.int32, device="cuda")
+            for prec in precs:
+                h.qr_out(A, Q, R, st, prec=prec, cutoff=128, **QR_KW)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                h.qr_out(A, Q, R, st, prec=prec, cutoff=128, **QR_KW)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t1) * 1e3
+                be, orth = sweep_metrics(A, Q, R)
+                rec[prec] = {"qr_ms": round(ms, 3), "backward_error_F": be,
+                             "orthogonality_F_over_n": orth, "status": int(st.item())}
+            if (m, n) == tuple(lls_size):
+                x_star, b = synth.lls_problem(g, A, "rel1e-6")
+                b = torch.as_tensor(b, device="cuda")
+                for prec in lls_precs:
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    _, info = h.lstsq(A, b, prec=prec, tol=1e-10, max_iter=20000, cutoff=128,
+                                      node_reorth=True, **QR_KW)
+                    torch.cuda.synchronize()
+                    rec["lls_" + prec] = {"ms": round((time.perf_counter() - t1) * 1e3, 2),
+                                          "iters": info["iters"], "eta_F": info["eta_F"],
+                                          "status": info["status"]}
+            log(f"sweep {m}x{n} {kind} cond={cond}: " + json.dumps(
+                {k: v for k, v in rec.items() if isinstance(v, dict)}))
+            out.append(rec)
+            del A, Q, R
+            torch.cuda.empty_cache()
+    return out
+
+
 def batched_bench(h, count, prec, repeats=2):
     """The uneven batch (n = 8 U{4..32}, m = n U{4..16}, columns scaled by
     10^U[-2,2]) solved to eta_F <= 1e-10 in one batched call."""
@@ -268,6 +334,9 @@ def main():
     ap.add_argument("--legs", default="qr,fp32,lls,batched,cpu",
                     help="comma list of qr (the timed QR step), fp32, lls, batched, cpu")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-problem batched solve")
+    ap.add_argument("--sweep-sizes", default="8192x4096,32768x16384",
+                    help="sizes of the opt-in 'sweep' leg (the paper's eight matrix types)")
+    ap.add_argument("--sweep-precs", default="fp16,fp32")
     ap.add_argument("--batched-count", type=int, default=4096)
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 256 MiB device copy (calibrates HBM byte counters)")
@@ -362,6 +431,15 @@ def main():
                                   precs=tuple(args.lls_precs.split(",")))
     if "batched" in legs:
         result["batched"] = batched_bench(h, args.batched_count, "bf16")
+    if "sweep" in legs:
+        sizes = [tuple(int(v) for v in x.split("x")) for x in args.sweep_sizes.split(",")]
+        result["sweep"] = {
+            "workload": "the paper's eight matrix types (uniform (0,1) and (-1,1), normal; "
+                        "U diag(s) V^T with s geometric cond 1e3, arithmetic cond 1e5 and 1e6, "
+                        "cluster cond 1e5 and 1e6), seeds 1000..1007; LLS at the first size with "
+                        "b = A x* + 1e-6 relative noise",
+            "results": sweep_bench(h, sizes, args.sweep_precs.split(","), sizes[0],
+                                   ("fp16", "fp16x3"))}
     if "cpu" in legs:
         log("timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline(A.cpu().numpy())

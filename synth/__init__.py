@@ -26,7 +26,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "rng", "gaussian", "orthonormal", "spectrum", "svd_matrix",
-    "paper_family", "lls_problem", "config_problem", "batched_problems",
+    "paper_family", "PAPER_TYPES", "lls_problem", "config_problem", "batched_problems",
     "CONFIGS", "scaled_config",
 ]
 
@@ -109,15 +109,30 @@ def svd_matrix(g, m, n, s, col_scale=None, device: str = "cpu"):
     return out
 
 
-def paper_family(g, kind: str, m: int, n: int, cond: float = 1e3):
-    """The paper's eight matrix types (Sec. 4.2, Fig. 3)."""
-    if kind == "uniform01":
-        return np.asfortranarray(g.random((n, m)).T.astype(np.float32))
-    if kind == "uniform11":
-        return np.asfortranarray((2.0 * g.random((n, m)).T - 1.0).astype(np.float32))
-    if kind == "normal":
-        return np.asfortranarray(gaussian(g, m, n).astype(np.float32))
-    return svd_matrix(g, m, n, spectrum(kind, n, cond, g))
+def paper_family(g, kind: str, m: int, n: int, cond: float = 1e3, device: str = "cpu"):
+    """The paper's eight matrix types (Sec. 4.2, Fig. 3). With a device, the
+    matrix is returned there (column-major float32 tensor); the draws are the
+    same as on the CPU."""
+    if kind in ("uniform01", "uniform11", "normal"):
+        if kind == "uniform01":
+            A = np.asfortranarray(g.random((n, m)).T.astype(np.float32))
+        elif kind == "uniform11":
+            A = np.asfortranarray((2.0 * g.random((n, m)).T - 1.0).astype(np.float32))
+        else:
+            A = np.asfortranarray(gaussian(g, m, n).astype(np.float32))
+        if device == "cpu":
+            return A
+        import torch
+        out = torch.empty((n, m), dtype=torch.float32, device=device).t()
+        out.copy_(torch.from_numpy(A))
+        return out
+    return svd_matrix(g, m, n, spectrum(kind, n, cond, g), device=device)
+
+
+# The eight types of the paper's sweep (Sec. 4.2): (kind, condition number)
+PAPER_TYPES = (("uniform01", None), ("uniform11", None), ("normal", None),
+               ("geometric", 1e3), ("arithmetic", 1e5), ("arithmetic", 1e6),
+               ("cluster", 1e5), ("cluster", 1e6))
 
 
 @dataclass

@@ -90,6 +90,27 @@ def test_leaf128_ill_conditioned_reorthogonalises(qrx):
     assert orth < 20 * 1e6 * 6e-8
 
 
+@pytest.mark.parametrize("kind,cond", synth.PAPER_TYPES)
+def test_paper_matrix_types(qrx, kind, cond):
+    # the paper's eight matrix types (Sec. 4.2) at 2048 x 512: FP32 products keep
+    # the factorisation at FP32 accuracy and orthogonality at O(kappa u32); FP16
+    # products keep the backward error at the FP16 level (Sec. 3.2.1)
+    g = np.random.default_rng(1000 + synth.PAPER_TYPES.index((kind, cond)))
+    A = synth.paper_family(g, kind, 2048, 512, cond or 1e3)
+    kappa = np.linalg.cond(A.astype(np.float64))
+    Q, R, st = _run(qrx, A, prec="fp32")
+    assert st == 0
+    be, orth = M.qr_backward_error(A, Q, R), M.orthogonality(Q)
+    Q16, R16, st16 = _run(qrx, A, prec="fp16", cutoff=128)
+    assert st16 == 0
+    be16 = M.qr_backward_error(A, Q16, R16)
+    print(f"{kind} {cond}: kappa={kappa:.2e} fp32 be={be:.2e} orth={orth:.2e}; fp16 be={be16:.2e}")
+    assert M.upper_triangular_ok(R) and M.upper_triangular_ok(R16)
+    assert be < 2e-6
+    assert orth < max(1e-5, 20 * kappa * 6e-8)
+    assert be16 < 4e-3
+
+
 def test_fp32_qr_c1_full_size(qrx):
     p = synth.config_problem("c1")
     Q, R, st = _run(qrx, p.A, panel_width=32)
