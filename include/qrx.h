@@ -82,10 +82,15 @@ typedef struct {
                              0 = default (off for qrx_qr_factor*, on for qrx_lls_solve),
                              1 = on, 2 = off */
     int gemm_tiles;       /* tiles of the low-precision trailing products: 0 = 256 x 256
-                             tiles for nodes with at least 256 rows and columns of output
+                             tiles for nodes with at least 512 rows and columns of output
                              (default), 1 = 128-row tiles only */
     int split_target;     /* workgroups a row-split projection aims at: 0 = default (256 with
-                             256 x 256 tiles, 1024 otherwise), else 16..8192 */
+                             256 x 256 tiles, 512 otherwise), else 16..8192 */
+    int q_reorth;         /* 1 = re-orthogonalise the whole Q: factor Q again with the same
+                             options (Q = Q2 R2) and return Q2 and R2 R (twice the time;
+                             orthogonality no longer grows with the condition of A).
+                             0 = off (default). Ignored by the least-squares calls;
+                             must be 0 for the batched calls */
 } qrx_qr_opts;
 
 /* Least-squares options; an all-zero struct selects the defaults. */

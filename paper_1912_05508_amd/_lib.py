@@ -22,7 +22,8 @@ class qrx_qr_opts(C.Structure):
     _fields_ = [("gemm_prec", C.c_int), ("panel_width", C.c_int), ("cutoff", C.c_int),
                 ("block_rows", C.c_int), ("no_col_scaling", C.c_int),
                 ("panel_single_pass", C.c_int), ("panel_alg", C.c_int),
-                ("node_reorth", C.c_int), ("gemm_tiles", C.c_int), ("split_target", C.c_int)]
+                ("node_reorth", C.c_int), ("gemm_tiles", C.c_int), ("split_target", C.c_int),
+                ("q_reorth", C.c_int)]
 
 
 class qrx_lls_opts(C.Structure):
@@ -135,8 +136,9 @@ PANEL = {"gram": 0, "tsqr": 1, "mgs": 1}
 
 
 def qr_opts(prec="fp32", panel_width=0, cutoff=0, col_scaling=True, reorth=True, panel="gram",
-            node_reorth=None, gemm_tiles=0, split_target=0):
+            node_reorth=None, gemm_tiles=0, split_target=0, q_reorth=False):
     o = qrx_qr_opts()
+    o.q_reorth = 1 if q_reorth else 0
     o.gemm_tiles = gemm_tiles
     o.split_target = split_target
     o.node_reorth = 0 if node_reorth is None else (1 if node_reorth else 2)

@@ -90,7 +90,7 @@ struct Carve {
 int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
 
 struct QrCfg {
-    int prec, nb, c, reorth, scaling, alg, node_reorth, tiles, split_target;
+    int prec, nb, c, reorth, scaling, alg, node_reorth, tiles, split_target, qreorth;
 };
 
 int resolve_qr(const qrx_qr_opts *o, QrCfg &c, bool lls = false) {
@@ -119,6 +119,8 @@ int resolve_qr(const qrx_qr_opts *o, QrCfg &c, bool lls = false) {
     if (o->split_target != 0 && (o->split_target < 16 || o->split_target > 8192)) return QRX_EINVAL;
     c.tiles = o->gemm_tiles;
     c.split_target = o->split_target;
+    if (o->q_reorth < 0 || o->q_reorth > 1) return QRX_EINVAL;
+    c.qreorth = lls ? 0 : o->q_reorth;
     return QRX_OK;
 }
 
@@ -157,6 +159,7 @@ void tsqr_sizes(int64_t m, int nb, std::vector<int64_t> &nblk) {
 struct QrWork {
     int *flags;
     float *colmax, *uscale, *part, *rtop, *stack_base, *rcorr, *cmpart;
+    float *r2, *r3;   // whole-Q re-orthogonalisation: R2 and the product R2 R (n x n)
     double *colss, *normA, *gram;
     size_t stack_floats;
     // 16-bit operand copies for low-precision nodes (null when there are none):
@@ -193,6 +196,8 @@ bool has_lowp_nodes(const QrCfg &c, const std::vector<Op> &ops) {
 void carve_qr(Carve &cv, int64_t m, int64_t n, const QrCfg &c, const std::vector<Op> &ops,
               QrWork &w) {
     w.flags = cv.take<int>(4);
+    w.r2 = cv.take<float>(c.qreorth ? (size_t)n * n : 1);
+    w.r3 = cv.take<float>(c.qreorth ? (size_t)n * n : 1);
     w.colmax = cv.take<float>(n);
     w.uscale = cv.take<float>(n);
     w.colss = cv.take<double>(n);
@@ -786,7 +791,7 @@ int resolve_batched(const qrx_qr_opts *o, QrCfg &c) {
     if (o->panel_width != 0 && o->panel_width != kBPanel) return QRX_EINVAL;
     if (o->cutoff < 0 || o->block_rows < 0) return QRX_EINVAL;
     if (o->no_col_scaling < 0 || o->no_col_scaling > 1) return QRX_EINVAL;
-    if (o->gemm_tiles != 0 || o->split_target != 0) return QRX_EINVAL;
+    if (o->gemm_tiles != 0 || o->split_target != 0 || o->q_reorth != 0) return QRX_EINVAL;
     c.prec = o->gemm_prec;
     c.alg = 0;
     c.nb = kBPanel;
@@ -798,6 +803,7 @@ int resolve_batched(const qrx_qr_opts *o, QrCfg &c) {
     c.reorth = 1;
     c.scaling = 0;
     c.node_reorth = 0;
+    c.qreorth = 0;
     return QRX_OK;
 }
 
@@ -991,6 +997,23 @@ static int qr_common(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t
         Rec r(h, stream);
         QRX_TRY(launch_r_finalize(stream, n, R, ldr, ws.flags));
         r.end("r_finalize", 0, 4.0 * n * n);
+    }
+    if (c.qreorth) {
+        // whole-Q re-orthogonalisation: Q = Q2 R2 by the same factorisation, R <- R2 R
+        {
+            Rec r(h, stream);
+            QRX_TRY(launch_scan(stream, m, n, Q, ldq, nullptr, ldq, ws.colmax, ws.colss,
+                                ws.flags));
+            r.end("scan", 0, 4.0 * m * n);
+        }
+        if ((rc = run_qr(h, stream, m, n, Q, ldq, ws.r2, n, c, ops, ws))) return rc;
+        {
+            Rec r(h, stream);
+            QRX_TRY(launch_r_finalize(stream, n, ws.r2, n, ws.flags));
+            QRX_TRY(launch_triu_mul(stream, n, ws.r2, n, R, ldr, ws.r3, n));
+            QRX_TRY(launch_copy_mat(stream, n, n, ws.r3, n, R, ldr));
+            r.end("q_reorth_r", 2.0 * n * n * n / 6.0, 20.0 * n * n);
+        }
     }
     if (status) QRX_TRY(launch_status_out(stream, ws.flags, status));
     return QRX_OK;

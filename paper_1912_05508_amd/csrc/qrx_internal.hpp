@@ -108,6 +108,11 @@ hipError_t launch_scan_vec(hipStream_t s, int64_t m, const double *b, int *flags
 hipError_t launch_norm_finalize(hipStream_t s, int64_t n, const double *colss, double *normA);
 hipError_t launch_fill_f32(hipStream_t s, float *p, int64_t count, float v);
 hipError_t launch_r_finalize(hipStream_t s, int64_t n, float *R, int64_t ldr, int *flags);
+// C = A B for upper-triangular n x n A, B (FP32; FP64 accumulation), C lower part zero
+hipError_t launch_triu_mul(hipStream_t s, int64_t n, const float *A, int64_t lda, const float *B,
+                           int64_t ldb, float *C, int64_t ldc);
+hipError_t launch_copy_mat(hipStream_t s, int64_t rows, int64_t cols, const float *src,
+                           int64_t lds, float *dst, int64_t ldd);
 hipError_t launch_status_out(hipStream_t s, const int *flags, int *status);
 
 // panel.hip : one TSQR panel of width w <= nb (nb = 32), m rows, column-major ld.

@@ -117,6 +117,67 @@ __global__ __launch_bounds__(256) void r_finalize_kernel(int64_t n, float *R, in
     }
 }
 
+// C = A B for upper-triangular A and B (n x n, FP32, column-major), FP64
+// accumulation, into C (FP32, ldc) with its strictly-lower part zero: the R
+// factor of a re-orthogonalised Q (R = R2 R). 64 x 64 tile per workgroup
+// (4 x 4 outputs per thread, rows and columns 16 apart), K in stages of 32 over
+// the range [i0, j0 + 63] where both triangles can be nonzero.
+__global__ __launch_bounds__(256) void triu_mul_kernel(int64_t n, const float *__restrict__ A,
+                                                       int64_t lda, const float *__restrict__ B,
+                                                       int64_t ldb, float *__restrict__ C,
+                                                       int64_t ldc) {
+    __shared__ double As[32][65], Bs[32][65];   // As[k][i] = A(i0 + i, k0 + k), Bs[k][j]
+    const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
+    const int t = threadIdx.x, ti = t % 16, tj = t / 16;
+    double acc[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
+    if (i0 <= j0) {
+        const int64_t kend = (j0 + 64 < n) ? j0 + 64 : n;
+        for (int64_t k0 = i0; k0 < kend; k0 += 32) {
+            for (int e = t; e < 64 * 32; e += 256) {
+                const int i = e % 64, k = e / 64;
+                const int64_t gi = i0 + i, gk = k0 + k;
+                As[k][i] = (gi < n && gk < n && gi <= gk) ? (double)A[gi + gk * lda] : 0.0;
+                const int kk = e % 32, j = e / 32;
+                const int64_t gk2 = k0 + kk, gj = j0 + j;
+                Bs[kk][j] = (gk2 < n && gj < n && gk2 <= gj) ? (double)B[gk2 + gj * ldb] : 0.0;
+            }
+            __syncthreads();
+            for (int k = 0; k < 32; ++k) {
+                double a[4], b[4];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) a[p] = As[k][ti + 16 * p];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) b[q] = Bs[k][tj + 16 * q];
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = i0 + ti + 16 * p, j = j0 + tj + 16 * q;
+            if (i < n && j < n) C[i + j * ldc] = (i <= j) ? (float)acc[p][q] : 0.0f;
+        }
+}
+
+// dst (rows x cols, ldd) = src (lds), FP32, column-major
+__global__ __launch_bounds__(256) void copy_mat_kernel(int64_t rows, const float *__restrict__ src,
+                                                       int64_t lds, float *__restrict__ dst,
+                                                       int64_t ldd) {
+    const int64_t j = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < rows; i += (int64_t)gridDim.x * 256)
+        dst[i + j * ldd] = src[i + j * lds];
+}
+
 // Map the flag bits to one status value (non-finite input wins).
 __global__ void status_out_kernel(const int *flags, int *status) {
     int f = *flags;
@@ -155,6 +216,26 @@ hipError_t launch_fill_f32(hipStream_t s, float *p, int64_t count, float v) {
 
 hipError_t launch_r_finalize(hipStream_t s, int64_t n, float *R, int64_t ldr, int *flags) {
     hipLaunchKernelGGL(r_finalize_kernel, dim3((unsigned)n), dim3(256), 0, s, n, R, ldr, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_triu_mul(hipStream_t s, int64_t n, const float *A, int64_t lda, const float *B,
+                           int64_t ldb, float *C, int64_t ldc) {
+    if (n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((n + 63) / 64);
+    if (nb > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(triu_mul_kernel, dim3(nb, nb), dim3(256), 0, s, n, A, lda, B, ldb, C, ldc);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_mat(hipStream_t s, int64_t rows, int64_t cols, const float *src,
+                           int64_t lds, float *dst, int64_t ldd) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    if (cols > 65535) return hipErrorInvalidValue;
+    int64_t gx = (rows + 255) / 256;
+    if (gx > 64) gx = 64;
+    hipLaunchKernelGGL(copy_mat_kernel, dim3((unsigned)gx, (unsigned)cols), dim3(256), 0, s, rows,
+                       src, lds, dst, ldd);
     return hipGetLastError();
 }
 

@@ -86,7 +86,8 @@ def test_qr_bad_pointers_and_options(lib, host_handle):
                               ("cutoff", -4, "gram"), ("block_rows", 128, "gram"),
                               ("no_col_scaling", 2, "gram"), ("panel_alg", 2, "gram"),
                               ("gemm_tiles", 2, "gram"), ("split_target", 8, "gram"),
-                              ("split_target", 9000, "gram")):
+                              ("split_target", 9000, "gram"), ("q_reorth", 2, "gram"),
+                              ("q_reorth", -1, "gram")):
         o = L.qr_opts(panel=panel)
         setattr(o, field, val)
         assert lib.qrx_qr_factor(host_handle, 10, 3, FAKE, 10, FAKE, 3, None, 0, C.byref(o),

@@ -111,6 +111,33 @@ def test_paper_matrix_types(qrx, kind, cond):
     assert be16 < 4e-3
 
 
+@pytest.mark.parametrize("prec,kind,cond", [("fp32", "arithmetic", 1e6), ("fp16", "geometric", 1e3),
+                                            ("fp16", "geometric", 1e5), ("fp16x3", "cluster", 1e6)])
+def test_whole_q_reorthogonalisation(qrx, prec, kind, cond):
+    # factoring Q again (Q = Q2 R2, R = R2 R) removes the kappa-proportional loss
+    # of orthogonality of block Gram-Schmidt (Sec. 3.2.1) when kappa u stays below
+    # about one (u of the product precision): Q2 is then orthonormal to the level
+    # of u while A = Q2 (R2 R) stays backward stable. FP16 at kappa = 1e5 (kappa
+    # u16 = 49) is beyond that: the second pass only improves orthogonality.
+    ok_range = cond * {"fp32": 6e-8, "fp16x3": 6e-8, "fp16": 4.9e-4}[prec] < 1
+    g = np.random.default_rng(11)
+    A = synth.paper_family(g, kind, 2048, 384, cond)
+    Q1, R1, st1 = _run(qrx, A, prec=prec, cutoff=128)
+    Q2, R2, st2 = _run(qrx, A, prec=prec, cutoff=128, q_reorth=True)
+    assert st1 == 0 and st2 == 0
+    o1, o2 = M.orthogonality(Q1), M.orthogonality(Q2)
+    be1, be2 = M.qr_backward_error(A, Q1, R1), M.qr_backward_error(A, Q2, R2)
+    print(f"{prec} {kind} {cond:.0e}: orth {o1:.2e} -> {o2:.2e}; be {be1:.2e} -> {be2:.2e}")
+    assert M.upper_triangular_ok(R2)
+    u, be_bound = {"fp32": (6e-8, 2e-6), "fp16x3": (6e-8, 2e-6), "fp16": (4.9e-4, 4e-3)}[prec]
+    assert be2 < be_bound
+    if not ok_range:
+        assert o2 < o1
+        return
+    assert o2 < 200 * u
+    assert o2 < max(o1 / 10, 1e-6) if prec != "fp16" else o2 < o1
+
+
 def test_fp32_qr_c1_full_size(qrx):
     p = synth.config_problem("c1")
     Q, R, st = _run(qrx, p.A, panel_width=32)
