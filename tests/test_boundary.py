@@ -172,7 +172,8 @@ def test_batched_sizes_and_validation(lib, host_handle):
                                                  C.byref(sz)) == EINVAL
     assert lib.qrx_qr_batched_workspace_size(host_handle, 0, m, n, None, C.byref(sz)) == EINVAL
     for field, val in (("gemm_prec", 1), ("gemm_prec", 3), ("panel_alg", 1), ("panel_width", 16),
-                       ("panel_single_pass", 1), ("node_reorth", 1)):
+                       ("panel_single_pass", 1), ("node_reorth", 1), ("q_reorth", 1),
+                       ("gemm_tiles", 1), ("split_target", 256)):
         o = _lib.qr_opts("fp32")
         setattr(o, field, val)
         assert lib.qrx_qr_batched_workspace_size(host_handle, 3, m, n, C.byref(o),
