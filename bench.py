@@ -10,7 +10,9 @@ Householder-equivalent count 2 m n^2 - 2 n^3 / 3.
 Legs (--legs, all by default): qr (the timed step above), fp32 (the same QR
 with FP32 MFMA products), lls (time to eta_F <= 1e-10 on the 65536 x 8192
 log-uniform workload, condition 1e6, for split-FP16, FP32 and FP16 trailing
-products), batched (4096 uneven problems in one batched call), cpu (the FP64
+products), batched (4096 uneven problems in one batched call), c5 (the
+262144 x 1024 column-scaled workload: FP16 with power-of-two column scaling,
+BF16 without it, split FP16 and FP32, each to eta_F <= 1e-10), cpu (the FP64
 oracle on a bounded sample of the QR workload, on the host cores). Opt-in:
 sweep (the paper's eight matrix types at --sweep-sizes: QR backward error and
 orthogonality per precision, LSQR iterations at the first size). The
@@ -275,6 +277,40 @@ def sweep_bench(h, sizes, precs, lls_size, lls_precs):
     return out
 
 
+def c5_bench(h):
+    """The very tall workload: FP16 with power-of-two column scaling against BF16
+    without it, split FP16 and FP32, each to eta_F <= 1e-10 (LSQR on A R^-1)."""
+    import torch
+    import synth
+    t0 = time.perf_counter()
+    p = synth.config_problem("c5", device="cuda")
+    A = p.A
+    b = p.b if torch.is_tensor(p.b) else torch.as_tensor(p.b, device="cuda")
+    torch.cuda.synchronize()
+    log(f"c5: generated 262144 x 1024 in {time.perf_counter() - t0:.1f} s")
+    out = {"workload": "c5: 262144 x 1024, s geometric cond 1e5, columns scaled by 10^U[-4,4], "
+                       "b = A x* + 1e-6 relative noise; LSQR right-preconditioned by R to "
+                       "eta_F <= 1e-10"}
+    for label, prec, kw, reps in (("fp16_scaled", "fp16", {}, 1),
+                                  ("bf16_unscaled", "bf16", {"col_scaling": False}, 1),
+                                  ("fp16x3", "fp16x3", {}, 2), ("fp32", "fp32", {}, 2)):
+        for r in range(reps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info = h.lstsq(A, b, prec=prec, tol=1e-10, max_iter=20000, cutoff=128,
+                              node_reorth=True, **kw, **QR_KW)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+        log(f"c5 {label}: {dt * 1e3:.1f} ms iters={info['iters']} eta={info['eta_F']:.2e} "
+            f"status={info['status']}")
+        out[label] = {"time_to_solution_ms": dt * 1e3, "iters": info["iters"],
+                      "eta_F": info["eta_F"], "status": info["status"],
+                      "qr_ms": info.get("qr_ms"), "krylov_ms": info.get("krylov_ms")}
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_bench(h, count, prec, repeats=2):
     """The uneven batch (n = 8 U{4..32}, m = n U{4..16}, columns scaled by
     10^U[-2,2]) solved to eta_F <= 1e-10 in one batched call."""
@@ -331,8 +367,8 @@ def main():
     ap.add_argument("--lls-precs", default="fp16x3,fp32,fp16")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--legs", default="qr,fp32,lls,batched,cpu",
-                    help="comma list of qr (the timed QR step), fp32, lls, batched, cpu")
+    ap.add_argument("--legs", default="qr,fp32,lls,batched,c5,cpu",
+                    help="comma list of qr (the timed QR step), fp32, lls, batched, c5, cpu; sweep is opt-in")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-problem batched solve")
     ap.add_argument("--sweep-sizes", default="8192x4096,32768x16384",
                     help="sizes of the opt-in 'sweep' leg (the paper's eight matrix types)")
@@ -431,6 +467,8 @@ def main():
                                   precs=tuple(args.lls_precs.split(",")))
     if "batched" in legs:
         result["batched"] = batched_bench(h, args.batched_count, "bf16")
+    if "c5" in legs:
+        result["c5"] = c5_bench(h)
     if "sweep" in legs:
         sizes = [tuple(int(v) for v in x.split("x")) for x in args.sweep_sizes.split(",")]
         result["sweep"] = {

@@ -127,7 +127,7 @@ hipError_t launch_copy_r_block(hipStream_t s, const float *src, int64_t ld_src, 
 // gram.hip : Cholesky QR twice on an FP64 Gram matrix (panel of w <= 128 columns);
 // ws holds gram_workspace_doubles(m, wmax) doubles for panels up to wmax (64 or
 // 128) columns; its flag area (gram_counter) is zeroed once before the first panel.
-// 16-bit operand copies a 64-column Gram panel writes with its Q (as pack_q
+// 16-bit operand copies a Gram panel of more than 32 columns writes with its Q (as pack_q
 // does): column-major qc (ldc) and row-major qr (ldq) of sc * Q, lo parts for
 // a split; prec 0 writes none.
 struct PanelPack {
