@@ -29,8 +29,10 @@ and Least Square Solver on GPU with TensorCore"):
 
 Parity status: every function above is pinned by ``tests/test_oracle_*.py``
 against closed forms, exact rational brute force, independent library
-routines or hand-derived fixtures, except the FP16/BF16 rounding model of
-``rmgs`` whose calibration role is "parity unpinned" beyond its FP64 mode.
+routines or hand-derived fixtures. In ``rmgs`` the operand rounding (FP16,
+BF16, split FP16) and the float32 sums are pinned to their definitions; that
+it rounds at the same points as the GPU path (its calibration role) is
+"parity unpinned" beyond its FP64 mode.
 """
 from . import householder, lls, krylov, metrics, rmgs  # noqa: F401
 

@@ -111,3 +111,72 @@ def test_low_precision_emulation_backward_error(prec, bound):
     A = synth.svd_matrix(g, 512, 64, synth.spectrum("geometric", 64, 1e3))
     Q, R = G.rmgs(A.astype(np.float64), cutoff=16, prec=prec)
     assert M.qr_backward_error(A, Q, R) < bound
+
+
+def test_bf16_rounding_against_definition():
+    # BF16 keeps 8 significant bits of an FP32 value, rounding to nearest with
+    # ties to even (Sec. 2.1 formats): the two candidates of each value are its
+    # truncation and the next value away from zero; the nearer one wins, exact
+    # distances by rational arithmetic, ties to the even last bit
+    from fractions import Fraction
+    g = np.random.default_rng(12)
+    mags = np.float32(10.0) ** g.integers(-30, 30, 3000).astype(np.float32)
+    x = np.concatenate([(g.standard_normal(3000) * mags).astype(np.float32),
+                        np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8, -(1 + 2 ** -8),
+                                  1 + 2 ** -8 + 2 ** -20, 2 ** -100], np.float32)])
+    y = G.to_bf16(x)
+    for xi, yi in zip(x, y):
+        bits = int(np.array([xi], np.float32).view(np.uint32)[0])
+        lo = bits & 0xFFFF0000
+        hi = lo + 0x10000
+        flo = float(np.array([lo], np.uint32).view(np.float32)[0])
+        fhi = float(np.array([hi], np.uint32).view(np.float32)[0])
+        dlo = abs(Fraction(float(xi)) - Fraction(flo))
+        dhi = abs(Fraction(float(xi)) - Fraction(fhi))
+        if dlo != dhi:
+            want = lo if dlo < dhi else hi
+        else:
+            want = lo if ((lo >> 16) & 1) == 0 else hi
+        got = int(np.array([yi], np.float32).view(np.uint32)[0])
+        assert got == want, (float(xi), hex(got), hex(want))
+
+
+def _half(v):
+    # IEEE binary16 round-to-nearest-even by Python's own conversion
+    import struct
+    return struct.unpack("<e", struct.pack("<e", float(v)))[0]
+
+
+def test_fp16_operand_rounding_against_python_half():
+    g = np.random.default_rng(13)
+    x = (g.uniform(-1, 1, 4000) * 10.0 ** g.integers(-4, 5, 4000)).astype(np.float32)
+    x = np.concatenate([x, np.array([1 + 2 ** -11, 1 + 3 * 2 ** -11, 2048 + 1, 65504.0], np.float32)])
+    y = G.round_operand(x, "fp16")
+    for xi, yi in zip(x, y):
+        assert yi == _half(xi), (float(xi), yi, _half(xi))
+
+
+def test_split_fp16_operand():
+    # hi = fl16(x), lo = fl16(x - hi) (the split of the split-FP16 products): the
+    # operand seen is hi + lo, within half an FP16 unit of lo of x (half the
+    # subnormal spacing 2^-24 once x - hi falls below the FP16 normal range), and
+    # exactly x when x is an FP16 value
+    g = np.random.default_rng(14)
+    x = (g.uniform(-1, 1, 4000) * 10.0 ** g.integers(-2, 4, 4000)).astype(np.float32)
+    y = G.round_operand(x, "fp16x3")
+    for xi, yi in zip(x, y):
+        hi = _half(xi)
+        lo = _half(np.float32(xi) - np.float32(hi))
+        assert yi == hi + lo
+        assert abs(float(xi) - yi) <= max(abs(lo) * 2.0 ** -11, 2.0 ** -25)
+    exact = np.array([_half(v) for v in x], np.float32)
+    assert np.array_equal(G.round_operand(exact, "fp16x3"), exact.astype(np.float64))
+
+
+def test_float32_sums_exact_on_small_integers():
+    # the emulator's products sum in float32; integer data whose partial sums stay
+    # below 2^24 must come out exact
+    g = np.random.default_rng(15)
+    X = g.integers(-64, 65, (40, 32)).astype(np.float64)
+    Y = g.integers(-64, 65, (32, 24)).astype(np.float64)
+    assert np.array_equal(G._mm32(X, Y), X @ Y)
