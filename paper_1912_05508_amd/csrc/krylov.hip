@@ -31,7 +31,27 @@ __global__ __launch_bounds__(KT) void gemv_n_kernel(int64_t m, int64_t n,
     double h[4] = {0, 0, 0, 0}, l[4] = {0, 0, 0, 0};
     if (r < m) {
         const bool v4 = vec && (r + 3 < m);
-        for (int64_t j = j0; j < j1; ++j) {
+        int64_t j = j0;
+        if (v4 && !dd) {
+            // GU column loads in flight per wave (one at a time leaves HBM
+            // latency-bound); the sums keep the column order of the loop below
+            constexpr int GU = 8;
+            for (; j + GU <= j1; j += GU) {
+                float4 q[GU];
+#pragma unroll
+                for (int u = 0; u < GU; ++u)
+                    q[u] = *reinterpret_cast<const float4 *>(A + (j + u) * lda + r);
+#pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    const double xj = x[j + u];
+                    h[0] = fma((double)q[u].x, xj, h[0]);
+                    h[1] = fma((double)q[u].y, xj, h[1]);
+                    h[2] = fma((double)q[u].z, xj, h[2]);
+                    h[3] = fma((double)q[u].w, xj, h[3]);
+                }
+            }
+        }
+        for (; j < j1; ++j) {
             const double xj = x[j];
             const float *a = A + j * lda + r;
             float e[4];
@@ -87,24 +107,39 @@ __global__ __launch_bounds__(KT) void gemv_t_kernel(int64_t m, int64_t n,
 #pragma unroll
     for (int q = 0; q < CW; ++q) acc[q] = 0.0;
     if (vec) {
-        for (int i = lane * 4; i < cnt; i += 256) {
-            if (i + 3 < cnt) {
-                float4 e[CW];
+        // rows i .. i + 3 of the lane's CW columns per block; two blocks' loads
+        // in flight, then one, then the ragged end (rows in ascending order)
+        auto block = [&](const float4 *e, int i) {
+            const double u0 = us[i], u1 = us[i + 1], u2 = us[i + 2], u3 = us[i + 3];
 #pragma unroll
-                for (int q = 0; q < CW; ++q) e[q] = *reinterpret_cast<const float4 *>(a[q] + i);
-                const double u0 = us[i], u1 = us[i + 1], u2 = us[i + 2], u3 = us[i + 3];
-#pragma unroll
-                for (int q = 0; q < CW; ++q) {
-                    acc[q] = fma((double)e[q].x, u0, acc[q]);
-                    acc[q] = fma((double)e[q].y, u1, acc[q]);
-                    acc[q] = fma((double)e[q].z, u2, acc[q]);
-                    acc[q] = fma((double)e[q].w, u3, acc[q]);
-                }
-            } else {
-                for (int k = 0; k < 4 && i + k < cnt; ++k)
-#pragma unroll
-                    for (int q = 0; q < CW; ++q) acc[q] = fma((double)a[q][i + k], us[i + k], acc[q]);
+            for (int q = 0; q < CW; ++q) {
+                acc[q] = fma((double)e[q].x, u0, acc[q]);
+                acc[q] = fma((double)e[q].y, u1, acc[q]);
+                acc[q] = fma((double)e[q].z, u2, acc[q]);
+                acc[q] = fma((double)e[q].w, u3, acc[q]);
             }
+        };
+        const int cnt4 = cnt & ~3;
+        int i = lane * 4;
+        for (; i + 256 < cnt4; i += 512) {
+            float4 e0[CW], e1[CW];
+#pragma unroll
+            for (int q = 0; q < CW; ++q) e0[q] = *reinterpret_cast<const float4 *>(a[q] + i);
+#pragma unroll
+            for (int q = 0; q < CW; ++q) e1[q] = *reinterpret_cast<const float4 *>(a[q] + i + 256);
+            block(e0, i);
+            block(e1, i + 256);
+        }
+        for (; i < cnt4; i += 256) {
+            float4 e0[CW];
+#pragma unroll
+            for (int q = 0; q < CW; ++q) e0[q] = *reinterpret_cast<const float4 *>(a[q] + i);
+            block(e0, i);
+        }
+        if (i < cnt) {
+            for (int k = 0; k < 4 && i + k < cnt; ++k)
+#pragma unroll
+                for (int q = 0; q < CW; ++q) acc[q] = fma((double)a[q][i + k], us[i + k], acc[q]);
         }
     } else {
         for (int i = lane; i < cnt; i += 64)
@@ -193,8 +228,18 @@ __global__ __launch_bounds__(KT) void combine_n_kernel(int64_t n, const double *
     const int64_t j = (int64_t)blockIdx.x * KT + threadIdx.x;
     double v2 = 0.0;
     if (j < n) {
+        // CU partials loaded at a time (n is small: few workgroups), added in split order
+        constexpr int CU = 16;
         double s = 0.0;
-        for (int q = 0; q < splits; ++q) s += part[(int64_t)q * n + j];
+        int q = 0;
+        for (; q + CU <= splits; q += CU) {
+            double pv[CU];
+#pragma unroll
+            for (int u = 0; u < CU; ++u) pv[u] = part[(int64_t)(q + u) * n + j];
+#pragma unroll
+            for (int u = 0; u < CU; ++u) s += pv[u];
+        }
+        for (; q < splits; ++q) s += part[(int64_t)q * n + j];
         z[j] = s;
         v2 = s * s;
     }

@@ -140,13 +140,14 @@ __global__ __launch_bounds__(TT) void trmv_n_kernel(int64_t np, const double *__
     double acc = 0.0;
     const double *xr = X + i;
     int64_t j = j0;
-    for (; j + 4 <= j1; j += 4) {
-        const double x0 = xr[j * ldx], x1 = xr[(j + 1) * ldx];
-        const double x2 = xr[(j + 2) * ldx], x3 = xr[(j + 3) * ldx];
-        acc = fma(x0, v[j], acc);
-        acc = fma(x1, v[j + 1], acc);
-        acc = fma(x2, v[j + 2], acc);
-        acc = fma(x3, v[j + 3], acc);
+    // TU loads in flight per thread (the workgroups are few), summed in column order
+    constexpr int TU = 16;
+    for (; j + TU <= j1; j += TU) {
+        double xv[TU];
+#pragma unroll
+        for (int u = 0; u < TU; ++u) xv[u] = xr[(j + u) * ldx];
+#pragma unroll
+        for (int u = 0; u < TU; ++u) acc = fma(xv[u], v[j + u], acc);
     }
     for (; j < j1; ++j) acc = fma(xr[j * ldx], v[j], acc);
     part[c * np + i] = acc;
