@@ -16,9 +16,9 @@ and Least Square Solver on GPU with TensorCore"):
 * ``lls``          -- the least-squares solution x = argmin ||Ax - b||
   (Sec. 2.2, eq. opt:lls), by Alg. 1 (x = R^{-1} Q^T b) plus correction steps
   with extended-precision residuals.
-* ``krylov``       -- LSQR (Paige & Saunders, cited in Sec. 5) and CGLS
-  (Alg. 5, with the three readings listed in its docstring), both optionally
-  right-preconditioned by an upper-triangular R (Sec. 3.2.3).
+* ``krylov``       -- LSQR (Paige & Saunders, cited in Sec. 5) and CG on the
+  normal equations of A R^{-1} (the mathematics behind Alg. 5's CGLS), both
+  optionally right-preconditioned by an upper-triangular R (Sec. 3.2.3).
 * ``metrics``      -- ||A - QR||/||A||, ||I - Q^T Q|| (Sec. 3.2.1) and the
   normal-equation backward error ||A^T r|| / (||A||_F ||r||) (Sec. 3.2.2,
   normalised).
@@ -29,7 +29,8 @@ and Least Square Solver on GPU with TensorCore"):
 
 Parity status: every function above is pinned by ``tests/test_oracle_*.py``
 against closed forms, exact rational brute force, independent library
-routines or hand-derived fixtures. In ``rmgs`` the operand rounding (FP16,
+routines or hand-derived fixtures (the metrics by closed-form values in
+tests/golden/metrics_*.json). In ``rmgs`` the operand rounding (FP16,
 BF16, split FP16) and the float32 sums are pinned to their definitions; that
 it rounds at the same points as the GPU path (its calibration role) is
 "parity unpinned" beyond its FP64 mode.

@@ -6,12 +6,13 @@ min ||B y - b||, B = A R^{-1}, whose conditioning is kappa(A R^{-1}) (close
 to 1 for a good R); the error contracts by (kappa-1)/(kappa+1) per step, and
 an exact R gives convergence in one step.
 
-Both solvers keep the iterate in x-space: each direction d = R^{-1} w is kept
-next to w so that x += step * d; no final back-transformation is needed.
+LSQR keeps its iterate in x-space: each direction d = R^{-1} w is kept next
+to w so that x += step * d; no final back-transformation is needed.
 
-``cgls`` is Alg. 5 with three readings of its listing: the starting s carries
-the preconditioner (s = R^{-T} A^T r), the step length is gamma / delta with
-delta = ||q||^2, and the update of x uses t = R^{-1} p (x-space), not p.
+``cgls`` is conjugate gradients on the normal equations of A R^{-1}, written
+from the mathematics in the preconditioned variable y = R x (see its
+docstring); in exact arithmetic its iterates are those of the paper's CGLS
+(Alg. 5).
 
 ``lsqr`` is Paige & Saunders' LSQR (the numerically preferred equivalent the
 paper cites in Sec. 5), Golub-Kahan bidiagonalisation with Givens rotations.
@@ -120,35 +121,59 @@ def lsqr(A, b, R=None, x0=None, tol=1e-10, maxit=200, estimate_only=False,
 
 
 def cgls(A, b, R=None, x0=None, tol=1e-10, maxit=200, record=False):
-    """Alg. 5 (CGLS right-preconditioned by R) with the readings above."""
+    """Conjugate gradients on the normal equations of B = A R^{-1} (Sec. 3.2.3).
+
+    With y = R x the preconditioned problem min ||B y - b|| has the normal
+    equations B^T B y = B^T b, a symmetric positive definite system; this is
+    the textbook Hestenes-Stiefel CG for it, written in y:
+
+        g_k     = B^T (b - B y_k)            (the normal-equation residual)
+        p_0     = g_0,  p_k = g_k + (|g_k|^2 / |g_{k-1}|^2) p_{k-1}
+        a_k     = |g_k|^2 / (p_k^T B^T B p_k) = |g_k|^2 / |B p_k|^2
+        y_{k+1} = y_k + a_k p_k
+
+    g_k is recomputed from the iterate every step (never updated by a
+    recurrence), and x = R^{-1} y is formed by back substitution whenever the
+    stopping test needs it. In exact arithmetic these are the iterates of the
+    paper's CGLS (Alg. 5), which updates r = b - A x by a recurrence instead.
+    """
     op = _Op(A, R)
     A64 = op.A
     m, n = A64.shape
     b = np.asarray(b, dtype=np.float64)
     normA_F = float(np.sqrt(np.sum(A64 * A64)))
     nb = float(np.linalg.norm(b))
-    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
-    r = b - A64 @ x
-    s = op.rinv_t(A64.T @ r)
-    p = s.copy()
-    gamma = float(s @ s)
+    if x0 is None:
+        y = np.zeros(n)
+    else:
+        x0 = np.asarray(x0, dtype=np.float64)
+        y = x0.copy() if op.R is None else op.R @ x0
+
+    def B(v):                   # B v = A (R^{-1} v)
+        return A64 @ op.rinv(v)
+
+    def Bt(w):                  # B^T w = R^{-T} (A^T w)
+        return op.rinv_t(A64.T @ w)
+
+    g = Bt(b - B(y))
+    gg = float(g @ g)
+    p = g.copy()
     hist = []
     it = 0
     eta = np.inf
-    while it < maxit and gamma > 0.0:
+    x = op.rinv(y)
+    while it < maxit and gg > 0.0:
         it += 1
-        t = op.rinv(p)
-        q = A64 @ t
-        delta = float(q @ q)
-        if delta == 0.0:
+        Bp = B(p)
+        pBBp = float(Bp @ Bp)
+        if pBBp == 0.0:
             break
-        alpha = gamma / delta
-        x = x + alpha * t
-        r = r - alpha * q
-        s = op.rinv_t(A64.T @ r)
-        gamma1 = gamma
-        gamma = float(s @ s)
-        p = s + (gamma / gamma1) * p
+        y = y + (gg / pBBp) * p
+        x = op.rinv(y)
+        g = Bt(b - A64 @ x)
+        gg_new = float(g @ g)
+        p = g + (gg_new / gg) * p
+        gg = gg_new
         done, eta = _converged(A64, b, x, normA_F, nb, tol)
         if record:
             hist.append(eta)
