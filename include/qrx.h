@@ -30,7 +30,12 @@
  *     Numerical outcomes (positive codes) are reported through the status /
  *     info outputs described per call.
  *   - A handle is bound to one device and is not thread-safe: use one handle
- *     per host thread.
+ *     per host thread. Calls on one handle that use its own workspace (work ==
+ *     NULL) share that workspace: issue them in stream order (one stream, or
+ *     streams ordered by events). When a call needs a larger workspace the
+ *     handle allocates a new one and keeps the old one alive until
+ *     qrx_destroy, so work already queued (or recorded in a graph) that points
+ *     at the old one stays valid.
  */
 #ifndef QRX_H
 #define QRX_H
@@ -52,6 +57,9 @@ extern "C" {
                                full column rank in working precision (Sec. 2.2) */
 #define QRX_ENONFINITE  2   /* A (or b) holds a NaN or Inf */
 #define QRX_ENOCONV     3   /* the Krylov iteration reached max_iter above tol */
+#define QRX_ESYNC       4   /* the persistent Krylov launch could not synchronise its
+                               workgroups (another persistent launch held the device);
+                               x is not written */
 
 typedef struct qrx_handle_s *qrx_handle;
 
@@ -106,18 +114,23 @@ typedef struct {
                              caller-supplied R (qrx_lls_solve_with_R) the start is x = 0. */
 } qrx_lls_opts;
 
-/* Result of a least-squares solve (host memory). */
+/* Result of a least-squares solve, written by the device at the end of the
+ * solve (valid once the stream has reached the end of the call). */
 typedef struct {
-    int status;           /* QRX_OK, QRX_ESINGULAR, QRX_ENONFINITE or QRX_ENOCONV */
+    int status;           /* QRX_OK, QRX_ESINGULAR, QRX_ENONFINITE, QRX_ENOCONV or QRX_ESYNC */
     int iters;            /* Krylov iterations over all restarts */
     int restarts;         /* residual certifications that failed and restarted */
+    int accepted;         /* the test that accepted x: 1 = eta_F <= tol; 2 = the
+                             compatible-system ratio ||r|| / (||A||_F ||x|| + ||b||) <= tol
+                             (for square systems, where eta_F is undefined, or a consistent
+                             m > n system whose residual is at the rounding level); 0 = none */
     double eta_F;         /* ||A^T r|| / (||A||_F ||r||), r = b - A x, for the returned x */
     double resid_norm;    /* ||r||_2 */
     double normA_F;       /* ||A||_F */
-    double qr_ms;         /* device time of the factorisation */
-    double krylov_ms;     /* device time of the iteration and checks */
     double eta_start;     /* eta_F of the starting iterate (for the default start: the
                              accuracy of the direct low-precision QR solve) */
+    double score;         /* the certified score of x: min(eta_F, compatible ratio scaled
+                             onto the tol scale); status is QRX_OK iff score <= tol */
 } qrx_lls_info;
 
 /* Per-kernel timing record (see qrx_timing_*). */
@@ -168,17 +181,23 @@ int qrx_lls_workspace_size(qrx_handle h, int64_t m, int64_t n,
 
 /* x = argmin ||A x - b||_2 (Sec. 2.2, eq. opt:lls) by the QR of A followed
  * by a Krylov iteration on A R^{-1} (Sec. 3.2.3, Alg. 5), stopped when the
- * certified eta_F <= tol. A (FP32) and b (FP64, length m) are not modified;
- * x (FP64, length n) receives the solution (and holds x0 on entry if
- * use_x0). `info` is a HOST pointer (required). The call blocks until the
- * solve is complete on `stream`. */
+ * certified score (info->score) <= tol. A (FP32) and b (FP64, length m) are
+ * not modified; x (FP64, length n) receives the solution (and holds x0 on
+ * entry if use_x0). `info` is a DEVICE pointer to one qrx_lls_info (required).
+ * Asynchronous on `stream`: the whole solve, including the iteration, its
+ * stopping test and the certifications, is enqueued without any host
+ * synchronisation (the iteration runs as one persistent kernel), so the call
+ * can be recorded into a HIP graph. x and *info are valid when the stream
+ * reaches the end of the call. Calls on one device must not overlap in time
+ * (the persistent kernel expects the device's compute units to itself). */
 int qrx_lls_solve(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
                   const double *b, double *x, void *work, size_t work_bytes,
                   const qrx_lls_opts *opts, qrx_lls_info *info, hipStream_t stream);
 
 /* The Krylov step alone with a caller-supplied preconditioner R (device,
  * FP32, n x n upper triangular, ldr >= n), or the identity when R == NULL.
- * Same kernels and semantics as qrx_lls_solve after its factorisation. */
+ * Same kernels and semantics (asynchronous, device `info`) as qrx_lls_solve
+ * after its factorisation. */
 int qrx_lls_solve_with_R(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
                          const float *R, int64_t ldr, const double *b, double *x,
                          void *work, size_t work_bytes, const qrx_lls_opts *opts,

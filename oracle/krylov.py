@@ -49,15 +49,16 @@ def _true_eta(A, b, x, normA_F):
     return float(np.sqrt(np.sum(atr * atr))) / (normA_F * nr) if nr > 0 else 0.0, nr
 
 
-def _converged(A, b, x, normA_F, nb, tol):
+def _converged(A, b, x, normA_F, nb, tol, compatible_test=True):
     eta, nr = _true_eta(A, b, x, normA_F)
-    compatible = nr <= tol * (normA_F * float(np.linalg.norm(x)) + nb)
+    compatible = compatible_test and nr <= tol * (normA_F * float(np.linalg.norm(x)) + nb)
     return (eta <= tol) or compatible, eta
 
 
 def lsqr(A, b, R=None, x0=None, tol=1e-10, maxit=200, estimate_only=False,
-         record=False):
-    """LSQR on A R^{-1}; returns (x, iterations, info dict)."""
+         record=False, compatible_test=True):
+    """LSQR on A R^{-1}; returns (x, iterations, info dict). compatible_test=False
+    stops on eta_F <= tol alone (not on the consistent-system residual test)."""
     op = _Op(A, R)
     A64 = op.A
     m, n = A64.shape
@@ -110,7 +111,7 @@ def lsqr(A, b, R=None, x0=None, tol=1e-10, maxit=200, estimate_only=False,
             if eta <= tol or phibar <= tol * nb:
                 break
         else:
-            done, eta = _converged(A64, b, x, normA_F, nb, tol)
+            done, eta = _converged(A64, b, x, normA_F, nb, tol, compatible_test)
             if record:
                 hist.append(eta)
             if done:

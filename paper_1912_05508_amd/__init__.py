@@ -20,7 +20,8 @@ from ._lib import (QRX_BF16, QRX_EHIP, QRX_EINVAL, QRX_ENOCONV, QRX_ENOMEM,  # n
                    lls_opts, qr_opts, qrx_kernel_stat, qrx_lls_info, qrx_lls_opts,
                    qrx_qr_opts, status_string)
 
-__all__ = ["Handle", "qr", "lstsq", "colmajor", "qr_opts", "lls_opts", "QrxError"]
+__all__ = ["Handle", "qr", "lstsq", "colmajor", "qr_opts", "lls_opts", "QrxError", "info_tensor",
+           "read_info", "QrxArgumentError"]
 
 
 def colmajor(t, ld=None):
@@ -43,6 +44,47 @@ def _ld(t):
 def _stream():
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class QrxArgumentError(ValueError):
+    """A tensor handed to the library has the wrong dtype, device, size or layout
+    (raised before any library call)."""
+
+
+def _check_mat(name, t, m, n, dtype):
+    """A column-major (m, n) device tensor of `dtype` (strides (1, ld), ld >= m)."""
+    import torch
+    if not (torch.is_tensor(t) and t.is_cuda and t.dtype == dtype):
+        raise QrxArgumentError(f"{name}: expected a {dtype} cuda tensor")
+    if tuple(t.shape) != (m, n):
+        raise QrxArgumentError(f"{name}: expected shape {(m, n)}, got {tuple(t.shape)}")
+    if n > 1 and not (t.stride(0) == 1 and t.stride(1) >= m):
+        raise QrxArgumentError(f"{name}: expected a column-major layout, strides {t.stride()}")
+    if n == 1 and t.stride(0) != 1:
+        raise QrxArgumentError(f"{name}: expected unit row stride")
+
+
+def _check_vec(name, t, length, dtype):
+    """A contiguous device vector of `length` entries of `dtype`."""
+    import torch
+    if not (torch.is_tensor(t) and t.is_cuda and t.dtype == dtype):
+        raise QrxArgumentError(f"{name}: expected a {dtype} cuda tensor")
+    if t.numel() != length or not t.is_contiguous():
+        raise QrxArgumentError(f"{name}: expected {length} contiguous entries, got {t.numel()}")
+
+
+def info_tensor(count=1, device=None):
+    """Device memory for `count` qrx_lls_info records (written by the library)."""
+    import torch
+    return torch.zeros(count * C.sizeof(qrx_lls_info), dtype=torch.uint8, device=device)
+
+
+def read_info(t, count=1):
+    """The qrx_lls_info records of a device buffer as dicts (synchronises with it)."""
+    raw = bytes(t.cpu().numpy())
+    sz = C.sizeof(qrx_lls_info)
+    return [qrx_lls_info.from_buffer_copy(raw[i * sz:(i + 1) * sz]).as_dict()
+            for i in range(count)]
 
 
 class Handle:
@@ -73,12 +115,15 @@ class Handle:
         """Factor column-major A in place (A -> Q); returns (Q, R, status tensor)."""
         import torch
         m, n = A.shape
-        assert A.dtype == torch.float32 and A.is_cuda
+        if not (A.dtype == torch.float32 and A.is_cuda):
+            raise QrxArgumentError("A: expected a float32 cuda tensor")
         A = colmajor(A)
         if R is None:
             R = torch.empty((n, n), dtype=torch.float32, device=A.device).t()
+        _check_mat("R", R, n, n, torch.float32)
         if status is None:
             status = torch.zeros(1, dtype=torch.int32, device=A.device)
+        _check_vec("status", status, 1, torch.int32)
         o = qr_opts(prec, **kw)
         rc = self.lib.qrx_qr_factor(self.h, m, n, C.c_void_p(A.data_ptr()), _ld(A),
                                     C.c_void_p(R.data_ptr()), _ld(R), None, 0, C.byref(o),
@@ -88,7 +133,12 @@ class Handle:
 
     def qr_out(self, A, Q, R, status, prec="fp32", **kw):
         """Out-of-place QR: A (column-major, untouched) -> Q, R (preallocated)."""
+        import torch
         m, n = A.shape
+        _check_mat("A", A, m, n, torch.float32)
+        _check_mat("Q", Q, m, n, torch.float32)
+        _check_mat("R", R, n, n, torch.float32)
+        _check_vec("status", status, 1, torch.int32)
         o = qr_opts(prec, **kw)
         rc = self.lib.qrx_qr_factor_out(self.h, m, n, C.c_void_p(A.data_ptr()), _ld(A),
                                         C.c_void_p(Q.data_ptr()), _ld(Q),
@@ -98,32 +148,52 @@ class Handle:
         return Q, R, status
 
     # -- least squares --------------------------------------------------------
-    def lstsq(self, A, b, prec="fp32", x=None, R=None, with_R=False, **kw):
-        """x = argmin ||A x - b|| (A untouched); returns (x, info dict)."""
+    def lstsq_async(self, A, b, x, info, prec="fp32", R=None, with_R=False, use_x0=False,
+                    **kw):
+        """Enqueue x = argmin ||A x - b|| on the current stream without waiting:
+        A (column-major float32, untouched), b (float64, m), x (float64, n; the
+        start when use_x0), info (from info_tensor()) are device tensors the
+        caller keeps alive until the stream reaches the end of the call."""
         import torch
         m, n = A.shape
-        assert A.dtype == torch.float32 and A.is_cuda
-        A = colmajor(A)
-        b = b.contiguous()
-        assert b.dtype == torch.float64 and b.numel() == m
-        use_x0 = x is not None
-        if x is None:
-            x = torch.zeros(n, dtype=torch.float64, device=A.device)
+        _check_mat("A", A, m, n, torch.float32)
+        _check_vec("b", b, m, torch.float64)
+        _check_vec("x", x, n, torch.float64)
+        if not (torch.is_tensor(info) and info.is_cuda and info.dtype == torch.uint8
+                and info.numel() >= C.sizeof(qrx_lls_info) and info.is_contiguous()):
+            raise QrxArgumentError("info: expected a device buffer from info_tensor()")
         o = lls_opts(prec, use_x0=use_x0, **kw)
-        info = qrx_lls_info()
+        ip = C.c_void_p(info.data_ptr())
         if with_R:
+            if R is not None:
+                _check_mat("R", R, n, n, torch.float32)
             rp = C.c_void_p(R.data_ptr()) if R is not None else None
             ldr = _ld(R) if R is not None else n
             rc = self.lib.qrx_lls_solve_with_R(self.h, m, n, C.c_void_p(A.data_ptr()), _ld(A),
                                                rp, ldr, C.c_void_p(b.data_ptr()),
                                                C.c_void_p(x.data_ptr()), None, 0, C.byref(o),
-                                               C.byref(info), _stream())
+                                               ip, _stream())
         else:
             rc = self.lib.qrx_lls_solve(self.h, m, n, C.c_void_p(A.data_ptr()), _ld(A),
                                         C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
-                                        None, 0, C.byref(o), C.byref(info), _stream())
+                                        None, 0, C.byref(o), ip, _stream())
         _lib.check(rc, "qrx_lls_solve")
-        return x, info.as_dict()
+
+    def lstsq(self, A, b, prec="fp32", x=None, R=None, with_R=False, **kw):
+        """x = argmin ||A x - b|| (A untouched); waits for the result and returns
+        (x, info dict)."""
+        import torch
+        m, n = A.shape
+        if not (A.dtype == torch.float32 and A.is_cuda):
+            raise QrxArgumentError("A: expected a float32 cuda tensor")
+        A = colmajor(A)
+        b = b.contiguous()
+        use_x0 = x is not None
+        if x is None:
+            x = torch.zeros(n, dtype=torch.float64, device=A.device)
+        info = info_tensor(device=A.device)
+        self.lstsq_async(A, b, x, info, prec=prec, R=R, with_R=with_R, use_x0=use_x0, **kw)
+        return x, read_info(info)[0]
 
     # -- batched ---------------------------------------------------------------
     @staticmethod
@@ -159,6 +229,8 @@ class Handle:
         mats = [colmajor(a) for a in mats]
         rhs = [b.contiguous() for b in rhs]
         k = len(mats)
+        for i, (a, b) in enumerate(zip(mats, rhs)):
+            _check_vec(f"rhs[{i}]", b, int(a.shape[0]), torch.float64)
         m, n, lda = self._arrays(mats)
         ns = [int(a.shape[1]) for a in mats]
         flat = torch.zeros(sum(ns), dtype=torch.float64, device=mats[0].device)

@@ -33,8 +33,8 @@ class qrx_lls_opts(C.Structure):
 
 class qrx_lls_info(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("restarts", C.c_int),
-                ("eta_F", C.c_double), ("resid_norm", C.c_double), ("normA_F", C.c_double),
-                ("qr_ms", C.c_double), ("krylov_ms", C.c_double), ("eta_start", C.c_double)]
+                ("accepted", C.c_int), ("eta_F", C.c_double), ("resid_norm", C.c_double),
+                ("normA_F", C.c_double), ("eta_start", C.c_double), ("score", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -68,10 +68,11 @@ _SIGS = {
     "qrx_qr_factor_out": (C.c_int, [_P, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, C.c_size_t,
                                     C.POINTER(qrx_qr_opts), _P, _P]),
     "qrx_lls_workspace_size": (C.c_int, [_P, _I64, _I64, C.POINTER(qrx_lls_opts), C.POINTER(C.c_size_t)]),
+    # info is a device pointer (qrx_lls_info written by the device)
     "qrx_lls_solve": (C.c_int, [_P, _I64, _I64, _P, _I64, _P, _P, _P, C.c_size_t,
-                                C.POINTER(qrx_lls_opts), C.POINTER(qrx_lls_info), _P]),
+                                C.POINTER(qrx_lls_opts), _P, _P]),
     "qrx_lls_solve_with_R": (C.c_int, [_P, _I64, _I64, _P, _I64, _P, _I64, _P, _P, _P, C.c_size_t,
-                                       C.POINTER(qrx_lls_opts), C.POINTER(qrx_lls_info), _P]),
+                                       C.POINTER(qrx_lls_opts), _P, _P]),
     "qrx_qr_batched_workspace_size": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(qrx_qr_opts),
                                                  C.POINTER(C.c_size_t)]),
     "qrx_qr_factor_batched": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, _P, _P, C.c_size_t,

@@ -23,12 +23,22 @@ struct PendingTiming {
     double flops, bytes;
 };
 
+// Per-phase wall-clock record of one persistent Krylov launch (pinned host
+// memory the kernel writes at its end), read by qrx_timing_get.
+struct PendingPhases {
+    long long *buf;
+    double khz;                   // wall-clock ticks per millisecond
+    int64_t m, n, np;
+    int splits_n, splits_t;
+};
+
 struct qrx_handle_s {
     int device = -1;
+    std::vector<PendingPhases> phase_pending;
+    std::vector<long long *> phase_spare;
     void *pool = nullptr;
     size_t pool_bytes = 0;
-    double *host_state = nullptr;   // pinned mirror of the Krylov scalar state
-    int *host_flags = nullptr;
+    std::vector<void *> retired;    // outgrown pools, freed by qrx_destroy
     bool timing = false;
     std::vector<PendingTiming> pending;
     std::vector<hipEvent_t> spare;
@@ -449,13 +459,16 @@ int check_qr_args(qrx_handle h, int64_t m, int64_t n, int64_t lda, int64_t ldr) 
     return QRX_OK;
 }
 
+// The handle's workspace. A larger request allocates a new pool; the old one is
+// kept (not freed) until qrx_destroy, because work already enqueued on some
+// stream, or recorded into a HIP graph, may still point at it.
 int ensure_pool(qrx_handle h, size_t bytes, void **out) {
     if (h->device < 0) return QRX_EHIP;
     if (h->pool_bytes < bytes) {
-        if (h->pool) hipFree(h->pool);
-        h->pool = nullptr;
-        h->pool_bytes = 0;
-        if (hipMalloc(&h->pool, bytes) != hipSuccess) return QRX_ENOMEM;
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return QRX_ENOMEM;
+        if (h->pool) h->retired.push_back(h->pool);
+        h->pool = p;
         h->pool_bytes = bytes;
     }
     *out = h->pool;
@@ -464,36 +477,40 @@ int ensure_pool(qrx_handle h, size_t bytes, void **out) {
 
 // ---- Krylov workspace --------------------------------------------------------
 struct KrWork {
-    double *X, *T, *tpart, *u, *r, *rc, *v, *t, *d, *z, *y, *vt, *vt2, *x, *xbest, *q;
-    double *part_n, *part_n2, *part_t, *ssq, *st;
+    double *X, *Xt, *T, *tpart, *u, *r, *rc, *v, *vn, *t, *t2, *d, *z, *vt, *x, *xbest, *q;
+    double *part_n, *part_n2, *part_t, *ssqA, *ssqB;
+    unsigned *bar;
     int splits_n, splits_t;
 };
 
-void carve_kr(Carve &cv, int64_t m, int64_t n, KrWork &k) {
+void carve_kr(Carve &cv, int64_t m, int64_t n, bool precond, KrWork &k) {
     const int64_t np = round_up(n, kTrsvBlock);
     k.splits_n = kr_gemv_n_splits(m, n);
     k.splits_t = kr_gemv_t_splits(m);
-    k.X = cv.take<double>((size_t)np * (size_t)np);
-    k.T = cv.take<double>(kr_trinv_tmp_doubles(np));
+    const size_t nn = precond ? (size_t)np * (size_t)np : 1;
+    k.X = cv.take<double>(nn);
+    k.Xt = cv.take<double>(nn);
+    k.T = cv.take<double>(precond ? kr_trinv_tmp_doubles(np) : 1);
     k.tpart = cv.take<double>(kr_trmv_part_doubles(np));
     k.u = cv.take<double>(m);
     k.r = cv.take<double>(m);
     k.rc = cv.take<double>(m);
     k.q = cv.take<double>(m);
     k.v = cv.take<double>(np);
+    k.vn = cv.take<double>(np);
     k.t = cv.take<double>(np);
+    k.t2 = cv.take<double>(np);
     k.d = cv.take<double>(np);
     k.z = cv.take<double>(np);
-    k.y = cv.take<double>(np);
     k.vt = cv.take<double>(np);
-    k.vt2 = cv.take<double>(np);
     k.x = cv.take<double>(np);
     k.xbest = cv.take<double>(np);
     k.part_n = cv.take<double>((size_t)k.splits_n * m);
     k.part_n2 = cv.take<double>((size_t)k.splits_n * m);
     k.part_t = cv.take<double>((size_t)k.splits_t * np);
-    k.ssq = cv.take<double>((size_t)((std::max(m, np) + 255) / 256 + 1));
-    k.st = cv.take<double>(S_COUNT);
+    k.ssqA = cv.take<double>(kr_loop_ssq_doubles(m, np));
+    k.ssqB = cv.take<double>(kr_loop_ssq_doubles(m, np));
+    k.bar = cv.take<unsigned>(64);
 }
 
 struct KrCfg {
@@ -518,251 +535,99 @@ int resolve_lls(const qrx_lls_opts *o, KrCfg &k) {
     return QRX_OK;
 }
 
-int sync_state(qrx_handle h, hipStream_t s, const double *st) {
-    if (hipMemcpyAsync(h->host_state, st, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s) !=
-        hipSuccess)
-        return QRX_EHIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return QRX_EHIP;
-    return QRX_OK;
-}
-
-unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
-
-// Certification: r = b - A x (double-double), z = A^T r, eta_F (into st).
-int certify(qrx_handle h, hipStream_t s, int64_t m, int64_t n, int64_t np, const float *A,
-            int64_t lda, const double *b, KrWork &k, double tol) {
-    Rec r(h, s);
-    QRX_TRY(kr_gemv_n(s, m, n, A, lda, k.x, k.part_n, k.part_n2, k.splits_n, 1));
-    QRX_TRY(kr_resid_combine(s, m, b, k.part_n, k.part_n2, k.splits_n, k.rc, k.ssq));
-    QRX_TRY(kr_norm(s, k.ssq, nblocks(m), k.st, S_RNORM, 1));
-    QRX_TRY(kr_gemv_t(s, m, n, A, lda, k.rc, k.part_t));
-    QRX_TRY(kr_combine_n(s, n, k.part_t, k.splits_t, k.z, k.ssq));
-    QRX_TRY(kr_norm(s, k.ssq, nblocks(n), k.st, S_ZNORM, 1));
-    QRX_TRY(kr_axpby(s, np, k.st, -2, -1, k.x, -1, 1.0, nullptr, k.vt2, k.ssq));
-    QRX_TRY(kr_norm(s, k.ssq, nblocks(np), k.st, S_XNORM, 1));
-    QRX_TRY(kr_eta(s, k.st, tol, compat_scale(m, n, tol)));
-    r.end("certify", 2.0 * 2.0 * m * n, 8.0 * m * n + 24.0 * m);
-    return QRX_OK;
-}
-
-// Right-preconditioned LSQR / CGLS (Sec. 3.2.3) on the device, wrapped in
-// iterative refinement: every outer step certifies the current x with the
-// true residual (double-double) and restarts the inner iteration on the
-// correction problem min ||A R^{-1} dy - r||; the inner iteration runs until
-// its own estimate of ||R^{-T} A^T r|| / ||r||, scaled by rho / ||A||_F
-// (rho ~ ||R||_2), drops below tol * gam. The best certified iterate is
-// returned. Blocks until done.
-int run_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A, int64_t lda,
-               const float *R, int64_t ldr, const double *b, double *x_user, bool use_x0,
-               const float *Q, int64_t ldq, const KrCfg &cfg, KrWork &k, qrx_lls_info *info,
-               double normA_host, double rho) {
+// Enqueues the Krylov step (Sec. 3.2.3): X = R^{-1} and its transpose, the
+// start (x0 from the caller, the direct solution R^{-1} Q^T b of Alg. 1 with
+// the computed factors, or zero), then the persistent iteration kernel, which
+// writes x_user and *info. No host synchronisation.
+int enqueue_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const float *A,
+                   int64_t lda, const float *R, int64_t ldr, const double *b, double *x_user,
+                   bool use_x0, const float *Q, int64_t ldq, const KrCfg &cfg, KrWork &k,
+                   const QrWork &ws, qrx_lls_info *info) {
     const int64_t np = round_up(n, kTrsvBlock);
-    const double tol = cfg.tol;
-    double *st = k.st;
-    double *hs = h->host_state;
-    {
+    if (R) {
         Rec r(h, s);
-        if (R) QRX_TRY(kr_trinv(s, n, np, R, ldr, k.X, k.T));
-        // recursive block inversion: ~np^3/3 FMA in FP64
-        r.end("trinv", R ? 2.0 * (double)np * np * np / 3.0 : 0.0, R ? 8.0 * np * np : 0.0);
+        QRX_TRY(kr_trinv(s, n, np, R, ldr, k.X, k.T));
+        QRX_TRY(kr_transpose(s, np, k.X, k.Xt));
+        // recursive block inversion: ~np^3/3 FMA in FP64; the transpose moves 16 np^2 bytes
+        r.end("trinv", 2.0 * (double)np * np * np / 3.0, 8.0 * np * np + 16.0 * np * np);
     }
     // the padded tails [n, np) of every n-vector must stay exactly zero
-    for (double *vec : {k.x, k.xbest, k.v, k.t, k.d, k.z, k.y, k.vt}) QRX_TRY(kr_zero(s, np, vec));
+    for (double *vec : {k.x, k.xbest, k.v, k.vn, k.t, k.t2, k.d, k.z, k.vt})
+        QRX_TRY(kr_zero(s, np, vec));
     if (use_x0) {
         QRX_TRY(hipMemcpyAsync(k.x, x_user, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else if (cfg.direct && Q && R) {
         // the direct solution of Alg. 1 with the computed factors: x0 = R^{-1} (Q^T b)
         Rec r(h, s);
         QRX_TRY(kr_gemv_t(s, m, n, Q, ldq, b, k.part_t));
-        QRX_TRY(kr_combine_n(s, n, k.part_t, k.splits_t, k.z, k.ssq));
+        QRX_TRY(kr_combine_n(s, n, k.part_t, k.splits_t, k.z, k.ssqA));
         QRX_TRY(kr_trmv(s, np, k.X, k.z, k.x, k.tpart, 0));
-        r.end("direct_start", 2.0 * m * n + (double)np * (np + 1), 4.0 * m * n + 8.0 * m + 4.0 * np * (np + 1));
+        r.end("direct_start", 2.0 * m * n + (double)np * (np + 1),
+              4.0 * m * n + 8.0 * m + 4.0 * np * (np + 1));
     }
-    for (int i = 0; i < S_COUNT; ++i) QRX_TRY(kr_set(s, st, i, 0.0));
-    QRX_TRY(kr_set(s, st, S_NORMA, normA_host));
-    QRX_TRY(kr_set(s, st, S_GAMMA_TOL, 1.0));
-    {   // ||b|| for the compatible-system test
-        Rec r(h, s);
-        QRX_TRY(kr_axpby(s, m, st, -2, -1, b, -1, 1.0, nullptr, k.q, k.ssq));
-        QRX_TRY(kr_norm(s, k.ssq, nblocks(m), st, S_BNORM, 1));
-        r.end("bnorm", 0, 16.0 * m);
+    // barrier words cleared by a kernel (the call stays safe to record in a HIP graph)
+    QRX_TRY(launch_fill_f32(s, reinterpret_cast<float *>(k.bar), 64, 0.0f));
+    KLoopArgs a;
+    memset(&a, 0, sizeof(a));
+    a.m = m;
+    a.n = n;
+    a.np = np;
+    a.lda = lda;
+    a.A = A;
+    a.b = b;
+    a.X = R ? k.X : nullptr;
+    a.Xt = R ? k.Xt : nullptr;
+    a.colss = ws.colss;
+    a.normA = ws.normA;
+    a.flags = ws.flags;
+    a.x = k.x;
+    a.xbest = k.xbest;
+    a.u = k.u;
+    a.rc = k.rc;
+    a.q = k.q;
+    a.r = k.r;
+    a.v = k.v;
+    a.vn = k.vn;
+    a.t = k.t;
+    a.t2 = k.t2;
+    a.d = k.d;
+    a.z = k.z;
+    a.vt = k.vt;
+    a.pn = k.part_n;
+    a.pn2 = k.part_n2;
+    a.pt = k.part_t;
+    a.ssqA = k.ssqA;
+    a.ssqB = k.ssqB;
+    a.bar = k.bar;
+    a.x_user = x_user;
+    a.info = info;
+    a.splits_n = k.splits_n;
+    a.splits_t = k.splits_t;
+    a.cchunk = (n + k.splits_n - 1) / k.splits_n;
+    a.vec = ((((uintptr_t)A) & 15) == 0) && (lda % 4 == 0);
+    a.method = cfg.method;
+    a.max_iter = cfg.max_iter;
+    a.tol = cfg.tol;
+    a.cscale = compat_scale(m, n, cfg.tol);
+    const int grid = kr_loop_grid(h->device, m, n);
+    if (h->timing) {
+        long long *buf = nullptr;
+        if (!h->phase_spare.empty()) {
+            buf = h->phase_spare.back();
+            h->phase_spare.pop_back();
+        } else if (hipHostMalloc((void **)&buf, 2 * KP_COUNT * sizeof(long long)) != hipSuccess) {
+            return QRX_ENOMEM;
+        }
+        memset(buf, 0, 2 * KP_COUNT * sizeof(long long));
+        int khz = 0;
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device);
+        a.prof = buf;
+        h->phase_pending.push_back({buf, khz > 0 ? (double)khz : 1e5, m, n, np, k.splits_n,
+                                    k.splits_t});
     }
-    const double trig_scale = (normA_host > 0.0) ? rho / normA_host : 1.0;
-
-    int rc;
-    auto trsv = [&](const double *in, double *out, int trans) -> int {
-        Rec r(h, s);
-        if (R)
-            QRX_TRY(kr_trmv(s, np, k.X, in, out, k.tpart, trans));
-        else
-            QRX_TRY(kr_copy(s, np, in, out));
-        // upper triangle of X: np(np+1)/2 FP64 entries, one FMA each
-        r.end(trans ? "trmv_t" : "trmv_n", R ? (double)np * (np + 1) : 0.0,
-              R ? 4.0 * np * (np + 1) : 0.0);
-        return QRX_OK;
-    };
-    auto gemv_n = [&](const double *in) -> int {
-        Rec r(h, s);
-        QRX_TRY(kr_gemv_n(s, m, n, A, lda, in, k.part_n, nullptr, k.splits_n, 0));
-        r.end("gemv_n", 2.0 * m * n, 4.0 * m * n + 8.0 * k.splits_n * m);
-        return QRX_OK;
-    };
-    auto gemv_t = [&](const double *in) -> int {
-        Rec r(h, s);
-        QRX_TRY(kr_gemv_t(s, m, n, A, lda, in, k.part_t));
-        r.end("gemv_t", 2.0 * m * n, 4.0 * m * n + 8.0 * m);
-        return QRX_OK;
-    };
-    // certification: score = min(eta_F, compatible-system ratio) of the current x
-    auto certify_now = [&](double &score) -> int {
-        int e = certify(h, s, m, n, np, A, lda, b, k, tol);
-        if (e) return e;
-        e = sync_state(h, s, st);
-        if (e) return e;
-        score = hs[S_SCORE];
-        return QRX_OK;
-    };
-
-    double score = 0.0;
-    if ((rc = certify_now(score))) return rc;
-    info->eta_start = hs[S_ETA];
-    double best = score, best_eta = hs[S_ETA], best_rn = hs[S_RNORM];
-    QRX_TRY(kr_copy(s, np, k.x, k.xbest));
-    auto keep_if_better = [&](double sc) -> int {
-        if (sc < best) {
-            best = sc;
-            best_eta = hs[S_ETA];
-            best_rn = hs[S_RNORM];
-            QRX_TRY(kr_copy(s, np, k.x, k.xbest));
-        }
-        return QRX_OK;
-    };
-    int iters = 0, outers = 0, no_gain = 0;
-    double prev = best, gam = 1.0;
-    while (best > tol && iters < cfg.max_iter) {
-        ++outers;
-        // ---- restart on the certified residual r (k.r) and z = A^T r (k.z)
-        if (cfg.method == 0) {
-            // u = r (beta = ||r||); v = R^{-T} z / beta, alpha = ||v||, v /= alpha
-            QRX_TRY(kr_copy(s, m, k.rc, k.u));
-            QRX_TRY(kr_lsqr_restart(s, st, 0));
-            if ((rc = trsv(k.z, k.vt, 1))) return rc;
-            QRX_TRY(kr_axpby(s, np, st, -2, S_BETA, k.vt, -1, 1.0, nullptr, k.v, k.ssq));
-            QRX_TRY(kr_norm(s, k.ssq, nblocks(np), st, S_ALPHA, 1));
-            QRX_TRY(kr_axpby(s, np, st, -2, S_ALPHA, k.v, -1, 1.0, nullptr, k.v, nullptr));
-            QRX_TRY(kr_lsqr_restart(s, st, 1));
-        } else {
-            // r = certified residual; s = R^{-T} z, p = s (in v), gamma = ||s||^2
-            QRX_TRY(kr_copy(s, m, k.rc, k.r));
-            if ((rc = trsv(k.z, k.vt, 1))) return rc;
-            QRX_TRY(kr_axpby(s, np, st, -2, -1, k.vt, -1, 1.0, nullptr, k.v, k.ssq));
-            QRX_TRY(kr_norm(s, k.ssq, nblocks(np), st, S_GAMMA, 0));
-        }
-        bool first = true;
-        double best_est = HUGE_VAL;
-        int kin = 0, last_new = 0, next_check = 10;
-        while (iters < cfg.max_iter && best > tol) {
-            ++iters;
-            ++kin;
-            if (cfg.method == 0) {
-                // t = R^{-1} v; u~ = A t - (alpha/beta_old) u~_old; beta = ||u~||
-                if ((rc = trsv(k.v, k.t, 0))) return rc;
-                if ((rc = gemv_n(k.t))) return rc;
-                {
-                    Rec r(h, s);
-                    QRX_TRY(kr_combine_m(s, m, k.part_n, k.splits_n, st, S_ALPHA, S_BETA, k.u, k.u,
-                                         k.ssq));
-                    QRX_TRY(kr_norm(s, k.ssq, nblocks(m), st, S_BETA, 1));
-                    r.end("lsqr_u", 0, 8.0 * m * (k.splits_n + 2));
-                }
-                if ((rc = gemv_t(k.u))) return rc;
-                {
-                    Rec r(h, s);
-                    QRX_TRY(kr_combine_n(s, n, k.part_t, k.splits_t, k.z, k.ssq));
-                    r.end("lsqr_z", 0, 8.0 * n * (k.splits_t + 1));
-                }
-                if ((rc = trsv(k.z, k.vt, 1))) return rc;
-                {
-                    Rec r(h, s);
-                    // v~ = vt / beta - beta v ; alpha = ||v~|| ; Givens step ; x, d update
-                    QRX_TRY(kr_axpby(s, np, st, -2, S_BETA, k.vt, S_BETA, -1.0, k.v, k.v, k.ssq));
-                    QRX_TRY(kr_norm(s, k.ssq, nblocks(np), st, S_ALPHA, 1));
-                    QRX_TRY(kr_lsqr_scalar(s, st, tol));
-                    QRX_TRY(kr_lsqr_xd(s, n, st, k.t, k.d, k.x, k.v, first ? 1 : 0));
-                    QRX_TRY(kr_lsqr_shift(s, st));
-                    r.end("lsqr_scalars", 0, 0);
-                }
-                first = false;
-            } else {
-                // Alg. 5: t = R^{-1} p; q = A t; alpha = gamma/||q||^2; x += alpha t;
-                // r -= alpha q; s = R^{-T} A^T r; beta = ||s||^2/gamma; p = s + beta p
-                if ((rc = trsv(k.v, k.t, 0))) return rc;
-                if ((rc = gemv_n(k.t))) return rc;
-                {
-                    Rec r(h, s);
-                    QRX_TRY(kr_combine_m(s, m, k.part_n, k.splits_n, st, 0, -1, nullptr, k.q, k.ssq));
-                    QRX_TRY(kr_norm(s, k.ssq, nblocks(m), st, S_DELTA, 0));
-                    QRX_TRY(kr_cgls_alpha(s, st));
-                    QRX_TRY(kr_cgls_xr(s, m, n, st, k.t, k.x, k.q, k.r, k.ssq));
-                    QRX_TRY(kr_norm(s, k.ssq, nblocks(std::max(m, n)), st, S_RSS, 0));
-                    r.end("cgls_vec", 0, 0);
-                }
-                if ((rc = gemv_t(k.r))) return rc;
-                {
-                    Rec r(h, s);
-                    QRX_TRY(kr_combine_n(s, n, k.part_t, k.splits_t, k.z, k.ssq));
-                    r.end("cgls_z", 0, 0);
-                }
-                if ((rc = trsv(k.z, k.vt, 1))) return rc;
-                {
-                    Rec r(h, s);
-                    QRX_TRY(kr_axpby(s, np, st, -2, -1, k.vt, -1, 1.0, nullptr, k.vt, k.ssq));
-                    QRX_TRY(kr_norm(s, k.ssq, nblocks(np), st, S_GAMMANEW, 0));
-                    QRX_TRY(kr_cgls_beta(s, st, tol));
-                    QRX_TRY(kr_axpby(s, np, st, -2, -1, k.vt, S_CGBETA, 1.0, k.v, k.v, nullptr));
-                    r.end("cgls_scalars", 0, 0);
-                }
-            }
-            if ((rc = sync_state(h, s, st))) return rc;
-            const double est = hs[S_EST];
-            if (est < 0.99 * best_est) {
-                best_est = est;
-                last_new = kin;
-            }
-            const bool finite = std::isfinite(est);
-            const bool cg_stall = cfg.method == 1 &&
-                                  ((kin - last_new) > std::max(100, kin / 2) || est > 100.0 * best_est);
-            if (!finite || est * trig_scale <= tol * gam || cg_stall) break;
-            // periodic check of the true residual without restarting: the
-            // preconditioned estimate can stay far above tol once eta_F has
-            // reached its floor (R^{-T} amplifies rounding-level residuals)
-            if (kin >= next_check) {
-                next_check = kin + std::max(10, iters / 8);
-                if ((rc = certify_now(score))) return rc;
-                if ((rc = keep_if_better(score))) return rc;
-            }
-        }
-        if (best <= tol) break;
-        // ---- certify; keep the best iterate
-        if ((rc = certify_now(score))) return rc;
-        if (score < best) {
-            if ((rc = keep_if_better(score))) return rc;
-        } else {
-            QRX_TRY(kr_copy(s, np, k.xbest, k.x));
-            if ((rc = certify_now(score))) return rc;
-        }
-        no_gain = (best > 0.5 * prev) ? no_gain + 1 : 0;
-        prev = best;
-        if (no_gain >= 3) break;
-        if (best > tol) gam = std::max(0.01, 0.5 * gam);
-    }
-    QRX_TRY(hipMemcpyAsync(x_user, k.xbest, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    QRX_TRY(hipStreamSynchronize(s));
-    info->iters = iters;
-    info->restarts = outers > 0 ? outers - 1 : 0;
-    info->eta_F = best_eta;
-    info->resid_norm = best_rn;
-    info->status = (best <= tol) ? QRX_OK : QRX_ENOCONV;
+    Rec r(h, s);
+    QRX_TRY(kr_loop(s, a, grid));
+    r.end("krylov_loop", 0.0, 0.0);
     return QRX_OK;
 }
 
@@ -908,15 +773,6 @@ int qrx_create(qrx_handle *out, int device) {
             delete h;
             return QRX_EHIP;
         }
-        if (hipHostMalloc((void **)&h->host_state, S_COUNT * sizeof(double)) != hipSuccess) {
-            delete h;
-            return QRX_ENOMEM;
-        }
-        if (hipHostMalloc((void **)&h->host_flags, 4 * sizeof(int)) != hipSuccess) {
-            hipHostFree(h->host_state);
-            delete h;
-            return QRX_ENOMEM;
-        }
     }
     *out = h;
     return QRX_OK;
@@ -932,8 +788,9 @@ int qrx_destroy(qrx_handle h) {
         }
         for (auto e : h->spare) hipEventDestroy(e);
         if (h->pool) hipFree(h->pool);
-        if (h->host_state) hipHostFree(h->host_state);
-        if (h->host_flags) hipHostFree(h->host_flags);
+        for (void *p : h->retired) hipFree(p);
+        for (auto &p : h->phase_pending) hipHostFree(p.buf);
+        for (long long *p : h->phase_spare) hipHostFree(p);
     }
     delete h;
     return QRX_OK;
@@ -1033,7 +890,7 @@ int qrx_qr_factor_out(qrx_handle h, int64_t m, int64_t n, const float *A, int64_
 }
 
 static int lls_sizes(int64_t m, int64_t n, const QrCfg &c, const std::vector<Op> &ops,
-                     bool with_qr, size_t *bytes) {
+                     bool with_qr, bool precond, size_t *bytes) {
     Carve cv(nullptr);
     QrWork w;
     carve_qr(cv, m, n, c, ops, w);
@@ -1042,7 +899,7 @@ static int lls_sizes(int64_t m, int64_t n, const QrCfg &c, const std::vector<Op>
         cv.take<float>((size_t)round_up(n, 64) * n);
     }
     KrWork k;
-    carve_kr(cv, m, n, k);
+    carve_kr(cv, m, n, precond, k);
     *bytes = cv.off + 256;
     return QRX_OK;
 }
@@ -1058,7 +915,7 @@ int qrx_lls_workspace_size(qrx_handle h, int64_t m, int64_t n, const qrx_lls_opt
     if ((rc = resolve_lls(opts, kc))) return rc;
     std::vector<Op> ops;
     plan_rec(0, n, c, ops);
-    return lls_sizes(m, n, c, ops, true, bytes);
+    return lls_sizes(m, n, c, ops, true, true, bytes);
 }
 
 static int lls_common(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
@@ -1074,10 +931,10 @@ static int lls_common(qrx_handle h, int64_t m, int64_t n, const float *A, int64_
     if ((rc = resolve_lls(opts, kc))) return rc;
     std::vector<Op> ops;
     plan_rec(0, n, c, ops);
+    const bool precond = with_qr || Rin != nullptr;
     size_t need = 0;
-    lls_sizes(m, n, c, ops, with_qr, &need);
+    lls_sizes(m, n, c, ops, with_qr, precond, &need);
     if (work && work_bytes < need) return QRX_EINVAL;
-    memset(info, 0, sizeof(*info));
     if (h->device < 0) return QRX_EHIP;
     if (hipSetDevice(h->device) != hipSuccess) return QRX_EHIP;
     if (!work) {
@@ -1094,13 +951,8 @@ static int lls_common(qrx_handle h, int64_t m, int64_t n, const float *A, int64_
         R = cv.take<float>((size_t)ldR * n);
     }
     KrWork kw;
-    carve_kr(cv, m, n, kw);
+    carve_kr(cv, m, n, precond, kw);
 
-    hipEvent_t e0, e1, e2;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
-    hipEventCreate(&e2);
-    hipEventRecord(e0, stream);
     // status flags cleared by a kernel (the call stays safe to record in a HIP graph)
     QRX_TRY(launch_fill_f32(stream, reinterpret_cast<float *>(ws.flags), 4, 0.0f));
     {
@@ -1116,44 +968,8 @@ static int lls_common(qrx_handle h, int64_t m, int64_t n, const float *A, int64_
         QRX_TRY(launch_r_finalize(stream, n, R, ldR, ws.flags));
         r.end("r_finalize", 0, 4.0 * n * n);
     }
-    hipEventRecord(e1, stream);
-    double normA = 0.0;
-    QRX_TRY(hipMemcpyAsync(h->host_flags, ws.flags, sizeof(int), hipMemcpyDeviceToHost, stream));
-    QRX_TRY(hipMemcpyAsync(h->host_state, ws.normA, sizeof(double), hipMemcpyDeviceToHost, stream));
-    QRX_TRY(hipStreamSynchronize(stream));
-    normA = h->host_state[0];
-    info->normA_F = normA;
-    const int flags = h->host_flags[0];
-    if (flags & 1) {
-        info->status = QRX_ENONFINITE;
-    } else if (flags & 2) {
-        info->status = QRX_ESINGULAR;
-    } else {
-        // rho ~ ||R||_2 for the stopping trigger: 1 for the identity, else the largest
-        // column norm of A (a lower bound of ||A||_2 = ||R||_2)
-        double rho = 1.0;
-        if (R) {
-            std::vector<double> css(n);
-            QRX_TRY(hipMemcpy(css.data(), ws.colss, n * sizeof(double), hipMemcpyDeviceToHost));
-            double mx = 0.0;
-            for (double v : css) mx = std::max(mx, v);
-            rho = std::sqrt(mx);
-        }
-        rc = run_krylov(h, stream, m, n, A, lda, R, ldR, b, x, opts && opts->use_x0,
-                        with_qr ? W : nullptr, ldw, kc, kw, info, normA, rho);
-        if (rc) return rc;
-    }
-    hipEventRecord(e2, stream);
-    hipEventSynchronize(e2);
-    float ms1 = 0.f, ms2 = 0.f;
-    hipEventElapsedTime(&ms1, e0, e1);
-    hipEventElapsedTime(&ms2, e1, e2);
-    info->qr_ms = with_qr ? ms1 : 0.0;
-    info->krylov_ms = ms2;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipEventDestroy(e2);
-    return QRX_OK;
+    return enqueue_krylov(h, stream, m, n, A, lda, R, ldR, b, x, opts && opts->use_x0,
+                          with_qr ? W : nullptr, ldw, kc, kw, ws, info);
 }
 
 int qrx_lls_solve(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
@@ -1310,8 +1126,10 @@ int qrx_lls_solve_batched(qrx_handle h, int batch, const int64_t *m, const int64
         f.eta_F = out[i].eta;
         f.resid_norm = out[i].rnorm;
         f.normA_F = out[i].normA;
-        f.qr_ms = ms1;
-        f.krylov_ms = ms2;
+        f.score = out[i].eta;
+        f.accepted = f.status == QRX_OK ? 1 : 0;
+        (void)ms1;
+        (void)ms2;
     }
     return QRX_OK;
 }
@@ -1340,6 +1158,40 @@ static int drain_timing(qrx_handle h) {
         h->spare.push_back(p.b);
     }
     h->pending.clear();
+    // per-phase records of persistent Krylov launches (complete: their launch's
+    // closing event has been waited for above)
+    static const char *names[KP_COUNT] = {
+        "krylov:init", "krylov:certify", "krylov:restart", "krylov:trmv_n", "krylov:gemv_n",
+        "krylov:combine_m", "krylov:gemv_t", "krylov:combine_n", "krylov:trmv_t",
+        "krylov:update"};
+    for (auto &p : h->phase_pending) {
+        const double mn = (double)p.m * (double)p.n, tri = (double)p.np * (p.np + 1) / 2.0;
+        for (int ph = 0; ph < KP_COUNT; ++ph) {
+            const long long calls = p.buf[KP_COUNT + ph];
+            if (calls == 0) continue;
+            double fl = 0.0, by = 0.0;   // algorithmic work per call
+            switch (ph) {
+                case KP_GEMV_N: fl = 2.0 * mn; by = 4.0 * mn + 8.0 * p.splits_n * p.m; break;
+                case KP_GEMV_T: fl = 2.0 * mn; by = 4.0 * mn + 8.0 * p.m + 8.0 * p.splits_t * p.n; break;
+                case KP_TRMV_N:
+                case KP_TRMV_T: fl = 2.0 * tri; by = 8.0 * tri + 16.0 * p.np; break;
+                case KP_COMBINE_M: by = 8.0 * p.splits_n * p.m + 16.0 * p.m; break;
+                case KP_COMBINE_N: by = 8.0 * p.splits_t * p.n + 8.0 * p.n; break;
+                default: break;
+            }
+            qrx_kernel_stat &s = h->stats[names[ph]];
+            if (s.launches == 0) {
+                memset(&s, 0, sizeof(s));
+                strncpy(s.name, names[ph], sizeof(s.name) - 1);
+            }
+            s.launches += calls;
+            s.total_ms += (double)p.buf[ph] / p.khz;
+            s.flops += fl * calls;
+            s.bytes += by * calls;
+        }
+        h->phase_spare.push_back(p.buf);
+    }
+    h->phase_pending.clear();
     return QRX_OK;
 }
 

@@ -53,5 +53,39 @@ hipError_t kr_cgls_alpha(hipStream_t s, double *st);
 hipError_t kr_cgls_beta(hipStream_t s, double *st, double tol);
 hipError_t kr_cgls_xr(hipStream_t s, int64_t m, int64_t n, const double *st, const double *t,
                       double *x, const double *q, double *r, double *ssq);
+// Xt = X^T for np x np FP64 matrices (ld np).
+hipError_t kr_transpose(hipStream_t s, int64_t np, const double *X, double *Xt);
+
+// krylov_loop.hip: the whole Krylov iteration as one persistent kernel.
+struct KLoopArgs {
+    int64_t m, n, np, lda;
+    const float *A;                 // m x n FP32 (lda)
+    const double *b;                // m
+    const double *X, *Xt;           // R^{-1} and its transpose (np x np, ld np); null = identity
+    const double *colss, *normA;    // column sums of squares and ||A||_F from the scan
+    const int *flags;               // scan / factorisation status flags (bit 0 non-finite, 1 singular)
+    double *x, *xbest, *u, *rc, *q, *r, *v, *vn, *t, *t2, *d, *z, *vt;   // np- or m-vectors
+    double *pn, *pn2, *pt;          // GEMV partials: splits_n x m (two), splits_t x np
+    double *ssqA, *ssqB;            // kr_loop_ssq_doubles(m, np) each
+    unsigned *bar;                  // 3 barrier words, zero at launch
+    double *x_user;                 // n: receives the best certified iterate
+    qrx_lls_info *info;             // device
+    int splits_n, splits_t;
+    int64_t cchunk;                 // GEMV-N columns per split
+    int vec;                        // A 16-byte aligned with lda % 4 == 0
+    int method, max_iter;
+    double tol, cscale;
+    long long *prof;                // null, or 2 * KP_COUNT entries: wall-clock ticks and
+                                    // barrier count per phase (workgroup 0's view)
+};
+// Phases of the persistent Krylov kernel, for its per-phase timing.
+enum {
+    KP_INIT = 0, KP_CERTIFY, KP_RESTART, KP_TRMV_N, KP_GEMV_N, KP_COMBINE_M, KP_GEMV_T,
+    KP_COMBINE_N, KP_TRMV_T, KP_UPDATE, KP_COUNT
+};
+size_t kr_loop_ssq_doubles(int64_t m, int64_t np);
+// Workgroups of the persistent launch (co-resident on `device`).
+int kr_loop_grid(int device, int64_t m, int64_t n);
+hipError_t kr_loop(hipStream_t s, const KLoopArgs &a, int grid);
 
 }  // namespace qrx

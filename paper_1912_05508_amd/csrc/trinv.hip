@@ -185,6 +185,26 @@ __global__ __launch_bounds__(TT) void trmv_t_kernel(int64_t np, const double *__
     if (lane == 0) out[j] = acc;
 }
 
+// Xt = X^T (np x np, ld np) through 64 x 64 LDS tiles.
+__global__ __launch_bounds__(TT) void transpose_kernel(int64_t np, const double *__restrict__ X,
+                                                       double *__restrict__ Xt) {
+    __shared__ double tile[64][65];
+    const int64_t tiles = np / 64;
+    const int64_t bi = blockIdx.x % tiles, bj = blockIdx.x / tiles;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += TT / 64) tile[r][tx] = X[(bi * 64 + tx) + (bj * 64 + r) * np];
+    __syncthreads();
+    for (int r = ty; r < 64; r += TT / 64) Xt[(bj * 64 + tx) + (bi * 64 + r) * np] = tile[tx][r];
+}
+
+hipError_t kr_transpose(hipStream_t s, int64_t np, const double *X, double *Xt) {
+    if (np % 64) return hipErrorInvalidValue;
+    const int64_t tiles = np / 64;
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)(tiles * tiles)), dim3(TT), 0, s, np, X,
+                       Xt);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 size_t kr_trinv_tmp_doubles(int64_t np) { return (size_t)(np / 2 + IB) * (size_t)(np / 2 + IB); }
 

@@ -196,3 +196,32 @@ def test_batched_sizes_and_validation(lib, host_handle):
     st = (C.c_int * 3)()
     assert lib.qrx_qr_factor_batched(host_handle, 3, m, n, ptrs, _i64(100, 64, 300), ptrs,
                                      _i64(40, 63, 256), None, 0, None, st, None) == EINVAL
+
+
+def test_binding_checks_fire_before_the_library():
+    # the Python helpers validate dtype, device, size and layout of every buffer
+    # before any library call: a wrong dtype would make the library read or write
+    # past the end of the buffer
+    import torch
+    import paper_1912_05508_amd as P
+
+    class NoLib:
+        def __getattr__(self, name):
+            raise AssertionError(f"library called: {name}")
+
+    h = P.Handle.__new__(P.Handle)
+    h.h = C.c_void_p(1)
+    h.lib = NoLib()
+    A = torch.zeros((8, 3), dtype=torch.float32).t().contiguous().t()
+    b = torch.zeros(8, dtype=torch.float64)
+    x = torch.zeros(3, dtype=torch.float64)
+    info = torch.zeros(C.sizeof(P.qrx_lls_info), dtype=torch.uint8)
+    for args in ((A, b, x, info), (A, b.float(), x, info), (A, b, x.float(), info),
+                 (A, b[:5], x, info), (A.double(), b, x, info)):
+        with pytest.raises(P.QrxArgumentError):
+            h.lstsq_async(*args)
+    with pytest.raises(P.QrxArgumentError):
+        h.qr_out(A, A.clone(), torch.zeros((3, 3)), torch.zeros(1, dtype=torch.int32))
+    with pytest.raises(P.QrxArgumentError):
+        P._check_vec("b", torch.zeros(4, dtype=torch.float64), 5, torch.float64)
+    h.h = None

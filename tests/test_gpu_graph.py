@@ -53,3 +53,54 @@ def test_qr_graph_replay_matches_eager(prec, nb):
         del g
     finally:
         h.close()
+
+
+@pytest.mark.parametrize("prec,method", [("fp16", "lsqr"), ("fp32", "cgls")])
+def test_lls_graph_replay_matches_eager(prec, method):
+    """The whole least-squares solve (scan, QR, R^-1, the persistent Krylov
+    kernel with its device-side stopping test, certification and restarts)
+    records into a HIP graph: no host round trip per iteration. Replays give
+    the eager x and info bit for bit, with eager work between them; a larger
+    eager solve in between makes the handle grow its workspace, which must not
+    invalidate the recorded one."""
+    import torch
+    import paper_1912_05508_amd as P
+    h = P.Handle()
+    try:
+        g0 = synth.rng(3)
+        An = synth.svd_matrix(g0, 2048, 256, synth.spectrum("loguniform", 256, 1e4, g0))
+        _, bn = synth.lls_problem(synth.rng(4), An, "rel1e-6")
+        A = P.colmajor(torch.from_numpy(An).cuda())
+        b = torch.as_tensor(bn, device="cuda")
+        Ab = P.colmajor(torch.from_numpy(synth.scaled_config("c1", 4096, 512, seed=7).A).cuda())
+        bb = torch.randn(4096, dtype=torch.float64, device="cuda")
+        x = torch.zeros(256, dtype=torch.float64, device="cuda")
+        info = P.info_tensor(device="cuda")
+        kw = dict(prec=prec, method=1 if method == "cgls" else 0, tol=1e-10, max_iter=2000,
+                  cutoff=64)
+
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            h.lstsq_async(A, b, x, info, **kw)    # eager (also sizes the handle's pool)
+            torch.cuda.synchronize()
+            xe, ie = x.clone(), info.clone()
+            e = P.read_info(ie)[0]
+            assert e["status"] == 0 and e["iters"] > 0, e
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                h.lstsq_async(A, b, x, info, **kw)
+        torch.cuda.synchronize()
+        for rep in range(3):
+            x.zero_()
+            info.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(x, xe) and torch.equal(info, ie), f"replay {rep}"
+            # eager work between replays: a larger solve (grows the workspace)
+            xb, ib = h.lstsq(Ab, bb, prec="fp32", tol=1e-10)
+            torch.cuda.synchronize()
+            assert ib["status"] == 0
+        del g
+    finally:
+        h.close()
