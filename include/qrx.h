@@ -172,6 +172,22 @@ int qrx_qr_factor_out(qrx_handle h, int64_t m, int64_t n, const float *A, int64_
                       size_t work_bytes, const qrx_qr_opts *opts, int *status,
                       hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): qrx_qr_factor
+ * with its workspace in a static device array of QRX_NOALLOC_SCRATCH_BYTES
+ * bytes that the library holds on every GPU it runs on until the process ends.
+ * Same arguments, results, status and stream semantics as qrx_qr_factor, minus
+ * the workspace. Problems whose workspace (qrx_qr_workspace_size) exceeds the
+ * array are rejected with QRX_EINVAL before anything is enqueued; so is a
+ * handle with per-kernel timing on (timing creates HIP events). The call
+ * allocates no device memory. Every call on a GPU shares that GPU's array and
+ * its contents stay from the last call: calls that overlap in time on one GPU
+ * (other streams or other handles) race; serialise them. */
+#define QRX_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int qrx_qr_factor_noalloc(qrx_handle h, int64_t m, int64_t n, float *A, int64_t lda, float *R,
+                          int64_t ldr, const qrx_qr_opts *opts, int *status,
+                          hipStream_t stream);
+
 /* ---- least squares ----------------------------------------------------- */
 /* Bytes of device workspace qrx_lls_solve needs: the QR workspace, a working
  * copy of A, FP64 Krylov vectors, and X = R^{-1} as an FP64 np x np matrix

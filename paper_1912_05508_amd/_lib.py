@@ -13,7 +13,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqrx.so")
 
 QRX_OK, QRX_EINVAL, QRX_ENOMEM, QRX_EHIP = 0, -1, -2, -3
-QRX_ESINGULAR, QRX_ENONFINITE, QRX_ENOCONV = 1, 2, 3
+QRX_ESINGULAR, QRX_ENONFINITE, QRX_ENOCONV, QRX_ESYNC = 1, 2, 3, 4
+QRX_NOALLOC_SCRATCH_BYTES = 64 << 20   # the static workspace of qrx_qr_factor_noalloc
 QRX_FP32, QRX_FP16, QRX_BF16, QRX_FP16X3 = 0, 1, 2, 3
 PREC = {"fp32": QRX_FP32, "fp16": QRX_FP16, "bf16": QRX_BF16, "fp16x3": QRX_FP16X3}
 
@@ -65,6 +66,8 @@ _SIGS = {
     "qrx_qr_workspace_size": (C.c_int, [_P, _I64, _I64, C.POINTER(qrx_qr_opts), C.POINTER(C.c_size_t)]),
     "qrx_qr_factor": (C.c_int, [_P, _I64, _I64, _P, _I64, _P, _I64, _P, C.c_size_t,
                                 C.POINTER(qrx_qr_opts), _P, _P]),
+    "qrx_qr_factor_noalloc": (C.c_int, [_P, _I64, _I64, _P, _I64, _P, _I64,
+                                        C.POINTER(qrx_qr_opts), _P, _P]),
     "qrx_qr_factor_out": (C.c_int, [_P, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, C.c_size_t,
                                     C.POINTER(qrx_qr_opts), _P, _P]),
     "qrx_lls_workspace_size": (C.c_int, [_P, _I64, _I64, C.POINTER(qrx_lls_opts), C.POINTER(C.c_size_t)]),

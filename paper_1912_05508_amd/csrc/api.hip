@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -34,6 +35,7 @@ struct PendingPhases {
 
 struct qrx_handle_s {
     int device = -1;
+    void *scratch_ptr = nullptr;   // this device's address of the static scratch array
     std::vector<PendingPhases> phase_pending;
     std::vector<long long *> phase_spare;
     void *pool = nullptr;
@@ -746,6 +748,28 @@ namespace qrx {
 int handle_device(qrx_handle h) { return h ? h->device : -1; }
 }  // namespace qrx
 
+// Workspace of qrx_qr_factor_noalloc: a static device array (one per GPU, held
+// until the process ends). In host code `scratch` names a host-side stand-in,
+// not device memory: only the address hipGetSymbolAddress returns for the
+// current device may be handed to kernels.
+static __device__ __align__(256) unsigned char scratch[QRX_NOALLOC_SCRATCH_BYTES];
+
+// That address for `device` (which must be current), looked up once per device.
+static int scratch_address(int device, void **out) {
+    static std::mutex mu;
+    static std::map<int, void *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+            return QRX_EHIP;
+        it = addr.emplace(device, p).first;
+    }
+    *out = it->second;
+    return QRX_OK;
+}
+
 extern "C" {
 
 const char *qrx_status_string(int st) {
@@ -769,7 +793,7 @@ int qrx_create(qrx_handle *out, int device) {
     if (device >= 0) {
         int count = 0;
         if (hipGetDeviceCount(&count) != hipSuccess || device >= count ||
-            hipSetDevice(device) != hipSuccess) {
+            hipSetDevice(device) != hipSuccess || scratch_address(device, &h->scratch_ptr)) {
             delete h;
             return QRX_EHIP;
         }
@@ -887,6 +911,17 @@ int qrx_qr_factor_out(qrx_handle h, int64_t m, int64_t n, const float *A, int64_
                       size_t work_bytes, const qrx_qr_opts *opts, int *status,
                       hipStream_t stream) {
     return qr_common(h, m, n, A, lda, Q, ldq, R, ldr, work, work_bytes, opts, status, stream);
+}
+
+int qrx_qr_factor_noalloc(qrx_handle h, int64_t m, int64_t n, float *A, int64_t lda, float *R,
+                          int64_t ldr, const qrx_qr_opts *opts, int *status,
+                          hipStream_t stream) {
+    if (!h) return QRX_EINVAL;
+    if (h->timing) return QRX_EINVAL;   // per-kernel timing creates HIP events
+    if (h->device < 0 || !h->scratch_ptr) return QRX_EHIP;
+    // qr_common rejects a workspace smaller than the problem needs (QRX_EINVAL)
+    return qr_common(h, m, n, A, lda, A, lda, R, ldr, h->scratch_ptr, QRX_NOALLOC_SCRATCH_BYTES,
+                     opts, status, stream);
 }
 
 static int lls_sizes(int64_t m, int64_t n, const QrCfg &c, const std::vector<Op> &ops,
