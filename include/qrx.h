@@ -91,7 +91,8 @@ typedef struct {
                              1 = on, 2 = off */
     int gemm_tiles;       /* tiles of the low-precision trailing products: 0 = 256 x 256
                              tiles for nodes with at least 512 rows and columns of output
-                             (default), 1 = 128-row tiles only */
+                             (default), 1 = 128-row tiles only. Batched plans: 0 = 128 x 128,
+                             1 = 64 x 64 */
     int split_target;     /* workgroups a row-split projection aims at: 0 = default (256 with
                              256 x 256 tiles, 512 otherwise), else 16..8192 */
     int q_reorth;         /* 1 = re-orthogonalise the whole Q: factor Q again with the same
@@ -219,50 +220,69 @@ int qrx_lls_solve_with_R(qrx_handle h, int64_t m, int64_t n, const float *A, int
                          void *work, size_t work_bytes, const qrx_lls_opts *opts,
                          qrx_lls_info *info, hipStream_t stream);
 
-/* ---- batched: many small problems, one workgroup each -------------------
- * Problem i is A_i (m[i] x n[i], FP32, column-major, lda[i] >= m[i]) with
- * 1 <= n[i] <= 256 and n[i] <= m[i] <= 2^31. The arrays m, n, lda, ldr, A, R,
- * b, x, status and info are HOST arrays of length `batch`; the matrices and
- * vectors they point to are device memory owned by the caller. Each problem
- * runs Alg. 2 with 32-column Cholesky-QR panels (re-orthogonalised) and FP32
- * products, or BF16 products (FP32 accumulation, no operand scaling: BF16
- * has the FP32 exponent range) for nodes wider than the cutoff (0 = 64).
- * Options other than gemm_prec in {QRX_FP32, QRX_BF16}, panel_width 0 or 32,
- * cutoff and no_col_scaling are rejected with QRX_EINVAL (no TSQR panel,
- * single-pass panel or node re-orthogonalisation here). Both calls block
- * until the batch is done. Problems are independent: a singular or
- * non-finite problem reports its own status and does not affect the others. */
-int qrx_qr_batched_workspace_size(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
-                                  const qrx_qr_opts *opts, size_t *bytes);
+/* ---- batched: many small problems, persistent work-queue launches ---------
+ * A batch is described once by a plan (host call, blocking, allocates the
+ * plan's device tables): problem i has m[i] x n[i] with 1 <= n[i] <= 256 and
+ * n[i] <= m[i] <= 2^31 (m, n are HOST arrays of length `batch`). The plan
+ * checks the sizes (QRX_EINVAL), builds each problem's recursion schedule
+ * (Alg. 2 with 32-column Cholesky-QR panels, re-orthogonalised, FP32 products
+ * for nodes of width <= cutoff, BF16 products with FP32 accumulation and no
+ * operand scaling above it), orders the problems longest first, and sizes the
+ * workspace. cutoff and tiles are optional HOST arrays of per-problem values
+ * (NULL: opts->qr.cutoff, 0 = 64, and opts->qr.gemm_tiles): the cutoff, and the
+ * tile of the BF16 products (0 = 128 x 128, 1 = 64 x 64), e.g. as
+ * qrx_tune_batched picks them per size class. opts->qr accepts gemm_prec
+ * QRX_FP32 or QRX_BF16, panel_width 0 or 32, cutoff, gemm_tiles and
+ * no_col_scaling; other QR options must be 0 (no TSQR panel, single-pass panel,
+ * node or whole-Q re-orthogonalisation here). lls = 1 plans least squares
+ * (LSQR only, method 0, no starting iterate; the iteration starts from x = 0;
+ * tol and max_iter as in qrx_lls_opts), lls = 0 a QR factorisation. */
+typedef struct qrx_batch_plan_s *qrx_batch_plan;
+int qrx_batch_plan_create(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
+                          const int *cutoff, const int *tiles, const qrx_lls_opts *opts, int lls,
+                          qrx_batch_plan *plan);
+/* Bytes of device workspace the plan's batched call needs. */
+int qrx_batch_plan_workspace_size(qrx_batch_plan plan, size_t *bytes);
+int qrx_batch_plan_destroy(qrx_batch_plan plan);
 
-/* In place: A_i receives Q_i, R_i (n[i] x n[i], ldr[i] >= n[i]) the upper-
- * triangular factor; status[i] = QRX_OK, QRX_ESINGULAR or QRX_ENONFINITE. */
-int qrx_qr_factor_batched(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
-                          float *const *A, const int64_t *lda, float *const *R,
-                          const int64_t *ldr, void *work, size_t work_bytes,
-                          const qrx_qr_opts *opts, int *status, hipStream_t stream);
+/* The batched calls take DEVICE descriptor arrays of length `batch` (pointer
+ * arrays of device pointers, leading dimensions, and per-problem outputs), in
+ * the plan's problem order, and enqueue one fill kernel (the work-queue heads)
+ * and the persistent kernels on `stream`: the QR kernel, whose workgroups each
+ * take the next problem off an atomic queue over the longest-first order and
+ * factor it, then (least squares) the LSQR kernel, which takes the problems off
+ * a second queue in the same order and iterates each to the end. The two run
+ * at different occupancies (the QR holds a 32-column panel and a product tile
+ * per workgroup; LSQR needs a fraction of that), which is why they are two
+ * launches rather than one.
+ * Nothing is synchronised and nothing is allocated when `work` is given (or the
+ * handle's workspace is already large enough), so the call can be recorded into
+ * a HIP graph. Problems are independent: a singular, non-finite or invalid
+ * problem (NULL pointer, lda < m, ldr < n, checked on the device) reports its
+ * own status (QRX_ESINGULAR, QRX_ENONFINITE, QRX_EINVAL) and does not affect
+ * the others. Outputs are valid when the stream reaches the end of the call. */
 
-int qrx_lls_batched_workspace_size(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
-                                   const qrx_lls_opts *opts, size_t *bytes);
+/* In place (plan made with lls = 0): A_i receives Q_i, R_i (n[i] x n[i],
+ * ldr[i] >= n[i]) the upper-triangular factor; status[i] = QRX_OK,
+ * QRX_ESINGULAR, QRX_ENONFINITE or QRX_EINVAL. */
+int qrx_qr_factor_batched(qrx_handle h, qrx_batch_plan plan, float *const *A, const int64_t *lda,
+                          float *const *R, const int64_t *ldr, void *work, size_t work_bytes,
+                          int *status, hipStream_t stream);
 
-/* x_i = argmin ||A_i x - b_i|| (b_i FP64 of length m[i], x_i FP64 of length
- * n[i]) by the batched QR followed by R-preconditioned LSQR with FP64 vectors,
- * certified with a double-double residual (eta_F <= tol, as qrx_lls_solve).
- * LSQR only (method 0) and no starting iterate (use_x0 = 0); the iteration
- * starts from x = 0 (zero_start is ignored, eta_start is 0). A_i and b_i are
- * not modified. info[i] as for qrx_lls_solve; qr_ms and krylov_ms are the
- * device times of the whole batch's two phases. */
-int qrx_lls_solve_batched(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
-                          const float *const *A, const int64_t *lda, const double *const *b,
-                          double *const *x, void *work, size_t work_bytes,
-                          const qrx_lls_opts *opts, qrx_lls_info *info, hipStream_t stream);
+/* x_i = argmin ||A_i x - b_i|| (plan made with lls = 1; b_i FP64 of length m[i],
+ * x_i FP64 of length n[i]) by the batched QR followed by R-preconditioned LSQR
+ * with FP64 vectors, certified with a double-double residual (score <= tol, as
+ * qrx_lls_solve). A_i and b_i are not modified. info[i] as for qrx_lls_solve
+ * (eta_start is the eta_F of x = 0). */
+int qrx_lls_solve_batched(qrx_handle h, qrx_batch_plan plan, const float *const *A,
+                          const int64_t *lda, const double *const *b, double *const *x,
+                          void *work, size_t work_bytes, qrx_lls_info *info, hipStream_t stream);
 
 /* ---- autotuning ---------------------------------------------------------
  * The paper fixes its blocking parameters (cutoff 128, 32-column panels, 256-row
  * TSQR blocks; Sec. 3.1.3); the tuner measures them per size class instead.
  * A size class is (device architecture, precision, panel algorithm or batched,
- * ceil(log2 m), ceil(log2 n)); batched tuning uses the largest m and n of the
- * batch. */
+ * ceil(log2 m), ceil(log2 n)). */
 typedef struct {
     int panel_width;      /* nb */
     int cutoff;           /* c */
@@ -291,14 +311,21 @@ int qrx_tune(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
              const qrx_qr_opts *base, int reps, const char *cache_path,
              qrx_tune_result *out, hipStream_t stream);
 
-/* The batched counterpart: the cutoff c in {32, 64, 128, 256} for
- * qrx_qr_factor_batched of this batch (arrays as there; the matrices are not
- * modified: each candidate factors copies). panel_width is 32, gemm_tiles and
- * split_target are 0 in the result. */
+/* The batched counterpart, per size class: the problems of the batch are
+ * grouped by (ceil(log2 m), ceil(log2 n)), and for each class the cutoff c in
+ * {32, 64, 128, 256} and the BF16 product tile (128 or 64) are timed on that
+ * class's problems as a sub-batch (copies; A is not modified), the median of
+ * `reps` runs each; the best pair is stored per class in the cache (key kind 1,
+ * "batched"; panel_width 32, cutoff c, gemm_tiles = the tile) and read from it
+ * when present. A and lda are HOST arrays of device pointers and leading
+ * dimensions. cutoff and tiles (HOST arrays of length batch, written) receive
+ * each problem's values for qrx_batch_plan_create; *out sums the classes
+ * (ms = sum of the chosen sub-batch times, trials = candidates timed,
+ * from_cache = 1 when every class came from the cache). Blocks. */
 int qrx_tune_batched(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
                      const float *const *A, const int64_t *lda, const qrx_qr_opts *base,
-                     int reps, const char *cache_path, qrx_tune_result *out,
-                     hipStream_t stream);
+                     int reps, const char *cache_path, int *cutoff, int *tiles,
+                     qrx_tune_result *out, hipStream_t stream);
 
 /* Host-only access to the tuning cache (no device work, no handle): the key
  * of a size class, "<arch>/<prec>/<kind>/m<ceil log2 m>/n<ceil log2 n>" with

@@ -21,7 +21,7 @@ from ._lib import (QRX_BF16, QRX_EHIP, QRX_EINVAL, QRX_ENOCONV, QRX_ENOMEM,  # n
                    qrx_qr_opts, status_string)
 
 __all__ = ["Handle", "qr", "lstsq", "colmajor", "qr_opts", "lls_opts", "QrxError", "info_tensor",
-           "read_info", "QrxArgumentError"]
+           "read_info", "QrxArgumentError", "BatchPlan"]
 
 
 def colmajor(t, ld=None):
@@ -196,54 +196,98 @@ class Handle:
         return x, read_info(info)[0]
 
     # -- batched ---------------------------------------------------------------
+    def plan_batched(self, sizes, prec="bf16", lls=True, cutoff=None, tiles=None, **kw):
+        """A plan for problems of the given (m, n) sizes: schedules, longest-first
+        order and workspace size; cutoff and tiles are one value or one per problem."""
+        return BatchPlan(self, sizes, prec, lls, cutoff, tiles, **kw)
+
     @staticmethod
-    def _arrays(mats, extra=()):
+    def _arrays(mats):
         m = (C.c_int64 * len(mats))(*[int(a.shape[0]) for a in mats])
         n = (C.c_int64 * len(mats))(*[int(a.shape[1]) for a in mats])
         lda = (C.c_int64 * len(mats))(*[_ld(a) for a in mats])
         return m, n, lda
 
-    def qr_batched(self, mats, prec="fp32", **kw):
+    @staticmethod
+    def _ptrs(ts, device):
+        import torch
+        return torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64, device=device)
+
+    def qr_batched_async(self, plan, A_ptrs, lda, R_ptrs, ldr, status, work=None):
+        """Enqueue the batched QR of `plan` (lls = False) on the current stream:
+        device int64 tensors of matrix pointers and leading dimensions, a device
+        int32 status tensor; nothing is synchronised or allocated (with work)."""
+        wp, wb = (C.c_void_p(work.data_ptr()), work.numel() * work.element_size()) if work is not None \
+            else (None, 0)
+        rc = self.lib.qrx_qr_factor_batched(self.h, plan.p, C.c_void_p(A_ptrs.data_ptr()),
+                                            C.c_void_p(lda.data_ptr()), C.c_void_p(R_ptrs.data_ptr()),
+                                            C.c_void_p(ldr.data_ptr()), wp, wb,
+                                            C.c_void_p(status.data_ptr()), _stream())
+        _lib.check(rc, "qrx_qr_factor_batched")
+
+    def lstsq_batched_async(self, plan, A_ptrs, lda, b_ptrs, x_ptrs, info, work=None):
+        """Enqueue the batched least squares of `plan` (lls = True) on the current
+        stream: device int64 tensors of pointers (A, b, x) and leading dimensions,
+        an info buffer from info_tensor(batch)."""
+        wp, wb = (C.c_void_p(work.data_ptr()), work.numel() * work.element_size()) if work is not None \
+            else (None, 0)
+        rc = self.lib.qrx_lls_solve_batched(self.h, plan.p, C.c_void_p(A_ptrs.data_ptr()),
+                                            C.c_void_p(lda.data_ptr()), C.c_void_p(b_ptrs.data_ptr()),
+                                            C.c_void_p(x_ptrs.data_ptr()), wp, wb,
+                                            C.c_void_p(info.data_ptr()), _stream())
+        _lib.check(rc, "qrx_lls_solve_batched")
+
+    def qr_batched(self, mats, prec="fp32", cutoff=None, tiles=None, **kw):
         """In-place QR of a list of column-major (m_i, n_i) float32 tensors
         (n_i <= 256): returns (list of Q = the same tensors, list of R, statuses)."""
         import torch
         mats = [colmajor(a) for a in mats]
-        k = len(mats)
-        m, n, lda = self._arrays(mats)
-        Rs = [torch.empty((int(a.shape[1]),) * 2, dtype=torch.float32, device=a.device).t()
+        for i, a in enumerate(mats):
+            if not (a.dtype == torch.float32 and a.is_cuda):
+                raise QrxArgumentError(f"mats[{i}]: expected a float32 cuda tensor")
+        dev = mats[0].device
+        Rs = [torch.empty((int(a.shape[1]),) * 2, dtype=torch.float32, device=dev).t()
               for a in mats]
-        ldr = (C.c_int64 * k)(*[_ld(r) for r in Rs])
-        Ap = (C.c_void_p * k)(*[a.data_ptr() for a in mats])
-        Rp = (C.c_void_p * k)(*[r.data_ptr() for r in Rs])
-        st = (C.c_int * k)()
-        o = qr_opts(prec, **kw)
-        rc = self.lib.qrx_qr_factor_batched(self.h, k, m, n, Ap, lda, Rp, ldr, None, 0,
-                                            C.byref(o), st, _stream())
-        _lib.check(rc, "qrx_qr_factor_batched")
-        return mats, Rs, list(st)
+        plan = self.plan_batched([tuple(a.shape) for a in mats], prec=prec, lls=False,
+                                 cutoff=cutoff, tiles=tiles, **kw)
+        try:
+            st = torch.zeros(len(mats), dtype=torch.int32, device=dev)
+            lda = torch.tensor([_ld(a) for a in mats], dtype=torch.int64, device=dev)
+            ldr = torch.tensor([_ld(r) for r in Rs], dtype=torch.int64, device=dev)
+            self.qr_batched_async(plan, self._ptrs(mats, dev), lda, self._ptrs(Rs, dev), ldr, st)
+            return mats, Rs, st.cpu().tolist()
+        finally:
+            plan.close()
 
-    def lstsq_batched(self, mats, rhs, prec="bf16", **kw):
+    def lstsq_batched(self, mats, rhs, prec="bf16", cutoff=None, tiles=None, plan=None, **kw):
         """Least squares for lists of column-major (m_i, n_i) float32 tensors and
-        float64 (m_i,) vectors: returns (list of x_i, list of info dicts)."""
+        float64 (m_i,) vectors with the persistent work-queue kernels: returns (list of x_i, list
+        of info dicts)."""
         import torch
         mats = [colmajor(a) for a in mats]
         rhs = [b.contiguous() for b in rhs]
         k = len(mats)
         for i, (a, b) in enumerate(zip(mats, rhs)):
+            if not (a.dtype == torch.float32 and a.is_cuda):
+                raise QrxArgumentError(f"mats[{i}]: expected a float32 cuda tensor")
             _check_vec(f"rhs[{i}]", b, int(a.shape[0]), torch.float64)
-        m, n, lda = self._arrays(mats)
+        dev = mats[0].device
         ns = [int(a.shape[1]) for a in mats]
-        flat = torch.zeros(sum(ns), dtype=torch.float64, device=mats[0].device)
+        flat = torch.zeros(sum(ns), dtype=torch.float64, device=dev)
         xs = list(torch.split(flat, ns))
-        Ap = (C.c_void_p * k)(*[a.data_ptr() for a in mats])
-        bp = (C.c_void_p * k)(*[b.data_ptr() for b in rhs])
-        xp = (C.c_void_p * k)(*[x.data_ptr() for x in xs])
-        infos = (qrx_lls_info * k)()
-        o = lls_opts(prec, **kw)
-        rc = self.lib.qrx_lls_solve_batched(self.h, k, m, n, Ap, lda, bp, xp, None, 0,
-                                            C.byref(o), infos, _stream())
-        _lib.check(rc, "qrx_lls_solve_batched")
-        return xs, [infos[i].as_dict() for i in range(k)]
+        own = plan is None
+        if own:
+            plan = self.plan_batched([tuple(a.shape) for a in mats], prec=prec, lls=True,
+                                     cutoff=cutoff, tiles=tiles, **kw)
+        try:
+            info = info_tensor(k, device=dev)
+            lda = torch.tensor([_ld(a) for a in mats], dtype=torch.int64, device=dev)
+            self.lstsq_batched_async(plan, self._ptrs(mats, dev), lda, self._ptrs(rhs, dev),
+                                     self._ptrs(xs, dev), info)
+            return xs, read_info(info, k)
+        finally:
+            if own:
+                plan.close()
 
     # -- autotuning -------------------------------------------------------------
     def tune(self, A, prec="fp16", cache=None, reps=3, **kw):
@@ -264,18 +308,25 @@ class Handle:
         return r.as_dict()
 
     def tune_batched(self, mats, prec="bf16", cache=None, reps=3, **kw):
-        """Tune the cutoff of the batched QR for this batch (matrices not modified)."""
+        """Tune the batched QR per size class of this batch (matrices not modified):
+        returns a dict with per-problem lists 'cutoff' and 'tiles' (for
+        plan_batched) and the summary fields ms, trials, from_cache."""
         mats = [colmajor(a) for a in mats]
         k = len(mats)
         m, n, lda = self._arrays(mats)
         Ap = (C.c_void_p * k)(*[a.data_ptr() for a in mats])
         o = qr_opts(prec, **kw)
         r = _lib.qrx_tune_result()
+        cut = (C.c_int * k)()
+        til = (C.c_int * k)()
         path = os.fsencode(cache) if cache is not None else None
         rc = self.lib.qrx_tune_batched(self.h, k, m, n, Ap, lda, C.byref(o), int(reps), path,
-                                       C.byref(r), _stream())
+                                       cut, til, C.byref(r), _stream())
         _lib.check(rc, "qrx_tune_batched")
-        return r.as_dict()
+        d = r.as_dict()
+        d["cutoff"] = list(cut)
+        d["tiles"] = list(til)
+        return d
 
     # -- timing ---------------------------------------------------------------
     def timing(self, enable=True):
@@ -295,6 +346,46 @@ class Handle:
             out[s.name.decode()] = dict(launches=s.launches, total_ms=s.total_ms, flops=s.flops,
                                         bytes=s.bytes)
         return out
+
+
+class BatchPlan:
+    """A batch plan (qrx_batch_plan): the problems' sizes, schedules and
+    longest-first order, uploaded to the device once."""
+
+    def __init__(self, handle, sizes, prec="bf16", lls=True, cutoff=None, tiles=None, **kw):
+        k = len(sizes)
+        self.handle = handle
+        self.batch = k
+        m = (C.c_int64 * k)(*[int(s[0]) for s in sizes])
+        n = (C.c_int64 * k)(*[int(s[1]) for s in sizes])
+
+        def per(v):
+            if v is None:
+                return None
+            vals = list(v) if hasattr(v, "__len__") else [int(v)] * k
+            if len(vals) != k:
+                raise QrxArgumentError("per-problem values: expected one per problem")
+            return (C.c_int * k)(*[int(x) for x in vals])
+        o = lls_opts(prec, **kw)
+        p = C.c_void_p()
+        rc = handle.lib.qrx_batch_plan_create(handle.h, k, m, n, per(cutoff), per(tiles),
+                                              C.byref(o), 1 if lls else 0, C.byref(p))
+        _lib.check(rc, "qrx_batch_plan_create")
+        self.p = p
+        sz = C.c_size_t()
+        _lib.check(handle.lib.qrx_batch_plan_workspace_size(p, C.byref(sz)))
+        self.work_bytes = sz.value
+
+    def close(self):
+        if self.p:
+            self.handle.lib.qrx_batch_plan_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _default = None

@@ -76,18 +76,17 @@ _SIGS = {
                                 C.POINTER(qrx_lls_opts), _P, _P]),
     "qrx_lls_solve_with_R": (C.c_int, [_P, _I64, _I64, _P, _I64, _P, _I64, _P, _P, _P, C.c_size_t,
                                        C.POINTER(qrx_lls_opts), _P, _P]),
-    "qrx_qr_batched_workspace_size": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(qrx_qr_opts),
-                                                 C.POINTER(C.c_size_t)]),
-    "qrx_qr_factor_batched": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, _P, _P, C.c_size_t,
-                                        C.POINTER(qrx_qr_opts), _P, _P]),
-    "qrx_lls_batched_workspace_size": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(qrx_lls_opts),
-                                                  C.POINTER(C.c_size_t)]),
-    "qrx_lls_solve_batched": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, _P, _P, C.c_size_t,
-                                        C.POINTER(qrx_lls_opts), _P, _P]),
+    # batched: a host-built plan, then device descriptor arrays
+    "qrx_batch_plan_create": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, C.POINTER(qrx_lls_opts),
+                                        C.c_int, C.POINTER(_P)]),
+    "qrx_batch_plan_workspace_size": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "qrx_batch_plan_destroy": (C.c_int, [_P]),
+    "qrx_qr_factor_batched": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P, _P]),
+    "qrx_lls_solve_batched": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P, _P]),
     "qrx_tune": (C.c_int, [_P, _I64, _I64, _P, _I64, C.POINTER(qrx_qr_opts), C.c_int, C.c_char_p,
                            C.POINTER(qrx_tune_result), _P]),
     "qrx_tune_batched": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, C.POINTER(qrx_qr_opts), C.c_int,
-                                   C.c_char_p, C.POINTER(qrx_tune_result), _P]),
+                                   C.c_char_p, _P, _P, C.POINTER(qrx_tune_result), _P]),
     "qrx_tune_key": (C.c_int, [C.c_char_p, _I64, _I64, C.c_int, C.c_int, C.c_char_p, C.c_size_t]),
     "qrx_tune_cache_get": (C.c_int, [C.c_char_p, C.c_char_p, C.POINTER(qrx_tune_result)]),
     "qrx_tune_cache_put": (C.c_int, [C.c_char_p, C.c_char_p, C.POINTER(qrx_tune_result)]),

@@ -638,16 +638,19 @@ int enqueue_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const floa
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
-// ---- batched (one workgroup per problem) -----------------------------------
-namespace {
-
-struct BPlan {
-    QrCfg c;
-    std::vector<BOp> ops;         // schedules of the distinct n, concatenated
-    std::vector<int> op0, nops;   // per problem
-    std::vector<int> order;       // longest first
-    size_t bytes = 0;
+// ---- batched: plans and the persistent work-queue launch ---------------------
+struct qrx_batch_plan_s {
+    int device = -1;
+    int batch = 0, lls = 0, prec = 0, max_iter = 0;
+    double tol = 0.0;
+    size_t work_bytes = 0;         // counter + per-problem storage
+    void *tables = nullptr;        // device: BEntry[batch] | int order[batch] | BOp ops[]
+    BEntry *ent = nullptr;
+    int *order = nullptr;
+    BOp *ops = nullptr;
 };
+
+namespace {
 
 int resolve_batched(const qrx_qr_opts *o, QrCfg &c) {
     qrx_qr_opts z;
@@ -658,11 +661,12 @@ int resolve_batched(const qrx_qr_opts *o, QrCfg &c) {
     if (o->panel_width != 0 && o->panel_width != kBPanel) return QRX_EINVAL;
     if (o->cutoff < 0 || o->block_rows < 0) return QRX_EINVAL;
     if (o->no_col_scaling < 0 || o->no_col_scaling > 1) return QRX_EINVAL;
-    if (o->gemm_tiles != 0 || o->split_target != 0 || o->q_reorth != 0) return QRX_EINVAL;
+    if (o->gemm_tiles < 0 || o->gemm_tiles > 1) return QRX_EINVAL;
+    if (o->split_target != 0 || o->q_reorth != 0) return QRX_EINVAL;
     c.prec = o->gemm_prec;
     c.alg = 0;
     c.nb = kBPanel;
-    c.tiles = 0;
+    c.tiles = o->gemm_tiles;
     c.split_target = 0;
     int cut = o->cutoff ? o->cutoff : 64;
     if (cut < c.nb) cut = c.nb;
@@ -674,78 +678,14 @@ int resolve_batched(const qrx_qr_opts *o, QrCfg &c) {
     return QRX_OK;
 }
 
-// Problem checks, schedules, launch order and workspace size (lls: working
-// copies and Krylov vectors too).
-int plan_batched(int batch, const int64_t *m, const int64_t *n, const int64_t *lda,
-                 const qrx_qr_opts *o, bool lls, BPlan &P) {
-    if (batch < 1 || !m || !n) return QRX_EINVAL;
-    int rc = resolve_batched(o, P.c);
-    if (rc) return rc;
-    std::map<int64_t, std::pair<int, int>> sched;
-    P.op0.resize(batch);
-    P.nops.resize(batch);
-    std::vector<double> cost(batch);
-    size_t bytes = 0;
-    auto add = [&](size_t b) { bytes = (bytes + 255) / 256 * 256 + b; };
-    for (int i = 0; i < batch; ++i) {
-        if (n[i] < 1 || n[i] > kBMaxN || m[i] < n[i] || m[i] > ((int64_t)1 << 31)) return QRX_EINVAL;
-        if (lda && lda[i] < m[i]) return QRX_EINVAL;
-        auto it = sched.find(n[i]);
-        if (it == sched.end()) {
-            std::vector<Op> ops;
-            plan_rec(0, n[i], P.c, ops);
-            const int start = (int)P.ops.size();
-            for (const Op &op : ops)
-                P.ops.push_back({op.kind, (int)op.c0, (int)op.k, (int)op.n2,
-                                 op.kind == 1 && op.prec != QRX_FP32 ? 1 : 0});
-            it = sched.emplace(n[i], std::make_pair(start, (int)ops.size())).first;
-        }
-        P.op0[i] = it->second.first;
-        P.nops[i] = it->second.second;
-        const double mm = (double)m[i], nn = (double)n[i];
-        cost[i] = mm * nn * nn + (lls ? 40.0 * mm * nn : 0.0);
-        add(sizeof(float) * (size_t)n[i] * (size_t)n[i]);                        // R
-        if (lls) {
-            add(sizeof(float) * (size_t)round_up(m[i], 4) * (size_t)n[i]);       // W
-            add(2 * sizeof(double) * (size_t)m[i]);                              // u, q
-        }
-    }
-    P.order.resize(batch);
-    for (int i = 0; i < batch; ++i) P.order[i] = i;
-    std::stable_sort(P.order.begin(), P.order.end(),
-                     [&](int a, int b) { return cost[a] > cost[b]; });
-    add(sizeof(BProb) * (size_t)batch);
-    add(sizeof(int) * (size_t)batch);
-    add(sizeof(BOp) * P.ops.size());
-    add(sizeof(BOut) * (size_t)batch);
-    P.bytes = bytes + 256;
-    return QRX_OK;
-}
-
-struct BRun {
-    BProb *probs;
-    int *order;
-    BOp *ops;
-    BOut *out;
-};
-
-// Carves the descriptor arrays (after the per-problem buffers) and uploads them.
-int upload_batched(hipStream_t s, Carve &cv, std::vector<BProb> &hp, const BPlan &P, BRun &r) {
-    const int batch = (int)hp.size();
-    r.probs = cv.take<BProb>(batch);
-    r.order = cv.take<int>(batch);
-    r.ops = cv.take<BOp>(P.ops.size());
-    r.out = cv.take<BOut>(batch);
-    QRX_TRY(hipMemcpyAsync(r.probs, hp.data(), sizeof(BProb) * batch, hipMemcpyHostToDevice, s));
-    QRX_TRY(hipMemcpyAsync(r.order, P.order.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
-    QRX_TRY(hipMemcpyAsync(r.ops, P.ops.data(), sizeof(BOp) * P.ops.size(), hipMemcpyHostToDevice, s));
-    return QRX_OK;
-}
-
 }  // namespace
 
 namespace qrx {
 int handle_device(qrx_handle h) { return h ? h->device : -1; }
+int batched_opts_check(const qrx_qr_opts *o) {
+    QrCfg c;
+    return resolve_batched(o, c);
+}
 }  // namespace qrx
 
 // Workspace of qrx_qr_factor_noalloc: a static device array (one per GPU, held
@@ -1023,150 +963,170 @@ int qrx_lls_solve_with_R(qrx_handle h, int64_t m, int64_t n, const float *A, int
                       stream);
 }
 
-int qrx_qr_batched_workspace_size(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
-                                  const qrx_qr_opts *opts, size_t *bytes) {
-    if (!h || !bytes) return QRX_EINVAL;
-    BPlan P;
-    int rc = plan_batched(batch, m, n, nullptr, opts, false, P);
-    if (rc) return rc;
-    *bytes = P.bytes;
-    return QRX_OK;
-}
-
-int qrx_qr_factor_batched(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
-                          float *const *A, const int64_t *lda, float *const *R,
-                          const int64_t *ldr, void *work, size_t work_bytes,
-                          const qrx_qr_opts *opts, int *status, hipStream_t stream) {
-    if (!h || !A || !lda || !R || !ldr || !status) return QRX_EINVAL;
-    BPlan P;
-    int rc = plan_batched(batch, m, n, lda, opts, false, P);
-    if (rc) return rc;
-    for (int i = 0; i < batch; ++i)
-        if (!A[i] || !R[i] || ldr[i] < n[i]) return QRX_EINVAL;
-    if (work && work_bytes < P.bytes) return QRX_EINVAL;
-    if (h->device < 0 || hipSetDevice(h->device) != hipSuccess) return QRX_EHIP;
-    if (!work && (rc = ensure_pool(h, P.bytes, &work))) return rc;
-    Carve cv(work);
-    std::vector<BProb> hp(batch);
-    for (int i = 0; i < batch; ++i) {
-        BProb &b = hp[i];
-        memset(&b, 0, sizeof(b));
-        b.m = m[i];
-        b.n = n[i];
-        b.lda = lda[i];
-        b.ldw = lda[i];
-        b.ldr = ldr[i];
-        b.A = A[i];
-        b.W = A[i];
-        b.R = R[i];
-        b.op0 = P.op0[i];
-        b.nops = P.nops[i];
-        cv.take<float>((size_t)n[i] * (size_t)n[i]);   // keeps the layout of the size query
-    }
-    BRun r;
-    if ((rc = upload_batched(stream, cv, hp, P, r))) return rc;
-    {
-        Rec rec(h, stream);
-        QRX_TRY(launch_bqr(stream, P.c.prec, batch, r.probs, r.order, r.ops, 0, r.out));
-        rec.end("bqr", 0, 0);
-    }
-    std::vector<BOut> out(batch);
-    QRX_TRY(hipMemcpyAsync(out.data(), r.out, sizeof(BOut) * batch, hipMemcpyDeviceToHost, stream));
-    QRX_TRY(hipStreamSynchronize(stream));
-    for (int i = 0; i < batch; ++i) status[i] = out[i].status;
-    return QRX_OK;
-}
-
-int qrx_lls_batched_workspace_size(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
-                                   const qrx_lls_opts *opts, size_t *bytes) {
-    if (!h || !bytes) return QRX_EINVAL;
-    BPlan P;
-    int rc = plan_batched(batch, m, n, nullptr, opts ? &opts->qr : nullptr, true, P);
-    if (rc) return rc;
-    *bytes = P.bytes;
-    return QRX_OK;
-}
-
-int qrx_lls_solve_batched(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
-                          const float *const *A, const int64_t *lda, const double *const *b,
-                          double *const *x, void *work, size_t work_bytes,
-                          const qrx_lls_opts *opts, qrx_lls_info *info, hipStream_t stream) {
-    if (!h || !A || !lda || !b || !x || !info) return QRX_EINVAL;
-    BPlan P;
-    int rc = plan_batched(batch, m, n, lda, opts ? &opts->qr : nullptr, true, P);
+int qrx_batch_plan_create(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
+                          const int *cutoff, const int *tiles, const qrx_lls_opts *opts, int lls,
+                          qrx_batch_plan *plan) {
+    if (!h || !plan || batch < 1 || !m || !n || (lls != 0 && lls != 1)) return QRX_EINVAL;
+    *plan = nullptr;
+    QrCfg c;
+    int rc = resolve_batched(opts ? &opts->qr : nullptr, c);
     if (rc) return rc;
     KrCfg kc;
-    if ((rc = resolve_lls(opts, kc))) return rc;
-    if (opts && (opts->method != 0 || opts->use_x0)) return QRX_EINVAL;
-    for (int i = 0; i < batch; ++i)
-        if (!A[i] || !b[i] || !x[i]) return QRX_EINVAL;
-    if (work && work_bytes < P.bytes) return QRX_EINVAL;
+    memset(&kc, 0, sizeof(kc));
+    if (lls) {
+        if ((rc = resolve_lls(opts, kc))) return rc;
+        if (opts && (opts->method != 0 || opts->use_x0)) return QRX_EINVAL;
+    }
+    std::vector<BEntry> ent(batch);
+    std::vector<BOp> ops;
+    std::map<std::pair<int64_t, int>, std::pair<int, int>> sched;   // (n, cutoff) -> slice
+    std::vector<double> cost(batch);
+    // the two work-queue heads, then the per-problem QR records (least squares)
+    size_t off = 256 + (lls ? sizeof(BRes) * (size_t)batch : 0);
+    auto take = [&](size_t bytes) {
+        off = (off + 255) / 256 * 256;
+        const size_t at = off;
+        off += bytes;
+        return (int64_t)at;
+    };
+    for (int i = 0; i < batch; ++i) {
+        if (n[i] < 1 || n[i] > kBMaxN || m[i] < n[i] || m[i] > ((int64_t)1 << 31)) return QRX_EINVAL;
+        int ci = cutoff ? cutoff[i] : c.c;
+        if (ci < 1) return QRX_EINVAL;
+        ci = (int)round_up(ci < c.nb ? c.nb : ci, c.nb);
+        const int ti = tiles ? tiles[i] : c.tiles;
+        if (ti < 0 || ti > 1) return QRX_EINVAL;
+        auto key = std::make_pair(n[i], ci);
+        auto it = sched.find(key);
+        if (it == sched.end()) {
+            QrCfg ck = c;
+            ck.c = ci;
+            std::vector<Op> o2;
+            plan_rec(0, n[i], ck, o2);
+            const int start = (int)ops.size();
+            for (const Op &op : o2)
+                ops.push_back({op.kind, (int)op.c0, (int)op.k, (int)op.n2,
+                               op.kind == 1 && op.prec != QRX_FP32 ? 1 : 0});
+            it = sched.emplace(key, std::make_pair(start, (int)o2.size())).first;
+        }
+        BEntry &e = ent[i];
+        memset(&e, 0, sizeof(e));
+        e.m = m[i];
+        e.n = n[i];
+        e.op0 = it->second.first;
+        e.nops = it->second.second;
+        e.tiles = ti;
+        if (lls) {
+            e.ldw = round_up(m[i], 4);
+            e.w_off = take(sizeof(float) * (size_t)e.ldw * (size_t)n[i]);
+            e.r_off = take(sizeof(float) * (size_t)n[i] * (size_t)n[i]);
+            e.v_off = take(2 * sizeof(double) * (size_t)m[i]);
+        }
+        const double mm = (double)m[i], nn = (double)n[i];
+        cost[i] = mm * nn * nn + (lls ? 40.0 * mm * nn : 0.0);
+    }
+    std::vector<int> order(batch);
+    for (int i = 0; i < batch; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     if (h->device < 0 || hipSetDevice(h->device) != hipSuccess) return QRX_EHIP;
-    if (!work && (rc = ensure_pool(h, P.bytes, &work))) return rc;
-    Carve cv(work);
-    std::vector<BProb> hp(batch);
-    for (int i = 0; i < batch; ++i) {
-        BProb &q = hp[i];
-        memset(&q, 0, sizeof(q));
-        q.m = m[i];
-        q.n = n[i];
-        q.lda = lda[i];
-        q.ldr = n[i];
-        q.A = A[i];
-        q.b = b[i];
-        q.x = x[i];
-        q.R = cv.take<float>((size_t)n[i] * (size_t)n[i]);
-        q.ldw = round_up(m[i], 4);
-        q.W = cv.take<float>((size_t)q.ldw * (size_t)n[i]);
-        double *uq = cv.take<double>(2 * (size_t)m[i]);
-        q.u = uq;
-        q.q = uq + m[i];
-        q.op0 = P.op0[i];
-        q.nops = P.nops[i];
+    qrx_batch_plan p = new qrx_batch_plan_s();
+    p->device = h->device;
+    p->batch = batch;
+    p->lls = lls;
+    p->prec = c.prec;
+    p->tol = kc.tol;
+    p->max_iter = kc.max_iter;
+    p->work_bytes = off + 256;
+    const size_t eb = sizeof(BEntry) * (size_t)batch;
+    const size_t ob = (sizeof(int) * (size_t)batch + 255) / 256 * 256;
+    const size_t pb = sizeof(BOp) * ops.size();
+    if (hipMalloc(&p->tables, eb + ob + pb) != hipSuccess) {
+        delete p;
+        return QRX_ENOMEM;
     }
-    BRun r;
-    if ((rc = upload_batched(stream, cv, hp, P, r))) return rc;
-    hipEvent_t e0, e1, e2;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
-    hipEventCreate(&e2);
-    hipEventRecord(e0, stream);
-    {
-        Rec rec(h, stream);
-        QRX_TRY(launch_bqr(stream, P.c.prec, batch, r.probs, r.order, r.ops, 1, r.out));
-        rec.end("bqr", 0, 0);
+    p->ent = reinterpret_cast<BEntry *>(p->tables);
+    p->order = reinterpret_cast<int *>((char *)p->tables + eb);
+    p->ops = reinterpret_cast<BOp *>((char *)p->tables + eb + ob);
+    if (hipMemcpy(p->ent, ent.data(), eb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->order, order.data(), sizeof(int) * (size_t)batch, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(p->ops, ops.data(), pb, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(p->tables);
+        delete p;
+        return QRX_EHIP;
     }
-    hipEventRecord(e1, stream);
-    {
-        Rec rec(h, stream);
-        QRX_TRY(launch_blsqr(stream, batch, r.probs, r.order, kc.tol, kc.max_iter, r.out));
-        rec.end("blsqr", 0, 0);
-    }
-    hipEventRecord(e2, stream);
-    std::vector<BOut> out(batch);
-    QRX_TRY(hipMemcpyAsync(out.data(), r.out, sizeof(BOut) * batch, hipMemcpyDeviceToHost, stream));
-    QRX_TRY(hipStreamSynchronize(stream));
-    float ms1 = 0.f, ms2 = 0.f;
-    hipEventElapsedTime(&ms1, e0, e1);
-    hipEventElapsedTime(&ms2, e1, e2);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipEventDestroy(e2);
-    for (int i = 0; i < batch; ++i) {
-        qrx_lls_info &f = info[i];
-        memset(&f, 0, sizeof(f));
-        f.status = out[i].status;
-        f.iters = out[i].iters;
-        f.restarts = out[i].restarts;
-        f.eta_F = out[i].eta;
-        f.resid_norm = out[i].rnorm;
-        f.normA_F = out[i].normA;
-        f.score = out[i].eta;
-        f.accepted = f.status == QRX_OK ? 1 : 0;
-        (void)ms1;
-        (void)ms2;
-    }
+    *plan = p;
     return QRX_OK;
+}
+
+int qrx_batch_plan_workspace_size(qrx_batch_plan plan, size_t *bytes) {
+    if (!plan || !bytes) return QRX_EINVAL;
+    *bytes = plan->work_bytes;
+    return QRX_OK;
+}
+
+int qrx_batch_plan_destroy(qrx_batch_plan plan) {
+    if (!plan) return QRX_EINVAL;
+    if (plan->tables) {
+        hipSetDevice(plan->device);
+        hipFree(plan->tables);
+    }
+    delete plan;
+    return QRX_OK;
+}
+
+static int batched_common(qrx_handle h, qrx_batch_plan plan, int lls, const float *const *A,
+                          const int64_t *lda, float *const *R, const int64_t *ldr,
+                          const double *const *b, double *const *x, void *work,
+                          size_t work_bytes, int *status, qrx_lls_info *info,
+                          hipStream_t stream) {
+    if (!h || !plan || plan->lls != lls || !A || !lda) return QRX_EINVAL;
+    if (lls ? (!b || !x || !info) : (!R || !ldr || !status)) return QRX_EINVAL;
+    if (h->device < 0 || h->device != plan->device) return QRX_EINVAL;
+    if (work && work_bytes < plan->work_bytes) return QRX_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return QRX_EHIP;
+    int rc;
+    if (!work && (rc = ensure_pool(h, plan->work_bytes, &work))) return rc;
+    BArgs a;
+    memset(&a, 0, sizeof(a));
+    a.ent = plan->ent;
+    a.order = plan->order;
+    a.ops = plan->ops;
+    a.batch = plan->batch;
+    a.lls = lls;
+    a.A = A;
+    a.lda = lda;
+    a.R = R;
+    a.ldr = ldr;
+    a.b = b;
+    a.x = x;
+    a.work = reinterpret_cast<char *>(work);
+    a.counter = reinterpret_cast<unsigned *>(work);
+    a.res = lls ? reinterpret_cast<BRes *>(reinterpret_cast<char *>(work) + 256) : nullptr;
+    a.status = status;
+    a.info = info;
+    a.tol = plan->tol;
+    a.max_iter = plan->max_iter;
+    // the work-queue heads are cleared by a kernel (the call stays safe to record in a graph)
+    QRX_TRY(launch_fill_f32(stream, reinterpret_cast<float *>(work), 2, 0.0f));
+    Rec r(h, stream);
+    QRX_TRY(launch_bsolve(stream, h->device, plan->prec, a));
+    r.end(lls ? "batched_lls" : "batched_qr", 0.0, 0.0);
+    return QRX_OK;
+}
+
+int qrx_qr_factor_batched(qrx_handle h, qrx_batch_plan plan, float *const *A, const int64_t *lda,
+                          float *const *R, const int64_t *ldr, void *work, size_t work_bytes,
+                          int *status, hipStream_t stream) {
+    return batched_common(h, plan, 0, const_cast<const float *const *>(A), lda, R, ldr, nullptr,
+                          nullptr, work, work_bytes, status, nullptr, stream);
+}
+
+int qrx_lls_solve_batched(qrx_handle h, qrx_batch_plan plan, const float *const *A,
+                          const int64_t *lda, const double *const *b, double *const *x,
+                          void *work, size_t work_bytes, qrx_lls_info *info, hipStream_t stream) {
+    return batched_common(h, plan, 1, A, lda, nullptr, nullptr, b, x, work, work_bytes, nullptr,
+                          info, stream);
 }
 
 int qrx_timing_enable(qrx_handle h, int enable) {

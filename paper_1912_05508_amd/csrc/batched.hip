@@ -34,11 +34,38 @@ constexpr int kPanelLds = gram::Lds<32>::C_DOUBLES + gram::Lds<32>::X_DOUBLES +
 constexpr int kGemmLds = 2 * 128 * (64 + 8) * 2 / 8;   // two 128 x (BK+PAD) 16-bit tiles
 static_assert(2 * 128 * (32 + 4) * 4 / 8 <= kGemmLds, "FP32 tiles fit");
 constexpr int kBqrLds = kPanelLds > kGemmLds ? kPanelLds : kGemmLds;
+// the LSQR phase reuses the same LDS: 8 n-vectors and a 64 x 65 FP32 block
+static_assert(8 * 256 + (64 * 65 + 1) / 2 <= kBqrLds, "LSQR vectors fit the QR's LDS");
 
 QRX_DEV bool al16(const void *p) { return (((uintptr_t)p) & 15) == 0; }
 
 // Second panel sweep skipped when Q1^T Q1 is within this of I in every entry.
 constexpr double kBSkipTau = 1.0 / (1 << 21);
+
+// A value every lane holds alike, made uniform for the compiler: branches on it
+// are then scalar branches. Loops and branches that contain barriers must be
+// uniform in this sense, or the compiler may restructure them per lane.
+QRX_DEV int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// The same for a trivially copyable value of whole 32-bit words (a descriptor
+// loaded from device memory at a uniform address arrives in vector registers).
+template <class T>
+QRX_DEV T uniform_v(const T &v) {
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    constexpr int W = sizeof(T) / 4;
+    unsigned w[W];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < W; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
+QRX_DEV double uniform_d(double v) {
+    const unsigned long long b = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(b & 0xffffffffu));
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 // Sum over the workgroup (fixed order); every thread gets the result.
 QRX_DEV double bsum(double v, double *sh) {
@@ -46,7 +73,7 @@ QRX_DEV double bsum(double v, double *sh) {
     __syncthreads();
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    return uniform_d((sh[0] + sh[1]) + (sh[2] + sh[3]));
 }
 QRX_DEV double bmax(double v, double *sh) {
 #pragma unroll
@@ -54,29 +81,30 @@ QRX_DEV double bmax(double v, double *sh) {
     __syncthreads();
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    return uniform_d(fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3])));
 }
 
 // ---------------------------------------------------------------------------
 // In-workgroup trailing products (same tiles as the single-problem kernels).
 // ---------------------------------------------------------------------------
-// R12 (k x n2, ldr) = Q1^T A2 over K = m rows, 128 x 128 output tiles.
-template <class Tr>
+// R12 (k x n2, ldr) = Q1^T A2 over K = m rows, TILE x TILE output tiles (4 waves
+// of TILE/2 x TILE/2).
+template <class Tr, int TILE>
 QRX_DEV void wg_project(int64_t m, int k, int n2, const float *Q1, const float *A2, int64_t ld,
                         float *R12, int64_t ldr, typename Tr::E *As, typename Tr::E *Bs, int t) {
     using E = typename Tr::E;
-    constexpr int BK = Tr::BK, LS = BK + Tr::PAD, FM = 4, FN = 4;
+    constexpr int BK = Tr::BK, LS = BK + Tr::PAD, FM = TILE / 32, FN = TILE / 32, WT = TILE / 2;
     const int lane = t & 63, wv = t >> 6, wm = wv % 2, wn = wv / 2;
     const bool vec = al16(Q1) && al16(A2) && (ld % 4 == 0);
     auto one = [](int64_t) { return 1.0f; };
-    for (int i0 = 0; i0 < k; i0 += 128)
-        for (int j0 = 0; j0 < n2; j0 += 128) {
+    for (int i0 = 0; i0 < k; i0 += TILE)
+        for (int j0 = 0; j0 < n2; j0 += TILE) {
             f32x4 acc[FM][FN];
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-            KLoader<BK, 128> la, lb;
+            KLoader<BK, TILE> la, lb;
             la.load(Q1, ld, 0, m, i0, k, vec, t);
             lb.load(A2, ld, 0, m, j0, n2, vec, t);
             for (int64_t k0 = 0; k0 < m; k0 += BK) {
@@ -88,14 +116,14 @@ QRX_DEV void wg_project(int64_t m, int k, int n2, const float *Q1, const float *
                     la.load(Q1, ld, k0 + BK, m, i0, k, vec, t);
                     lb.load(A2, ld, k0 + BK, m, j0, n2, vec, t);
                 }
-                mma_stage<Tr, FM, FN>(As, Bs, wm * 64, wn * 64, acc, lane);
+                mma_stage<Tr, FM, FN>(As, Bs, wm * WT, wn * WT, acc, lane);
             }
 #pragma unroll
             for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
                 for (int fn = 0; fn < FN; ++fn) {
-                    const int j = j0 + wn * 64 + fn * 16 + (lane & 15);
-                    const int ib = i0 + wm * 64 + fm * 16 + 4 * (lane >> 4);
+                    const int j = j0 + wn * WT + fn * 16 + (lane & 15);
+                    const int ib = i0 + wm * WT + fm * 16 + 4 * (lane >> 4);
                     if (j < n2) {
 #pragma unroll
                         for (int v = 0; v < 4; ++v)
@@ -106,27 +134,27 @@ QRX_DEV void wg_project(int64_t m, int k, int n2, const float *Q1, const float *
     __syncthreads();
 }
 
-// A2 (m x n2) -= Q1 (m x k) R12 (k x n2), 128-row x 128-column tiles.
-template <class Tr>
+// A2 (m x n2) -= Q1 (m x k) R12 (k x n2), TILE-row x TILE-column tiles.
+template <class Tr, int TILE>
 QRX_DEV void wg_update(int64_t m, int k, int n2, const float *Q1, float *A2, int64_t ld,
                        const float *R12, int64_t ldr, typename Tr::E *As, typename Tr::E *Bs,
                        int t) {
     using E = typename Tr::E;
-    constexpr int BK = Tr::BK, LS = BK + Tr::PAD, FM = 4, FN = 4;
+    constexpr int BK = Tr::BK, LS = BK + Tr::PAD, FM = TILE / 32, FN = TILE / 32, WT = TILE / 2;
     const int lane = t & 63, wv = t >> 6, wm = wv % 2, wn = wv / 2;
     const bool vecq = al16(Q1) && (ld % 4 == 0);
     const bool vecr = al16(R12) && (ldr % 4 == 0);
     const bool veca = al16(A2) && (ld % 4 == 0);
     auto one = [](int64_t) { return 1.0f; };
-    for (int j0 = 0; j0 < n2; j0 += 128)
-        for (int64_t r0 = 0; r0 < m; r0 += 128) {
+    for (int j0 = 0; j0 < n2; j0 += TILE)
+        for (int64_t r0 = 0; r0 < m; r0 += TILE) {
             f32x4 acc[FM][FN];
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-            MLoader<BK, 128> la;
-            KLoader<BK, 128> lb;
+            MLoader<BK, TILE> la;
+            KLoader<BK, TILE> lb;
             la.load(Q1, ld, r0, m, 0, k, vecq, t);
             lb.load(R12, ldr, 0, k, j0, n2, vecr, t);
             for (int k0 = 0; k0 < k; k0 += BK) {
@@ -138,15 +166,15 @@ QRX_DEV void wg_update(int64_t m, int k, int n2, const float *Q1, float *A2, int
                     la.load(Q1, ld, r0, m, k0 + BK, k, vecq, t);
                     lb.load(R12, ldr, k0 + BK, k, j0, n2, vecr, t);
                 }
-                mma_stage<Tr, FM, FN>(As, Bs, wm * 64, wn * 64, acc, lane);
+                mma_stage<Tr, FM, FN>(As, Bs, wm * WT, wn * WT, acc, lane);
             }
 #pragma unroll
             for (int fn = 0; fn < FN; ++fn) {
-                const int j = j0 + wn * 64 + fn * 16 + (lane & 15);
+                const int j = j0 + wn * WT + fn * 16 + (lane & 15);
                 if (j >= n2) continue;
 #pragma unroll
                 for (int fm = 0; fm < FM; ++fm) {
-                    const int64_t rb = r0 + wm * 64 + fm * 16 + 4 * (lane >> 4);
+                    const int64_t rb = r0 + wm * WT + fm * 16 + 4 * (lane >> 4);
                     float *dst = A2 + (int64_t)j * ld + rb;
                     if (veca && rb + 3 < m) {
                         float4 x = *reinterpret_cast<float4 *>(dst);
@@ -247,22 +275,26 @@ QRX_DEV void wg_panel(float *P, int64_t ld, int64_t m, int w, float *Rb, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// QR kernel
+// One problem's QR in one workgroup: scan (||A||_F, largest column norm, finite
+// check, working copy), the recursion over its schedule, R finalisation.
 // ---------------------------------------------------------------------------
+
+struct BProb {
+    int64_t m, n, lda, ldw, ldr;
+    const float *A;   // the problem matrix (read by the scan and by the Krylov products)
+    float *W;         // working copy, Q on exit (== A for an in-place QR)
+    float *R;         // n x n upper triangle, ldr
+    const double *b;  // right-hand side (least squares)
+    double *x;        // solution (least squares)
+    double *u, *q;    // FP64 m-vectors (least squares)
+    int op0, nops, tiles;
+};
+
 template <class Tr>
-__global__ __launch_bounds__(BT) void bqr_kernel(const BProb *__restrict__ probs,
-                                                 const int *__restrict__ order,
-                                                 const BOp *__restrict__ ops, int copy,
-                                                 BOut *__restrict__ out) {
-    __shared__ __align__(16) double lds[kBqrLds];
-    __shared__ double sh[4];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int pi = order[blockIdx.x];
-    const BProb p = probs[pi];
+QRX_DEV BRes wg_qr(const BProb &p, const BOp *ops, int copy, double *lds, double *sh, int t) {
+    const int lane = t & 63, wv = t >> 6;
     const int64_t m = p.m;
     const int n = (int)p.n;
-
-    // scan: ||A||_F^2 and the largest column norm (FP64), finite check, copy
     double ss_tot = 0.0, ss_max = 0.0;
     int bad = 0;
     for (int j = wv; j < n; j += BT / 64) {
@@ -287,7 +319,7 @@ __global__ __launch_bounds__(BT) void bqr_kernel(const BProb *__restrict__ probs
     if (!bad) {
         using E = typename Tr::E;
         for (int o = p.op0; o < p.op0 + p.nops; ++o) {
-            const BOp op = ops[o];
+            const BOp op = uniform_v(ops[o]);
             float *Wc = p.W + (int64_t)op.c0 * p.ldw;
             if (op.kind == 0) {
                 wg_panel(Wc, p.ldw, m, op.k, p.R + op.c0 + (int64_t)op.c0 * p.ldr, p.ldr, lds, t);
@@ -297,13 +329,23 @@ __global__ __launch_bounds__(BT) void bqr_kernel(const BProb *__restrict__ probs
                 if (op.lowp) {
                     E *As = reinterpret_cast<E *>(lds);
                     E *Bs = As + 128 * (Tr::BK + Tr::PAD);
-                    wg_project<Tr>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
-                    wg_update<Tr>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
+                    bool small = false;
+                    if constexpr (Tr::BK == 64) {   // 64 x 64 tiles: 16-bit operands only
+                        if (p.tiles == 1) {
+                            small = true;
+                            wg_project<Tr, 64>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
+                            wg_update<Tr, 64>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
+                        }
+                    }
+                    if (!small) {
+                        wg_project<Tr, 128>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
+                        wg_update<Tr, 128>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
+                    }
                 } else {
                     float *As = reinterpret_cast<float *>(lds);
                     float *Bs = As + 128 * (PF32::BK + PF32::PAD);
-                    wg_project<PF32>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
-                    wg_update<PF32>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
+                    wg_project<PF32, 128>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
+                    wg_update<PF32, 128>(m, op.k, op.n2, Wc, A2, p.ldw, R12, p.ldr, As, Bs, t);
                 }
             }
         }
@@ -320,11 +362,12 @@ __global__ __launch_bounds__(BT) void bqr_kernel(const BProb *__restrict__ probs
         }
     }
     sing = bsum(sing ? 1.0 : 0.0, sh) > 0.0;
-    if (t == 0) {
-        out[pi].status = bad ? QRX_ENONFINITE : (sing ? QRX_ESINGULAR : QRX_OK);
-        out[pi].normA = sqrt(ss_tot);
-        out[pi].rho = sqrt(ss_max);
-    }
+    __syncthreads();
+    BRes r;
+    r.status = bad ? QRX_ENONFINITE : (sing ? QRX_ESINGULAR : QRX_OK);
+    r.normA = sqrt(ss_tot);
+    r.rho = sqrt(ss_max);
+    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -448,15 +491,12 @@ QRX_DEV double wg_certify(const BProb &p, const double *x, double *z, double *q,
     return fmin(eta, s1);
 }
 
-__global__ __launch_bounds__(BT) void blsqr_kernel(const BProb *__restrict__ probs,
-                                                   const int *__restrict__ order, double tol,
-                                                   int max_iter, BOut *__restrict__ out) {
-    __shared__ double vecs[8 * kBMaxN];
-    __shared__ float Rb[64 * 65];
-    __shared__ double sh[4];
-    const int t = threadIdx.x;
-    const int pi = order[blockIdx.x];
-    const BProb p = probs[pi];
+// One problem's R-preconditioned LSQR (Sec. 3.2.3) in one workgroup, from x = 0,
+// certified with a double-double residual and restarted on it; writes x and *info.
+QRX_DEV void wg_lsqr(const BProb &p, const BRes &qr, double tol, int max_iter, qrx_lls_info *info,
+                     double *lds, double *sh, int t) {
+    double *vecs = lds;   // 8 n-vectors, then the 64 x 65 block of the triangular solves
+    float *Rb = reinterpret_cast<float *>(lds + 8 * kBMaxN);
     const int n = (int)p.n;
     BVec V;
     V.x = vecs;
@@ -469,30 +509,30 @@ __global__ __launch_bounds__(BT) void blsqr_kernel(const BProb *__restrict__ pro
     V.xs = vecs + 7 * kBMaxN;
     for (int i = t; i < 8 * kBMaxN; i += BT) vecs[i] = 0.0;
     __syncthreads();
-    const int qst = out[pi].status;
-    if (qst != QRX_OK) {
+    if (qr.status != QRX_OK) {
         for (int j = t; j < n; j += BT) p.x[j] = 0.0;
         if (t == 0) {
-            out[pi].iters = 0;
-            out[pi].restarts = 0;
-            out[pi].eta = 0.0;
-            out[pi].rnorm = 0.0;
+            memset(info, 0, sizeof(*info));
+            info->status = qr.status;
+            info->normA_F = qr.normA;
         }
+        __syncthreads();
         return;
     }
-    const double normA = out[pi].normA;
+    const double normA = qr.normA;
     // the LSQR estimate bounds ||(A R^{-1})^T r|| / ||r||; the scaled test compares
     // it with the eta_F target through the largest column norm
-    const double trig = normA > 0.0 ? out[pi].rho / normA : 1.0;
+    const double trig = normA > 0.0 ? qr.rho / normA : 1.0;
     double bb = 0.0;
     for (int64_t r = t; r < p.m; r += BT) bb = fma(p.b[r], p.b[r], bb);
     const double bnorm = sqrt(bsum(bb, sh));
-
     double gamma = 1.0, best = 1e300, eta = 0.0, rnorm = 0.0, best_eta = 0.0, best_rn = 0.0;
+    double first_eta = 0.0;
     int iters = 0, restarts = 0, stall = 0, status = QRX_ENOCONV;
     for (int outer = 0;; ++outer) {
         // certify the current x; q = residual, z = A^T q
         const double score = wg_certify(p, V.x, V.z, p.q, normA, bnorm, eta, rnorm, sh, t, tol);
+        if (outer == 0) first_eta = eta;
         if (score < best) {
             if (score < 0.5 * best) stall = 0; else ++stall;
             best = score;
@@ -564,34 +604,152 @@ __global__ __launch_bounds__(BT) void blsqr_kernel(const BProb *__restrict__ pro
     }
     for (int j = t; j < n; j += BT) p.x[j] = V.xb[j];
     if (t == 0) {
-        out[pi].status = status;
-        out[pi].iters = iters;
-        out[pi].restarts = restarts;
-        out[pi].eta = best_eta;
-        out[pi].rnorm = best_rn;
+        info->status = status;
+        info->iters = iters;
+        info->restarts = restarts;
+        info->accepted = status == QRX_OK ? (best_eta <= tol ? 1 : 2) : 0;
+        info->eta_F = best_eta;
+        info->resid_norm = best_rn;
+        info->normA_F = normA;
+        info->eta_start = first_eta;
+        info->score = best;
+    }
+    __syncthreads();
+}
+
+
+// ---------------------------------------------------------------------------
+// The persistent batched kernels: each workgroup takes the next problem from an
+// atomic queue over the longest-first order until the queue is empty. The QR
+// kernel factors it; for least squares a second kernel, with its own queue,
+// runs LSQR on each factored problem (it fits four workgroups per CU where the
+// QR fits one).
+// ---------------------------------------------------------------------------
+// The next queue index for this workgroup (uniform: every lane gets it in a
+// scalar register; read back through LDS it would count as divergent, and the
+// loop around it holds barriers).
+QRX_DEV int queue_next(unsigned *counter, int *s_idx, int t) {
+    if (t == 0) *s_idx = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int idx = uniform_i(*s_idx);
+    __syncthreads();
+    return idx;
+}
+
+// Problem `pi` as the batched calls describe it (uniform values); false for a
+// bad descriptor.
+QRX_DEV bool load_problem(const BArgs &a, int pi, BProb &p) {
+    const BEntry e = uniform_v(a.ent[pi]);
+    p.m = e.m;
+    p.n = e.n;
+    p.A = uniform_v(a.A[pi]);
+    p.lda = uniform_v(a.lda[pi]);
+    p.op0 = e.op0;
+    p.nops = e.nops;
+    p.tiles = e.tiles;
+    bool ok = p.A != nullptr && p.lda >= p.m;
+    if (a.lls) {
+        p.b = uniform_v(a.b[pi]);
+        p.x = uniform_v(a.x[pi]);
+        p.W = reinterpret_cast<float *>(a.work + e.w_off);
+        p.ldw = e.ldw;
+        p.R = reinterpret_cast<float *>(a.work + e.r_off);
+        p.ldr = e.n;
+        p.u = reinterpret_cast<double *>(a.work + e.v_off);
+        p.q = p.u + e.m;
+        ok = ok && p.b != nullptr && p.x != nullptr;
+    } else {
+        p.W = const_cast<float *>(p.A);
+        p.ldw = p.lda;
+        p.R = uniform_v(a.R[pi]);
+        p.ldr = uniform_v(a.ldr[pi]);
+        p.b = nullptr;
+        p.x = nullptr;
+        p.u = p.q = nullptr;
+        ok = ok && p.R != nullptr && p.ldr >= p.n;
+    }
+    return ok;
+}
+
+// Phase 1 of a batch: every problem's QR, taken off the first work queue in the
+// longest-first order. For least squares the factorisation's results go to the
+// per-problem records of phase 2; a bad descriptor is reported here.
+template <class Tr>
+__global__ __launch_bounds__(BT) void bqr_queue_kernel(BArgs a) {
+    __shared__ __align__(16) double lds[kBqrLds];
+    __shared__ double sh[4];
+    __shared__ int s_idx;
+    const int t = threadIdx.x;
+    // one loop, one back edge, no early exits: each pass takes one problem
+    for (int idx = queue_next(a.counter, &s_idx, t); idx < a.batch;
+         idx = queue_next(a.counter, &s_idx, t)) {
+        const int pi = uniform_i(a.order[idx]);
+        BProb p;
+        const bool ok = load_problem(a, pi, p);
+        if (ok) {
+            const BRes r = wg_qr<Tr>(p, a.ops, a.lls, lds, sh, t);
+            if (t == 0) {
+                if (a.lls)
+                    a.res[pi] = r;
+                else
+                    a.status[pi] = r.status;
+            }
+        } else if (t == 0) {
+            if (a.lls) {
+                memset(a.info + pi, 0, sizeof(qrx_lls_info));
+                a.info[pi].status = QRX_EINVAL;
+                a.res[pi].status = QRX_EINVAL;
+            } else {
+                a.status[pi] = QRX_EINVAL;
+            }
+        }
+    }
+}
+
+// Phase 2 (least squares): every problem's LSQR, off the second work queue.
+__global__ __launch_bounds__(BT) void blsqr_queue_kernel(BArgs a) {
+    __shared__ __align__(16) double lds[8 * kBMaxN + (64 * 65 + 1) / 2];
+    __shared__ double sh[4];
+    __shared__ int s_idx;
+    const int t = threadIdx.x;
+    for (int idx = queue_next(a.counter + 1, &s_idx, t); idx < a.batch;
+         idx = queue_next(a.counter + 1, &s_idx, t)) {
+        const int pi = uniform_i(a.order[idx]);
+        BProb p;
+        if (load_problem(a, pi, p)) {
+            const BRes r = uniform_v(a.res[pi]);
+            wg_lsqr(p, r, a.tol, a.max_iter, a.info + pi, lds, sh, t);
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-hipError_t launch_bqr(hipStream_t s, int prec, int batch, const BProb *probs, const int *order,
-                      const BOp *ops, int copy, BOut *out) {
-    const dim3 g((unsigned)batch), b(BT);
-    switch (prec) {
-        case QRX_FP32:
-            hipLaunchKernelGGL(bqr_kernel<PF32>, g, b, 0, s, probs, order, ops, copy, out);
-            break;
-        case QRX_BF16:
-            hipLaunchKernelGGL(bqr_kernel<PBF16>, g, b, 0, s, probs, order, ops, copy, out);
-            break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+// Workgroups of a persistent queue launch: what fits on the device at once,
+// and no more than there are problems.
+static int queue_grid(const void *kernel, int device, int batch) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        cus < 1)
+        cus = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, BT, 0) != hipSuccess || per < 1)
+        per = 1;
+    const int64_t g = (int64_t)per * cus;
+    return (int)(batch < g ? batch : g);
 }
 
-hipError_t launch_blsqr(hipStream_t s, int batch, const BProb *probs, const int *order,
-                        double tol, int max_iter, BOut *out) {
-    hipLaunchKernelGGL(blsqr_kernel, dim3((unsigned)batch), dim3(BT), 0, s, probs, order, tol,
-                       max_iter, out);
+hipError_t launch_bsolve(hipStream_t s, int device, int prec, const BArgs &a) {
+    const void *qk = prec == QRX_BF16 ? (const void *)bqr_queue_kernel<PBF16>
+                                      : (const void *)bqr_queue_kernel<PF32>;
+    if (prec != QRX_FP32 && prec != QRX_BF16) return hipErrorInvalidValue;
+    const int gq = queue_grid(qk, device, a.batch);
+    if (prec == QRX_BF16)
+        hipLaunchKernelGGL(bqr_queue_kernel<PBF16>, dim3((unsigned)gq), dim3(BT), 0, s, a);
+    else
+        hipLaunchKernelGGL(bqr_queue_kernel<PF32>, dim3((unsigned)gq), dim3(BT), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.lls) return e;
+    const int gl = queue_grid((const void *)blsqr_queue_kernel, device, a.batch);
+    hipLaunchKernelGGL(blsqr_queue_kernel, dim3((unsigned)gl), dim3(BT), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,4 +1,4 @@
-// Descriptors of the batched path (device memory, written by the host).
+// The batched path: a plan's device tables and the one persistent kernel.
 #pragma once
 #include "qrx_internal.hpp"
 
@@ -13,25 +13,45 @@ struct BOp {          // one step of the recursion schedule (Alg. 2)
     int lowp;         // node products in the low precision (width > cutoff)
 };
 
-struct BProb {
-    int64_t m, n, lda, ldw, ldr;
-    const float *A;   // the problem matrix (read by the scan and by the Krylov products)
-    float *W;         // working copy, Q on exit (== A for an in-place QR)
-    float *R;         // n x n upper triangle, ldr
-    const double *b;  // right-hand side (LLS)
-    double *x;        // solution (LLS)
-    double *u, *q;    // FP64 m-vectors (LLS)
-    int op0, nops;    // slice of the schedule table
+// Per problem, built by a plan on the host and uploaded once.
+struct BEntry {
+    int64_t m, n;
+    int64_t ldw;                   // leading dimension of the working copy (least squares)
+    int64_t w_off, r_off, v_off;   // workspace byte offsets: working copy, R, u | q
+    int op0, nops;                 // slice of the schedule table
+    int tiles;                     // trailing-product tile of the low-precision nodes (0: 128, 1: 64)
+    int pad;
 };
 
-struct BOut {
-    int status, iters, restarts, pad;
-    double eta, rnorm, normA, rho;
+// What a problem's QR hands to its LSQR (per-problem record in the workspace).
+struct BRes {
+    int status, pad;
+    double normA, rho;
 };
 
-hipError_t launch_bqr(hipStream_t s, int prec, int batch, const BProb *probs, const int *order,
-                      const BOp *ops, int copy, BOut *out);
-hipError_t launch_blsqr(hipStream_t s, int batch, const BProb *probs, const int *order,
-                        double tol, int max_iter, BOut *out);
+// Arguments of the persistent batched kernels (device arrays throughout).
+struct BArgs {
+    const BEntry *ent;
+    const int *order;              // longest first
+    const BOp *ops;
+    int batch, lls;
+    const float *const *A;         // problem matrices (QR: overwritten by Q)
+    const int64_t *lda;
+    float *const *R;               // QR: R outputs
+    const int64_t *ldr;
+    const double *const *b;        // least squares: right-hand sides and solutions
+    double *const *x;
+    char *work;                    // per-problem working storage (least squares)
+    unsigned *counter;             // heads of the QR and LSQR work queues, zero at launch
+    BRes *res;                     // least squares: per-problem QR results
+    int *status;                   // QR: per-problem status
+    qrx_lls_info *info;            // least squares: per-problem result
+    double tol;
+    int max_iter;
+};
+
+// The persistent batched launch: the QR work-queue kernel, then (least squares)
+// the LSQR work-queue kernel, each with as many workgroups as fit on the device.
+hipError_t launch_bsolve(hipStream_t s, int device, int prec, const BArgs &a);
 
 }  // namespace qrx

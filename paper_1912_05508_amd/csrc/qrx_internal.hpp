@@ -18,6 +18,8 @@ namespace qrx {
 
 // Device index of a handle (-1 if it has none).
 int handle_device(qrx_handle h);
+// QRX_OK when *o is a valid set of options for the batched path.
+int batched_opts_check(const qrx_qr_opts *o);
 
 // The compatible-system ratio ||r|| / (||A||_F ||x|| + ||b||) certifies a
 // solution at tol for square systems, where eta_F is undefined (r is rounding

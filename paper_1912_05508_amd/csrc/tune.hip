@@ -12,6 +12,7 @@
 #include "qrx_internal.hpp"
 
 #include <algorithm>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -335,137 +336,191 @@ int qrx_tune(qrx_handle h, int64_t m, int64_t n, const float *A, int64_t lda,
 
 int qrx_tune_batched(qrx_handle h, int batch, const int64_t *m, const int64_t *n,
                      const float *const *A, const int64_t *lda, const qrx_qr_opts *base,
-                     int reps, const char *cache_path, qrx_tune_result *out,
-                     hipStream_t stream) {
-    if (!h || batch < 1 || !m || !n || !A || !lda || !out || reps < 1 || reps > 20)
+                     int reps, const char *cache_path, int *cutoff, int *tiles,
+                     qrx_tune_result *out, hipStream_t stream) {
+    if (!h || batch < 1 || !m || !n || !A || !lda || !cutoff || !tiles || !out || reps < 1 ||
+        reps > 20)
         return QRX_EINVAL;
-    qrx_qr_opts b0;
-    memset(&b0, 0, sizeof(b0));
-    if (base) b0 = *base;
-    size_t probe = 0;
-    int rc = qrx_qr_batched_workspace_size(h, batch, m, n, &b0, &probe);   // validates
-    if (rc != QRX_OK) return rc;
+    qrx_lls_opts lo;
+    memset(&lo, 0, sizeof(lo));
+    if (base) lo.qr = *base;
+    // sizes and options are checked before any device work
+    for (int i = 0; i < batch; ++i)
+        if (!A[i] || lda[i] < m[i] || n[i] < 1 || n[i] > 256 || m[i] < n[i] ||
+            m[i] > ((int64_t)1 << 31))
+            return QRX_EINVAL;
+    if (batched_opts_check(&lo.qr) != QRX_OK) return QRX_EINVAL;
     if (handle_device(h) < 0) return QRX_EHIP;
     memset(out, 0, sizeof(*out));
-    int64_t mmax = 0, nmax = 0, total = 0;
-    for (int i = 0; i < batch; ++i) {
-        if (!A[i] || lda[i] < m[i]) return QRX_EINVAL;
-        mmax = std::max(mmax, m[i]);
-        nmax = std::max(nmax, n[i]);
-        total += m[i] * n[i];
-    }
-    char arch[64], key[256];
+    char arch[64];
     if (!device_arch(h, arch, sizeof(arch))) return QRX_EHIP;
-    rc = qrx_tune_key(arch, mmax, nmax, b0.gemm_prec, 1, key, sizeof(key));
-    if (rc != QRX_OK) return rc;
-    if (cache_path) {
-        rc = cache_lookup(cache_path, key, out);
-        if (rc == QRX_OK) return QRX_OK;
-        if (rc != 1) return rc;
-    }
-    // compact copies: a pristine one and a working one restored before each run
-    float *pristine = nullptr, *wk = nullptr, *Rb = nullptr;
-    int *st = nullptr;
-    void *work = nullptr;
-    int64_t rtot = 0;
-    for (int i = 0; i < batch; ++i) rtot += n[i] * n[i];
-    auto release = [&]() {
-        if (pristine) (void)hipFree(pristine);
-        if (wk) (void)hipFree(wk);
-        if (Rb) (void)hipFree(Rb);
-        if (st) (void)hipFree(st);
-        if (work) (void)hipFree(work);
-    };
-    std::vector<std::vector<int>> lists(4);
-    lists[0] = {32};
-    lists[1] = {32, 64, 128, 256};
-    lists[2] = {0};
-    lists[3] = {0};
-    size_t wmax = 0;
-    for (int c : lists[1]) {
-        qrx_qr_opts o = b0;
-        o.cutoff = c;
-        size_t b = 0;
-        if (qrx_qr_batched_workspace_size(h, batch, m, n, &o, &b) == QRX_OK) wmax = std::max(wmax, b);
-    }
-    if (hipMalloc(&pristine, sizeof(float) * (size_t)total) != hipSuccess ||
-        hipMalloc(&wk, sizeof(float) * (size_t)total) != hipSuccess ||
-        hipMalloc(&Rb, sizeof(float) * (size_t)rtot) != hipSuccess ||
-        hipMalloc(&st, sizeof(int) * (size_t)batch) != hipSuccess ||
-        (wmax && hipMalloc(&work, wmax) != hipSuccess)) {
-        release();
-        return QRX_ENOMEM;
-    }
-    std::vector<float *> Aw(batch), Rw(batch);
-    std::vector<int64_t> ldw(batch), ldr(batch);
-    std::vector<int> sth(batch);
-    {
-        int64_t off = 0, roff = 0;
-        for (int i = 0; i < batch; ++i) {
-            if (hipMemcpy2DAsync(pristine + off, sizeof(float) * m[i], A[i], sizeof(float) * lda[i],
-                                 sizeof(float) * m[i], n[i], hipMemcpyDeviceToDevice,
-                                 stream) != hipSuccess) {
-                release();
-                return QRX_EHIP;
-            }
-            Aw[i] = wk + off;
-            ldw[i] = m[i];
-            Rw[i] = Rb + roff;
-            ldr[i] = n[i];
-            off += m[i] * n[i];
-            roff += n[i] * n[i];
-        }
-    }
+    // size classes
+    std::map<std::pair<int, int>, std::vector<int>> classes;
+    for (int i = 0; i < batch; ++i)
+        classes[std::make_pair(ceil_log2(m[i]), ceil_log2(n[i]))].push_back(i);
+    bool all_cached = true;
+    int trials = 0;
+    double ms_sum = 0.0;
     hipEvent_t ea = nullptr, eb = nullptr;
     if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
         if (ea) (void)hipEventDestroy(ea);
-        release();
         return QRX_EHIP;
     }
-    // each run factors a fresh copy (restored outside the timed interval); run 0 warms up
-    auto run = [&](const Cand &c, double &ms) -> int {
-        qrx_qr_opts o = b0;
-        o.cutoff = c.c;
-        o.panel_width = 0;
-        size_t b = 0;
-        int r2 = qrx_qr_batched_workspace_size(h, batch, m, n, &o, &b);
-        if (r2 != QRX_OK) return r2;
-        std::vector<double> ts;
-        for (int r = 0; r <= reps; ++r) {
-            if (hipMemcpyAsync(wk, pristine, sizeof(float) * (size_t)total,
-                               hipMemcpyDeviceToDevice, stream) != hipSuccess ||
-                hipEventRecord(ea, stream) != hipSuccess)
-                return QRX_EHIP;
-            r2 = qrx_qr_factor_batched(h, batch, m, n, Aw.data(), ldw.data(), Rw.data(),
-                                       ldr.data(), work, wmax, &o, sth.data(), stream);
-            if (r2 != QRX_OK) return r2;
-            float t = 0.f;
-            if (hipEventRecord(eb, stream) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
-                hipEventElapsedTime(&t, ea, eb) != hipSuccess)
-                return QRX_EHIP;
-            if (r > 0) ts.push_back(t);
+    int rc = QRX_OK;
+    for (auto &cl : classes) {
+        const std::vector<int> &idx = cl.second;
+        const int k = (int)idx.size();
+        int64_t mmax = 0, nmax = 0, total = 0, rtot = 0;
+        for (int i : idx) {
+            mmax = std::max(mmax, m[i]);
+            nmax = std::max(nmax, n[i]);
+            total += m[i] * n[i];
+            rtot += n[i] * n[i];
         }
-        std::sort(ts.begin(), ts.end());
-        ms = ts[ts.size() / 2];
-        return QRX_OK;
-    };
-    Cand cur{32, b0.cutoff ? b0.cutoff : 64, 0, 0};
-    Cand best;
-    double best_ms = 0.0;
-    int trials = 0;
-    rc = coord_search(lists, cur, run, best, best_ms, trials);
+        char key[256];
+        if ((rc = qrx_tune_key(arch, mmax, nmax, lo.qr.gemm_prec, 1, key, sizeof(key)))) break;
+        qrx_tune_result r;
+        memset(&r, 0, sizeof(r));
+        int found = 1;
+        if (cache_path) {
+            found = cache_lookup(cache_path, key, &r);
+            if (found != QRX_OK && found != 1) {
+                rc = found;
+                break;
+            }
+        }
+        if (found != QRX_OK) {
+            all_cached = false;
+            // the class's problems as a sub-batch of compact copies
+            std::vector<int64_t> ms(k), ns(k), ldw(k), ldr(k);
+            std::vector<float *> Aw(k), Rw(k);
+            float *pristine = nullptr, *wk = nullptr, *Rb = nullptr;
+            void *dev = nullptr, *work = nullptr;
+            auto release = [&]() {
+                for (void *q : {(void *)pristine, (void *)wk, (void *)Rb, dev, work})
+                    if (q) (void)hipFree(q);
+            };
+            const size_t descb = (size_t)k * (2 * sizeof(void *) + 2 * sizeof(int64_t) + sizeof(int));
+            if (hipMalloc(&pristine, sizeof(float) * (size_t)total) != hipSuccess ||
+                hipMalloc(&wk, sizeof(float) * (size_t)total) != hipSuccess ||
+                hipMalloc(&Rb, sizeof(float) * (size_t)rtot) != hipSuccess ||
+                hipMalloc(&dev, descb) != hipSuccess) {
+                release();
+                rc = QRX_ENOMEM;
+                break;
+            }
+            int64_t off = 0, roff = 0;
+            for (int q = 0; q < k; ++q) {
+                const int i = idx[q];
+                ms[q] = m[i];
+                ns[q] = n[i];
+                if (hipMemcpy2DAsync(pristine + off, sizeof(float) * m[i], A[i],
+                                     sizeof(float) * lda[i], sizeof(float) * m[i], n[i],
+                                     hipMemcpyDeviceToDevice, stream) != hipSuccess) {
+                    rc = QRX_EHIP;
+                    break;
+                }
+                Aw[q] = wk + off;
+                ldw[q] = m[i];
+                Rw[q] = Rb + roff;
+                ldr[q] = n[i];
+                off += m[i] * n[i];
+                roff += n[i] * n[i];
+            }
+            // device descriptor arrays: A | R | lda | ldr | status
+            float **dA = reinterpret_cast<float **>(dev);
+            float **dR = dA + k;
+            int64_t *dlda = reinterpret_cast<int64_t *>(dR + k);
+            int64_t *dldr = dlda + k;
+            int *dst = reinterpret_cast<int *>(dldr + k);
+            if (rc == QRX_OK &&
+                (hipMemcpy(dA, Aw.data(), sizeof(void *) * k, hipMemcpyHostToDevice) != hipSuccess ||
+                 hipMemcpy(dR, Rw.data(), sizeof(void *) * k, hipMemcpyHostToDevice) != hipSuccess ||
+                 hipMemcpy(dlda, ldw.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice) !=
+                     hipSuccess ||
+                 hipMemcpy(dldr, ldr.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice) !=
+                     hipSuccess))
+                rc = QRX_EHIP;
+            double best_ms = 1e300;
+            int best_c = 64, best_t = 0;
+            for (int c : {32, 64, 128, 256}) {
+                if (rc != QRX_OK) break;
+                if (c > 32 && c / 2 >= nmax) break;   // every node is already FP32
+                for (int tl : {0, 1}) {
+                    if (tl == 1 && c >= nmax) break;  // no low-precision node to tile
+                    std::vector<int> cv(k, c), tv(k, tl);
+                    qrx_batch_plan plan = nullptr;
+                    if ((rc = qrx_batch_plan_create(h, k, ms.data(), ns.data(), cv.data(),
+                                                    tv.data(), &lo, 0, &plan)))
+                        break;
+                    size_t wb = 0;
+                    qrx_batch_plan_workspace_size(plan, &wb);
+                    if (work) (void)hipFree(work);
+                    work = nullptr;
+                    if (hipMalloc(&work, wb) != hipSuccess) {
+                        qrx_batch_plan_destroy(plan);
+                        rc = QRX_ENOMEM;
+                        break;
+                    }
+                    std::vector<double> ts;
+                    for (int rep = 0; rep <= reps && rc == QRX_OK; ++rep) {
+                        if (hipMemcpyAsync(wk, pristine, sizeof(float) * (size_t)total,
+                                           hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+                            hipEventRecord(ea, stream) != hipSuccess) {
+                            rc = QRX_EHIP;
+                            break;
+                        }
+                        rc = qrx_qr_factor_batched(h, plan, dA, dlda, dR, dldr, work, wb, dst,
+                                                   stream);
+                        if (rc != QRX_OK) break;
+                        float t = 0.f;
+                        if (hipEventRecord(eb, stream) != hipSuccess ||
+                            hipEventSynchronize(eb) != hipSuccess ||
+                            hipEventElapsedTime(&t, ea, eb) != hipSuccess) {
+                            rc = QRX_EHIP;
+                            break;
+                        }
+                        if (rep > 0) ts.push_back(t);
+                    }
+                    qrx_batch_plan_destroy(plan);
+                    if (rc != QRX_OK) break;
+                    ++trials;
+                    std::sort(ts.begin(), ts.end());
+                    const double med = ts[ts.size() / 2];
+                    if (med < best_ms) {
+                        best_ms = med;
+                        best_c = c;
+                        best_t = tl;
+                    }
+                }
+            }
+            release();
+            if (rc != QRX_OK) break;
+            r.panel_width = 32;
+            r.cutoff = best_c;
+            r.gemm_tiles = best_t;
+            r.split_target = 0;
+            r.ms = best_ms;
+            r.trials = trials;
+            r.from_cache = 0;
+            if (cache_path && (rc = qrx_tune_cache_put(cache_path, key, &r))) break;
+        }
+        ms_sum += r.ms;
+        for (int i : idx) {
+            cutoff[i] = r.cutoff;
+            tiles[i] = r.gemm_tiles;
+        }
+    }
     (void)hipEventDestroy(ea);
     (void)hipEventDestroy(eb);
-    release();
     if (rc != QRX_OK) return rc;
     out->panel_width = 32;
-    out->cutoff = best.c;
+    out->cutoff = 0;
     out->gemm_tiles = 0;
     out->split_target = 0;
-    out->ms = best_ms;
+    out->ms = ms_sum;
     out->trials = trials;
-    out->from_cache = 0;
-    if (cache_path) return qrx_tune_cache_put(cache_path, key, out);
+    out->from_cache = all_cached ? 1 : 0;
     return QRX_OK;
 }
 

@@ -157,45 +157,52 @@ def _i64(*v):
     return (C.c_int64 * len(v))(*v)
 
 
-def test_batched_sizes_and_validation(lib, host_handle):
+def test_batched_plan_validation(lib, host_handle):
+    # a batch plan checks sizes and options on the host before any device work
+    # (a host-only handle then stops at the device stage with QRX_EHIP)
     from paper_1912_05508_amd import _lib
-    sz = C.c_size_t()
+    EINVAL, EHIP = _lib.QRX_EINVAL, _lib.QRX_EHIP
     m, n = _i64(100, 64, 300), _i64(40, 64, 256)
-    assert lib.qrx_lls_batched_workspace_size(host_handle, 3, m, n, None, C.byref(sz)) == 0
-    lls_bytes = sz.value
-    assert lib.qrx_qr_batched_workspace_size(host_handle, 3, m, n, None, C.byref(sz)) == 0
-    # the LLS workspace adds working copies and FP64 m-vectors to the QR one
-    assert lls_bytes > sz.value > 4 * (40 * 40 + 64 * 64 + 256 * 256)
-    EINVAL = _lib.QRX_EINVAL
+    plan = C.c_void_p()
+    lo = _lib.lls_opts("bf16")
+    assert lib.qrx_batch_plan_create(host_handle, 3, m, n, None, None, C.byref(lo), 1,
+                                     C.byref(plan)) == EHIP
+    assert lib.qrx_batch_plan_create(host_handle, 3, m, n, None, None, None, 0,
+                                     C.byref(plan)) == EHIP
     for bad_m, bad_n in (((10,), (11,)), ((300,), (257,)), ((5,), (0,))):
-        assert lib.qrx_qr_batched_workspace_size(host_handle, 1, _i64(*bad_m), _i64(*bad_n), None,
-                                                 C.byref(sz)) == EINVAL
-    assert lib.qrx_qr_batched_workspace_size(host_handle, 0, m, n, None, C.byref(sz)) == EINVAL
+        assert lib.qrx_batch_plan_create(host_handle, 1, _i64(*bad_m), _i64(*bad_n), None, None,
+                                         None, 0, C.byref(plan)) == EINVAL
+    assert lib.qrx_batch_plan_create(host_handle, 0, m, n, None, None, None, 0,
+                                     C.byref(plan)) == EINVAL
+    assert lib.qrx_batch_plan_create(host_handle, 3, m, n, None, None, None, 2,
+                                     C.byref(plan)) == EINVAL
     for field, val in (("gemm_prec", 1), ("gemm_prec", 3), ("panel_alg", 1), ("panel_width", 16),
                        ("panel_single_pass", 1), ("node_reorth", 1), ("q_reorth", 1),
-                       ("gemm_tiles", 1), ("split_target", 256)):
-        o = _lib.qr_opts("fp32")
+                       ("gemm_tiles", 2), ("split_target", 256)):
+        o = _lib.lls_opts("fp32")
+        setattr(o.qr, field, val)
+        assert lib.qrx_batch_plan_create(host_handle, 3, m, n, None, None, C.byref(o), 0,
+                                         C.byref(plan)) == EINVAL, field
+    for field, val in (("method", 1), ("use_x0", 1), ("tol", -1.0)):
+        o = _lib.lls_opts("bf16")
         setattr(o, field, val)
-        assert lib.qrx_qr_batched_workspace_size(host_handle, 3, m, n, C.byref(o),
-                                                 C.byref(sz)) == EINVAL, field
-    o = _lib.qr_opts("bf16")
-    assert lib.qrx_qr_batched_workspace_size(host_handle, 3, m, n, C.byref(o), C.byref(sz)) == 0
-    # lda < m, null arrays and CGLS / x0 are rejected before any device work
-    ptrs = (C.c_void_p * 3)(0x1000, 0x1000, 0x1000)
-    info = (_lib.qrx_lls_info * 3)()
-    lo = _lib.lls_opts("bf16")
-    assert lib.qrx_lls_solve_batched(host_handle, 3, m, n, ptrs, _i64(99, 64, 300), ptrs, ptrs,
-                                     None, 0, C.byref(lo), info, None) == EINVAL
-    assert lib.qrx_lls_solve_batched(host_handle, 3, m, n, None, _i64(100, 64, 300), ptrs, ptrs,
-                                     None, 0, C.byref(lo), info, None) == EINVAL
-    for field, val in (("method", 1), ("use_x0", 1)):
-        lo = _lib.lls_opts("bf16")
-        setattr(lo, field, val)
-        assert lib.qrx_lls_solve_batched(host_handle, 3, m, n, ptrs, _i64(100, 64, 300), ptrs,
-                                         ptrs, None, 0, C.byref(lo), info, None) == EINVAL
-    st = (C.c_int * 3)()
-    assert lib.qrx_qr_factor_batched(host_handle, 3, m, n, ptrs, _i64(100, 64, 300), ptrs,
-                                     _i64(40, 63, 256), None, 0, None, st, None) == EINVAL
+        assert lib.qrx_batch_plan_create(host_handle, 3, m, n, None, None, C.byref(o), 1,
+                                         C.byref(plan)) == EINVAL, field
+    # per-problem cutoffs and tiles
+    assert lib.qrx_batch_plan_create(host_handle, 3, m, n, (C.c_int * 3)(64, 0, 32), None,
+                                     None, 0, C.byref(plan)) == EINVAL
+    assert lib.qrx_batch_plan_create(host_handle, 3, m, n, None, (C.c_int * 3)(0, 2, 1),
+                                     None, 0, C.byref(plan)) == EINVAL
+    assert lib.qrx_batch_plan_create(host_handle, 3, m, n, (C.c_int * 3)(64, 128, 32),
+                                     (C.c_int * 3)(0, 1, 1), None, 0, C.byref(plan)) == EHIP
+    sz = C.c_size_t()
+    assert lib.qrx_batch_plan_workspace_size(None, C.byref(sz)) == EINVAL
+    assert lib.qrx_batch_plan_destroy(None) == EINVAL
+    ptrs = C.c_void_p(0x1000)
+    assert lib.qrx_lls_solve_batched(host_handle, None, ptrs, ptrs, ptrs, ptrs, None, 0, ptrs,
+                                     None) == EINVAL
+    assert lib.qrx_qr_factor_batched(host_handle, None, ptrs, ptrs, ptrs, ptrs, None, 0, ptrs,
+                                     None) == EINVAL
 
 
 def test_binding_checks_fire_before_the_library():

@@ -50,6 +50,8 @@ def test_tune_qr_and_cache(qrx, tmp_path):
 
 
 def test_tune_batched(qrx, tmp_path):
+    # per size class (ceil log2 m, ceil log2 n): a cutoff and a product tile for
+    # each class, cached per class; the tuned batch keeps the BF16 accuracy
     import torch
     g = np.random.default_rng(3)
     mats = []
@@ -62,10 +64,20 @@ def test_tune_batched(qrx, tmp_path):
     r = qrx.tune_batched(mats, prec="bf16", cache=cache, reps=2)
     print(r)
     assert all(torch.equal(a, b) for a, b in zip(mats, copies))
-    assert r["cutoff"] in (32, 64, 128, 256) and r["panel_width"] == 32 and r["trials"] >= 2
+    assert all(c in (32, 64, 128, 256) for c in r["cutoff"]) and len(r["cutoff"]) == 24
+    assert all(t in (0, 1) for t in r["tiles"]) and r["trials"] >= 2 and r["from_cache"] == 0
+    classes = {(int(np.ceil(np.log2(a.shape[0]))), int(np.ceil(np.log2(a.shape[1])))) for a in mats}
+    doc = json.load(open(cache))
+    assert len(doc["qrx_tune"]) == len(classes)
+    # problems of one class share their values
+    by_class = {}
+    for a, c, t in zip(mats, r["cutoff"], r["tiles"]):
+        key = (int(np.ceil(np.log2(a.shape[0]))), int(np.ceil(np.log2(a.shape[1]))))
+        assert by_class.setdefault(key, (c, t)) == (c, t)
     r2 = qrx.tune_batched(mats, prec="bf16", cache=cache, reps=2)
-    assert r2["from_cache"] == 1 and r2["cutoff"] == r["cutoff"]
-    Qs, Rs, st = qrx.qr_batched(mats, prec="bf16", cutoff=r["cutoff"])
+    assert r2["from_cache"] == 1 and r2["trials"] == 0
+    assert r2["cutoff"] == r["cutoff"] and r2["tiles"] == r["tiles"]
+    Qs, Rs, st = qrx.qr_batched(mats, prec="bf16", cutoff=r["cutoff"], tiles=r["tiles"])
     torch.cuda.synchronize()
     assert st == [0] * len(mats)
     for A0, Q, R in zip(copies, Qs, Rs):

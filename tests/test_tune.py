@@ -90,6 +90,11 @@ def test_tune_validates_before_device_work(lib, host_handle):
     lda = (C.c_int64 * 2)(100, 60)
     A = (C.c_void_p * 2)(0x1000, 0x2000)
     ob = L.qr_opts("bf16")
-    assert lib.qrx_tune_batched(host_handle, 2, m, n, A, lda, C.byref(ob), 3, None, C.byref(r), None) == L.QRX_EHIP
+    cut, til = (C.c_int * 2)(), (C.c_int * 2)()
+    assert lib.qrx_tune_batched(host_handle, 2, m, n, A, lda, C.byref(ob), 3, None, cut, til,
+                                C.byref(r), None) == L.QRX_EHIP
+    assert lib.qrx_tune_batched(host_handle, 2, m, n, A, lda, C.byref(ob), 3, None, None, til,
+                                C.byref(r), None) == L.QRX_EINVAL
     ob.split_target = 256                     # not a batched option
-    assert lib.qrx_tune_batched(host_handle, 2, m, n, A, lda, C.byref(ob), 3, None, C.byref(r), None) == L.QRX_EINVAL
+    assert lib.qrx_tune_batched(host_handle, 2, m, n, A, lda, C.byref(ob), 3, None, cut, til,
+                                C.byref(r), None) == L.QRX_EINVAL
