@@ -91,8 +91,6 @@ def kernel_bound(name):
         return "mfma", PEAKS["fp32_mfma"], "TFLOP/s"
     if name.startswith("tsqr"):
         return "alu", PEAKS["fp32_valu_nopk"], "TFLOP/s"
-    if name.startswith("gram"):
-        return "alu", PEAKS["fp64"], "TFLOP/s"
     return "hbm", PEAKS["hbm_gbs"], "GB/s"
 
 
@@ -110,6 +108,125 @@ def roofline_of(stats):
                   "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                   "algorithmic_bytes_per_launch": s["bytes"] / max(1, s["launches"]),
                   "avg_launch_ms": avg_ms, "launches": s["launches"]}
+
+
+def qr_fractions(stats, prec):
+    """Both roofline fractions of the QR step: the leaf panels against HBM (16 m w
+    bytes per panel) and against FP64 (their Gram and Q-formation flops), and
+    the trailing products (projection, update, their reduction and operand
+    packing) against the MFMA peak of each product type."""
+    out = {}
+    g = stats.get("gram_panel")
+    if g and g["total_ms"] > 0:
+        sec = g["total_ms"] * 1e-3
+        out["panel_hbm"] = {"achieved_GBs": g["bytes"] / sec / 1e9, "peak_GBs": PEAKS["hbm_gbs"],
+                            "frac": g["bytes"] / sec / 1e9 / PEAKS["hbm_gbs"],
+                            "bytes_model": "16 m w per panel"}
+        out["panel_fp64"] = {"achieved_TFs": g["flops"] / sec / 1e12, "peak_TFs": PEAKS["fp64"],
+                             "frac": g["flops"] / sec / 1e12 / PEAKS["fp64"]}
+    prod = {k: v for k, v in stats.items()
+            if k.startswith(("proj_", "update_", "pack_a2", "pack_q"))}
+    ms = sum(v["total_ms"] for v in prod.values())
+    if ms > 0:
+        lp = {k: v for k, v in prod.items() if k.endswith("_" + prec)}
+        lp_ms = sum(v["total_ms"] for v in lp.values())
+        lp_fl = sum(v["flops"] for v in lp.values())
+        peak = PEAKS.get(prec, PEAKS["fp16"]) if prec != "fp32" else PEAKS["fp32_mfma"]
+        if prec == "fp16x3":
+            peak = PEAKS["fp16"] / 3.0
+        fl = sum(v["flops"] for k, v in prod.items() if k.startswith(("proj_", "update_"))
+                 and k != "proj_reduce")
+        out["products_mfma"] = {
+            "kernels": sorted(prod), "ms_per_step_all": None,
+            "tflops_all": fl / (ms * 1e-3) / 1e12,
+            "tflops_" + prec + "_kernels": lp_fl / (lp_ms * 1e-3) / 1e12 if lp_ms else None,
+            "peak_TFs": peak,
+            "frac_" + prec + "_kernels": (lp_fl / (lp_ms * 1e-3) / 1e12 / peak) if lp_ms else None,
+            "frac_all_vs_" + prec + "_peak": fl / (ms * 1e-3) / 1e12 / peak,
+            "note": "flops 2 m k n2 per projection or update; all = every product, "
+                    "reduction and packing kernel of the step (nodes at or below the "
+                    "cutoff run in FP32)"}
+    return out
+
+
+def phase_table(stats, prefix="krylov:"):
+    """Per-phase time and HBM rate of the persistent Krylov kernel (workgroup 0's
+    clock between grid barriers, so each phase includes one barrier)."""
+    out = {}
+    for k, v in stats.items():
+        if not k.startswith(prefix) or v["launches"] == 0:
+            continue
+        sec = v["total_ms"] * 1e-3
+        out[k[len(prefix):]] = {
+            "calls": v["launches"], "avg_us": 1e3 * v["total_ms"] / v["launches"],
+            "GBs": v["bytes"] / sec / 1e9 if sec > 0 else None,
+            "hbm_frac": v["bytes"] / sec / 1e9 / PEAKS["hbm_gbs"] if sec > 0 else None}
+    return out
+
+
+# Inputs of the large workloads can be generated once in a separate process
+# (--save-inputs) and loaded by a profiled run (--inputs-dir): the generator's
+# device QR then stays out of the profiled process.
+INPUTS = {"dir": None, "save": False}
+
+
+def get_problem(name, m=None, n=None, seed=0):
+    import numpy as np
+    import torch
+    import synth
+    d = INPUTS["dir"]
+    if d:
+        cfg = synth.CONFIGS[name]
+        mm, nn = m or cfg["m"], n or cfg["n"]
+        stem = os.path.join(d, f"{name}_{mm}x{nn}_s{seed}")
+        if not INPUTS["save"] and os.path.exists(stem + "_A.npy"):
+            At = np.load(stem + "_A.npy", mmap_mode="r")      # (n, m): A column-major
+            A = torch.empty((nn, mm), dtype=torch.float32, device="cuda")
+            A.copy_(torch.from_numpy(np.ascontiguousarray(At)))
+            b = None
+            if os.path.exists(stem + "_b.npy"):
+                b = torch.as_tensor(np.load(stem + "_b.npy"), device="cuda")
+            log(f"{name}: loaded {mm} x {nn} from {d}")
+            return A.t(), b
+    p = synth.config_problem(name, device="cuda", m=m, n=n, seed=seed)
+    A = p.A
+    b = None if p.b is None else (p.b if torch.is_tensor(p.b) else torch.as_tensor(p.b, device="cuda"))
+    if d and INPUTS["save"]:
+        os.makedirs(d, exist_ok=True)
+        cfg = synth.CONFIGS[name]
+        mm, nn = m or cfg["m"], n or cfg["n"]
+        stem = os.path.join(d, f"{name}_{mm}x{nn}_s{seed}")
+        np.save(stem + "_A.npy", A.t().contiguous().cpu().numpy())
+        if b is not None:
+            np.save(stem + "_b.npy", b.cpu().numpy())
+        log(f"{name}: saved {mm} x {nn} to {d}")
+    return A, b
+
+
+def c1_bench(h, runs=10):
+    """c1: the plain method at 1024 x 256 (Gaussian A, b = A x* + 1e-6 g): FP32
+    QR with 32-column panels, then LSQR preconditioned by R to eta_F <= 1e-6.
+    Time to solution (call entry to certified x, A and b resident), median of
+    `runs` after one warm-up."""
+    import torch
+    A, b = get_problem("c1")
+    kw = dict(prec="fp32", tol=1e-6, max_iter=20000, cutoff=32, panel_width=32)
+    x, info = h.lstsq(A, b, **kw)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = h.lstsq(A, b, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    times.sort()
+    log(f"c1: {1e3 * times[len(times) // 2]:.3f} ms iters={info['iters']} eta={info['eta_F']:.2e}")
+    return {"workload": "c1: 1024 x 256 Gaussian A (seed 0), b = A x* + 1e-6 g; FP32 QR, "
+                        "32-column panels, LSQR preconditioned by R to eta_F <= 1e-6",
+            "time_to_solution_ms": 1e3 * times[len(times) // 2],
+            "min_ms": 1e3 * times[0], "iters": info["iters"], "eta_F": info["eta_F"],
+            "status": info["status"], "runs": runs}
 
 
 # extra QR options of every leg (--panel-width)
@@ -184,9 +301,7 @@ def lls_bench(h, prec, m_n, repeats, precs=("fp16x3", "fp32", "fp16")):
     import torch
     import synth
     name = "c3"
-    p = synth.config_problem(name, device="cuda") if m_n is None else synth.config_problem(
-        name, device="cuda", m=m_n[0], n=m_n[1])
-    A, b = p.A, torch.as_tensor(p.b, device="cuda") if not torch.is_tensor(p.b) else p.b
+    A, b = get_problem(name) if m_n is None else get_problem(name, m=m_n[0], n=m_n[1])
     out = {}
     for pr in precs:
         reps = 1 if pr == "fp16" else repeats   # FP16 at condition 1e6: thousands of iterations
@@ -282,11 +397,9 @@ def c5_bench(h):
     import torch
     import synth
     t0 = time.perf_counter()
-    p = synth.config_problem("c5", device="cuda")
-    A = p.A
-    b = p.b if torch.is_tensor(p.b) else torch.as_tensor(p.b, device="cuda")
+    A, b = get_problem("c5")
     torch.cuda.synchronize()
-    log(f"c5: generated 262144 x 1024 in {time.perf_counter() - t0:.1f} s")
+    log(f"c5: inputs ready (262144 x 1024) in {time.perf_counter() - t0:.1f} s")
     out = {"workload": "c5: 262144 x 1024, s geometric cond 1e5, columns scaled by 10^U[-4,4], "
                        "b = A x* + 1e-6 relative noise; LSQR right-preconditioned by R to "
                        "eta_F <= 1e-10"}
@@ -305,6 +418,23 @@ def c5_bench(h):
         out[label] = {"time_to_solution_ms": dt * 1e3, "iters": info["iters"],
                       "eta_F": info["eta_F"], "status": info["status"],
                       }
+        if label == "fp16_scaled":
+            # the same solve once more with per-phase timing of the Krylov kernel
+            h.timing_reset()
+            h.timing(True)
+            _, info2 = h.lstsq(A, b, prec=prec, tol=1e-10, max_iter=20000, cutoff=128,
+                               node_reorth=True, **kw, **QR_KW)
+            torch.cuda.synchronize()
+            h.timing(False)
+            st = h.timing_get()
+            ph = phase_table(st)
+            it = max(1, info2["iters"])
+            loop = st.get("krylov_loop", {}).get("total_ms", 0.0)
+            out[label]["krylov"] = {
+                "loop_ms": loop, "ms_per_iteration": loop / it, "phases": ph,
+                "note": "phases timed by workgroup 0 between grid barriers; fused_pass "
+                        "reads A once per iteration for both products"}
+            log(f"c5 {label}: Krylov loop {loop:.1f} ms, {loop / it:.3f} ms/iteration")
     del A
     torch.cuda.empty_cache()
     return out
@@ -384,8 +514,13 @@ def main():
     ap.add_argument("--lls-precs", default="fp16x3,fp32,fp16")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--legs", default="qr,fp32,lls,batched,c5,cpu",
-                    help="comma list of qr (the timed QR step), fp32, lls, batched, c5, cpu; sweep is opt-in")
+    ap.add_argument("--legs", default="qr,fp32,c1,lls,batched,c5,cpu",
+                    help="comma list of qr (the timed QR step), fp32, c1, lls, batched, c5, cpu; "
+                         "sweep is opt-in")
+    ap.add_argument("--inputs-dir", default=None,
+                    help="load the workload inputs from this folder (written by --save-inputs)")
+    ap.add_argument("--save-inputs", action="store_true",
+                    help="generate the inputs of the chosen legs, save them to --inputs-dir, exit")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-problem batched solve")
     ap.add_argument("--sweep-sizes", default="8192x4096,32768x16384",
                     help="sizes of the opt-in 'sweep' leg (the paper's eight matrix types)")
@@ -394,6 +529,8 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+    INPUTS["dir"] = args.inputs_dir
+    INPUTS["save"] = args.save_inputs
     if args.panel_width:
         QR_KW["panel_width"] = args.panel_width
     if args.gpus != 1:
@@ -423,6 +560,17 @@ def main():
         legs.discard("cpu")
     if args.lls:
         legs.add("lls")
+    if args.save_inputs:
+        assert args.inputs_dir, "--save-inputs needs --inputs-dir"
+        if legs & {"qr", "fp32", "cpu"}:
+            get_problem("c2", m=args.m, n=args.n)
+        if "lls" in legs:
+            get_problem("c3")
+        if "c5" in legs:
+            get_problem("c5")
+        if "c1" in legs:
+            get_problem("c1")
+        return
     h = P.Handle()
     m, n = args.m, args.n
     flops = qr_flops(m, n)
@@ -441,8 +589,7 @@ def main():
     if legs & {"qr", "fp32", "cpu"}:
         log(f"generating c2 workload {m} x {n} ...")
         t0 = time.perf_counter()
-        p = synth.config_problem("c2", device="cuda", m=m, n=n)
-        A = p.A
+        A, _ = get_problem("c2", m=m, n=n)
         torch.cuda.synchronize()
         log(f"generated in {time.perf_counter() - t0:.1f} s")
         Q = torch.empty((n, m), dtype=torch.float32, device=dev).t()
@@ -459,6 +606,7 @@ def main():
         acc = accuracy_torch(A, Q, R)
         acc["status"] = status
         _, roof = roofline_of(stats)
+        roof["fractions"] = qr_fractions(stats, args.prec)
         result["value"] = flops / dt_clean / 1e12
         result["ms_per_step"] = dt_clean * 1e3
         result["roofline"] = roof
@@ -475,6 +623,8 @@ def main():
         if result["ms_per_step"]:
             result["fp32_path"]["speedup_fp16_vs_fp32"] = dt32 * 1e3 / result["ms_per_step"]
         log(f"fp32 QR: {dt32*1e3:.3f} ms/step")
+    if "c1" in legs:
+        result["c1"] = c1_bench(h)
     if "lls" in legs:
         mn = tuple(int(v) for v in args.lls_size.split("x")) if args.lls_size else None
         if A is not None:

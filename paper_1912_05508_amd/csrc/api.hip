@@ -30,7 +30,8 @@ struct PendingPhases {
     long long *buf;
     double khz;                   // wall-clock ticks per millisecond
     int64_t m, n, np;
-    int splits_n, splits_t;
+    int splits_n, splits_t, grid;
+    int fused;                    // LSQR iterations take the one-pass products
 };
 
 struct qrx_handle_s {
@@ -303,8 +304,9 @@ int run_panel_core(qrx_handle h, hipStream_t s, int64_t m, float *P, int64_t ld,
         QRX_TRY(launch_gram_panel(s, P, ld, m, w, R, ldr, ws.gram, c.reorth, pack));
         // FP64 work: Gram of P, Q formation, Gram of Q1 (m w(w+1)/2 FMA each); the
         // second Q formation runs only when Q1 is not yet orthonormal, so the
-        // usual case is counted. Traffic (FP32): read P, read P + write Q1.
-        r.end("gram_panel", (c.reorth ? 3.0 : 2.0) * m * (double)w * (w + 1), 12.0 * m * w);
+        // usual case is counted. Traffic model of a leaf panel (FP32): read the
+        // panel, write Q, and read and write it once more, 16 m w bytes.
+        r.end("gram_panel", (c.reorth ? 3.0 : 2.0) * m * (double)w * (w + 1), 16.0 * m * w);
         return QRX_OK;
     }
     constexpr int NB = 32;
@@ -479,8 +481,8 @@ int ensure_pool(qrx_handle h, size_t bytes, void **out) {
 
 // ---- Krylov workspace --------------------------------------------------------
 struct KrWork {
-    double *X, *Xt, *T, *tpart, *u, *r, *rc, *v, *vn, *t, *t2, *d, *z, *vt, *x, *xbest, *q;
-    double *part_n, *part_n2, *part_t, *ssqA, *ssqB;
+    double *X, *Xt, *T, *tpart, *u, *u2, *r, *rc, *v, *vn, *t, *t2, *d, *z, *vt, *x, *xbest, *q;
+    double *part_n, *part_n2, *part_t, *part_f, *ssqA, *ssqB;
     unsigned *bar;
     int splits_n, splits_t;
 };
@@ -495,6 +497,7 @@ void carve_kr(Carve &cv, int64_t m, int64_t n, bool precond, KrWork &k) {
     k.T = cv.take<double>(precond ? kr_trinv_tmp_doubles(np) : 1);
     k.tpart = cv.take<double>(kr_trmv_part_doubles(np));
     k.u = cv.take<double>(m);
+    k.u2 = cv.take<double>(n <= kr_fused_max_n ? m : 1);
     k.r = cv.take<double>(m);
     k.rc = cv.take<double>(m);
     k.q = cv.take<double>(m);
@@ -510,6 +513,8 @@ void carve_kr(Carve &cv, int64_t m, int64_t n, bool precond, KrWork &k) {
     k.part_n = cv.take<double>((size_t)k.splits_n * m);
     k.part_n2 = cv.take<double>((size_t)k.splits_n * m);
     k.part_t = cv.take<double>((size_t)k.splits_t * np);
+    // per-workgroup partials of the one-pass LSQR products (n <= kr_fused_max_n)
+    k.part_f = cv.take<double>(n <= kr_fused_max_n ? (size_t)kr_max_grid * n : 1);
     k.ssqA = cv.take<double>(kr_loop_ssq_doubles(m, np));
     k.ssqB = cv.take<double>(kr_loop_ssq_doubles(m, np));
     k.bar = cv.take<unsigned>(64);
@@ -585,6 +590,7 @@ int enqueue_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const floa
     a.x = k.x;
     a.xbest = k.xbest;
     a.u = k.u;
+    a.u2 = k.u2;
     a.rc = k.rc;
     a.q = k.q;
     a.r = k.r;
@@ -598,6 +604,7 @@ int enqueue_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const floa
     a.pn = k.part_n;
     a.pn2 = k.part_n2;
     a.pt = k.part_t;
+    a.pf = k.part_f;
     a.ssqA = k.ssqA;
     a.ssqB = k.ssqB;
     a.bar = k.bar;
@@ -608,6 +615,8 @@ int enqueue_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const floa
     a.cchunk = (n + k.splits_n - 1) / k.splits_n;
     a.vec = ((((uintptr_t)A) & 15) == 0) && (lda % 4 == 0);
     a.method = cfg.method;
+    // the one-pass products address A and u by 32-bit byte offsets from their starts
+    a.fused = cfg.method == 0 && a.vec && kr_fused_ok(m, n, lda);
     a.max_iter = cfg.max_iter;
     a.tol = cfg.tol;
     a.cscale = compat_scale(m, n, cfg.tol);
@@ -625,7 +634,7 @@ int enqueue_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const floa
         hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device);
         a.prof = buf;
         h->phase_pending.push_back({buf, khz > 0 ? (double)khz : 1e5, m, n, np, k.splits_n,
-                                    k.splits_t});
+                                    k.splits_t, grid, a.fused});
     }
     Rec r(h, s);
     QRX_TRY(kr_loop(s, a, grid));
@@ -1158,7 +1167,7 @@ static int drain_timing(qrx_handle h) {
     static const char *names[KP_COUNT] = {
         "krylov:init", "krylov:certify", "krylov:restart", "krylov:trmv_n", "krylov:gemv_n",
         "krylov:combine_m", "krylov:gemv_t", "krylov:combine_n", "krylov:trmv_t",
-        "krylov:update"};
+        "krylov:update", "krylov:fused_pass"};
     for (auto &p : h->phase_pending) {
         const double mn = (double)p.m * (double)p.n, tri = (double)p.np * (p.np + 1) / 2.0;
         for (int ph = 0; ph < KP_COUNT; ++ph) {
@@ -1171,7 +1180,11 @@ static int drain_timing(qrx_handle h) {
                 case KP_TRMV_N:
                 case KP_TRMV_T: fl = 2.0 * tri; by = 8.0 * tri + 16.0 * p.np; break;
                 case KP_COMBINE_M: by = 8.0 * p.splits_n * p.m + 16.0 * p.m; break;
-                case KP_COMBINE_N: by = 8.0 * p.splits_t * p.n + 8.0 * p.n; break;
+                case KP_COMBINE_N:
+                    by = 8.0 * (p.fused ? p.grid : p.splits_t) * p.n + 8.0 * p.n;
+                    break;
+                // A once, u~_old read and u~ written, one n-vector of partials per workgroup
+                case KP_FUSED: fl = 4.0 * mn; by = 4.0 * mn + 16.0 * p.m + 8.0 * p.grid * p.n; break;
                 default: break;
             }
             qrx_kernel_stat &s = h->stats[names[ph]];

@@ -64,8 +64,9 @@ struct KLoopArgs {
     const double *X, *Xt;           // R^{-1} and its transpose (np x np, ld np); null = identity
     const double *colss, *normA;    // column sums of squares and ||A||_F from the scan
     const int *flags;               // scan / factorisation status flags (bit 0 non-finite, 1 singular)
-    double *x, *xbest, *u, *rc, *q, *r, *v, *vn, *t, *t2, *d, *z, *vt;   // np- or m-vectors
+    double *x, *xbest, *u, *u2, *rc, *q, *r, *v, *vn, *t, *t2, *d, *z, *vt;   // np- or m-vectors
     double *pn, *pn2, *pt;          // GEMV partials: splits_n x m (two), splits_t x np
+    double *pf;                     // one-pass partials of A^T u: n x grid (fused only)
     double *ssqA, *ssqB;            // kr_loop_ssq_doubles(m, np) each
     unsigned *bar;                  // 3 barrier words, zero at launch
     double *x_user;                 // n: receives the best certified iterate
@@ -73,6 +74,7 @@ struct KLoopArgs {
     int splits_n, splits_t;
     int64_t cchunk;                 // GEMV-N columns per split
     int vec;                        // A 16-byte aligned with lda % 4 == 0
+    int fused;                      // LSQR takes A t and A^T u~ in one pass over A (n <= kr_fused_max_n)
     int method, max_iter;
     double tol, cscale;
     long long *prof;                // null, or 2 * KP_COUNT entries: wall-clock ticks and
@@ -81,9 +83,17 @@ struct KLoopArgs {
 // Phases of the persistent Krylov kernel, for its per-phase timing.
 enum {
     KP_INIT = 0, KP_CERTIFY, KP_RESTART, KP_TRMV_N, KP_GEMV_N, KP_COMBINE_M, KP_GEMV_T,
-    KP_COMBINE_N, KP_TRMV_T, KP_UPDATE, KP_COUNT
+    KP_COMBINE_N, KP_TRMV_T, KP_UPDATE, KP_FUSED, KP_COUNT
 };
+// Largest n for the one-pass LSQR products, and the most workgroups a
+// persistent Krylov launch uses (the fused partials are sized for it).
+constexpr int64_t kr_fused_max_n = 1024;
+constexpr int kr_max_grid = 1024;
 size_t kr_loop_ssq_doubles(int64_t m, int64_t np);
+// Whether an m x n matrix with leading dimension lda (16-byte aligned, lda % 4
+// == 0) can take the one-pass LSQR products (n <= kr_fused_max_n and the byte
+// offsets of its loads within 32 bits).
+bool kr_fused_ok(int64_t m, int64_t n, int64_t lda);
 // Workgroups of the persistent launch (co-resident on `device`).
 int kr_loop_grid(int device, int64_t m, int64_t n);
 hipError_t kr_loop(hipStream_t s, const KLoopArgs &a, int grid);

@@ -14,8 +14,9 @@
 //
 // Per LSQR iteration, with X = R^{-1} (FP64, formed once) and its transpose:
 //   t = X v                   (triangular product, one wave per column of X^T)
-//   u~ = A t - alpha u        (GEMV-N partials over column splits, then summed)
-//   z = A^T u~                (GEMV-T partials over row splits, then summed)
+//   u~ = A t - alpha u, z = A^T u~   (n <= 1024: both in one pass over A, partials
+//                             per workgroup, then summed; otherwise a GEMV-N over
+//                             column splits and a GEMV-T over row splits)
 //   v~ = X^T z / beta - beta v, alpha = ||v~||   (one wave per column of X)
 //   Givens step, d = t - (theta/rho) d, x += (phi/rho) d, v = v~ / alpha
 // All sums are taken in a fixed order (deterministic results).
@@ -413,11 +414,413 @@ QRX_DEV void ph_tri(const KLoopArgs &K, const double *M, const double *in, int u
     }
 }
 
+// ---- LSQR's two products with A in one pass -------------------------------------
+// The bidiagonalisation needs A t and then A^T of the result; the second
+// product over a row block needs only that block's entries of the first, so a
+// block of A serves both while it is on chip: A is read once per iteration
+// instead of twice. Blocks are FR rows; groups of FG = 32 / FR consecutive
+// blocks (32 rows, whole 128-byte lines of each column) go to the workgroups in
+// turn (group k to workgroup k mod G), so the blocks in flight across the chip
+// are adjacent in memory. For the workgroup's blocks:
+//   u~[r] = (A t)[r] - coef uo[r]          (written to un; uo is not modified)
+//   ssqA[wg] = sum of u~[r]^2 over its rows
+//   pf[j G + wg] = sum over its rows of A[r, j] u~[r]      (j < n)
+// Wave w takes columns [w cw, (w + 1) cw), cw = FS KC with FS = 64 / FQ column
+// groups per wave; lane (q, g) = (lane % FQ, lane / FQ), FQ = FR / 4, holds rows
+// 4q .. 4q + 3 of its columns w cw + g + FS k, k < KC.
+// The entries go from HBM straight into LDS (16 bytes per lane per load, no
+// registers) through FNBUF buffers: FNBUF - 1 blocks are in flight while one
+// is reduced. (Measured on the 262144 x 1024 workload: 16-row blocks in two
+// buffers stream faster than 8-row blocks in four; the access pattern itself
+// streams at about 5 TB/s without any arithmetic.)
+constexpr int FR = 16;                                  // rows per block
+constexpr int FQ = FR / 4;                              // lanes per column of a block
+constexpr int FS = 64 / FQ;                             // column groups per wave
+constexpr int FG = 32 / FR;                             // blocks per group
+constexpr int FKC = (int)(kr_fused_max_n / (LT / 64) / FS);   // most loads per lane
+constexpr int FNBUF = 2;                                // LDS buffers
+// per wave and buffer: FKC loads x 64 lanes, then the block's FR entries of uo
+// (FR / 2 lanes x 16 bytes)
+constexpr int FWAVE_F4 = FKC * 64 + FR / 2;
+constexpr int FBUF_F4 = 8 * FWAVE_F4;
+constexpr int FUSED_LDS_DOUBLES = FNBUF * FBUF_F4 * 2;
+constexpr int US_DOUBLES = FUSED_LDS_DOUBLES > GT_R ? FUSED_LDS_DOUBLES : GT_R;
+
+typedef __attribute__((address_space(3))) void lvoid;
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+// s_waitcnt with vmcnt(N) alone (expcnt, lgkmcnt at their no-wait maxima);
+// lgkmcnt(0) alone
+template <int N>
+QRX_DEV void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
+QRX_DEV void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+// vmcnt(c) for a count known only at run time (c clamped to 0..15)
+QRX_DEV void wait_vm_rt(int c) {
+    switch (c <= 0 ? 0 : c >= 15 ? 15 : c) {
+        case 0: wait_vm<0>(); break;
+        case 1: wait_vm<1>(); break;
+        case 2: wait_vm<2>(); break;
+        case 3: wait_vm<3>(); break;
+        case 4: wait_vm<4>(); break;
+        case 5: wait_vm<5>(); break;
+        case 6: wait_vm<6>(); break;
+        case 7: wait_vm<7>(); break;
+        case 8: wait_vm<8>(); break;
+        case 9: wait_vm<9>(); break;
+        case 10: wait_vm<10>(); break;
+        case 11: wait_vm<11>(); break;
+        case 12: wait_vm<12>(); break;
+        case 13: wait_vm<13>(); break;
+        case 14: wait_vm<14>(); break;
+        default: wait_vm<15>(); break;
+    }
+}
+
+// LDS byte address of a shared-memory pointer
+QRX_DEV unsigned lds_addr(const void *p) {
+    return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) char *)p;
+}
+
+// A pointer every lane holds alike, in scalar registers
+template <class T>
+QRX_DEV T *uniform_ptr(T *p) {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Buffer descriptor of `bytes` bytes at p (32-bit data format, as the vector
+// memory unit expects of raw buffers); a load past `bytes` returns zeros.
+QRX_DEV __amdgpu_buffer_rsrc_t raw_rsrc(const void *p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+// LDS reads of the one-pass products, written out so that the compiler does
+// not hold them behind the loads of later blocks still in flight (it cannot
+// tell the buffers apart). Each group waits for its own reads before it ends,
+// so no read is left in flight.
+// KC 16-byte reads at a, a + 1024, ...
+template <int KC>
+QRX_DEV void lds_read_cols(unsigned a, f4v (&e)[KC]) {
+    static_assert(KC == 1 || KC == 2 || KC == 4 || KC == 8, "column loads per lane");
+    if constexpr (KC == 1) {
+        asm volatile("ds_read_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(e[0]) : "v"(a) : "memory");
+    } else if constexpr (KC == 2) {
+        asm volatile("ds_read_b128 %0, %2\n\tds_read_b128 %1, %2 offset:1024\n\t"
+                     "s_waitcnt lgkmcnt(0)"
+                     : "=&v"(e[0]), "=&v"(e[1]) : "v"(a) : "memory");
+    } else if constexpr (KC == 4) {
+        asm volatile("ds_read_b128 %0, %4\n\tds_read_b128 %1, %4 offset:1024\n\t"
+                     "ds_read_b128 %2, %4 offset:2048\n\tds_read_b128 %3, %4 offset:3072\n\t"
+                     "s_waitcnt lgkmcnt(0)"
+                     : "=&v"(e[0]), "=&v"(e[1]), "=&v"(e[2]), "=&v"(e[3]) : "v"(a) : "memory");
+    } else {
+        asm volatile("ds_read_b128 %0, %8\n\tds_read_b128 %1, %8 offset:1024\n\t"
+                     "ds_read_b128 %2, %8 offset:2048\n\tds_read_b128 %3, %8 offset:3072\n\t"
+                     "ds_read_b128 %4, %8 offset:4096\n\tds_read_b128 %5, %8 offset:5120\n\t"
+                     "ds_read_b128 %6, %8 offset:6144\n\tds_read_b128 %7, %8 offset:7168\n\t"
+                     "s_waitcnt lgkmcnt(0)"
+                     : "=&v"(e[0]), "=&v"(e[1]), "=&v"(e[2]), "=&v"(e[3]), "=&v"(e[4]),
+                       "=&v"(e[5]), "=&v"(e[6]), "=&v"(e[7])
+                     : "v"(a) : "memory");
+    }
+}
+// four doubles at a and a + 16
+QRX_DEV void lds_read_d4(unsigned a, d2v &lo, d2v &hi) {
+    asm volatile("ds_read_b128 %0, %2\n\tds_read_b128 %1, %2 offset:16\n\ts_waitcnt lgkmcnt(0)"
+                 : "=&v"(lo), "=&v"(hi) : "v"(a) : "memory");
+}
+// four doubles at a + 8 FR w and a + 8 FR w + 16 for w = 0..3 (four waves' row
+// partials of one row quad, as 8 pairs in wave order)
+static_assert(FR == 16, "row partial layout of lds_read_red4");
+QRX_DEV void lds_read_red4(unsigned a, d2v (&v)[8]) {
+    asm volatile("ds_read_b128 %0, %8\n\tds_read_b128 %1, %8 offset:16\n\t"
+                 "ds_read_b128 %2, %8 offset:128\n\tds_read_b128 %3, %8 offset:144\n\t"
+                 "ds_read_b128 %4, %8 offset:256\n\tds_read_b128 %5, %8 offset:272\n\t"
+                 "ds_read_b128 %6, %8 offset:384\n\tds_read_b128 %7, %8 offset:400\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]),
+                   "=&v"(v[5]), "=&v"(v[6]), "=&v"(v[7])
+                 : "v"(a) : "memory");
+}
+
+// KC loads per lane (n <= 8 FS KC). Load k of wave w lands at
+// buf[w FWAVE_F4 + 64 k + lane]; one more load (lanes 0..FR/2-1) brings the
+// block's FR uo entries to buf[w FWAVE_F4 + 64 KC ...], entry r of the block at
+// double index r there. Each wave reads back only its own loads, after its own wait.
+// Columns past n lie past the A descriptor and load zeros (their t entry is
+// zero and their sums are never stored). red: 2 x 8 waves x FR doubles.
+// The host takes this path only when n lda 4 and m 8 are below 2^31 and
+// 8 FS KC lda 4 below 2^32 (kr_fused_ok), so no byte offset below wraps.
+template <int KC>
+QRX_DEV void fused_pass(const KLoopArgs &K, const double *t, double coef, const double *uo,
+                        double *un, double *lds, double *red, unsigned *voffs, double *sh) {
+    const int64_t m = K.m, n = K.n, lda = K.lda;
+    const int G = gridDim.x, wg = blockIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int q = lane % FQ, g = lane / FQ;
+    constexpr int CW = FS * KC;                  // columns per wave
+    float4 *bufs = reinterpret_cast<float4 *>(lds);
+    const int c0 = wv * CW + g;                  // this lane's first column
+    // this lane's entries of t (zero past n)
+    double tv[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) tv[k] = (c0 + FS * k < n) ? t[c0 + FS * k] : 0.0;
+    __syncthreads();                             // the previous phase is done with lds
+    const int64_t nfull = m / FR;                // blocks with all FR rows inside
+    const int64_t nsb = (m + FR - 1) / FR;
+    // the workgroup's i-th block: group wg + (i / FG) G, block i % FG of it
+    auto blk_of = [&](int64_t i) -> int64_t { return FG * (wg + (i / FG) * (int64_t)G) + (i % FG); };
+    int64_t nb = 0;                              // full blocks of this workgroup
+    {
+        const int64_t nq = nfull / FG;           // whole groups of full blocks
+        const int64_t groups = nq > wg ? (nq - wg + G - 1) / G : 0;
+        nb = FG * groups;
+        // leftover full blocks (nfull % FG) start group nq
+        if ((nfull % FG) && nq % G == wg) nb += nfull % FG;
+    }
+    // column loads this wave issues per block (those with a lane inside the
+    // matrix: the lowest column of load k is wv CW + FS k); with the uo load,
+    // nk + 1 load instructions per block and wave
+    int nk = 0;
+    {
+        const int64_t lo = (int64_t)__builtin_amdgcn_readfirstlane(wv) * CW;
+        nk = lo >= n ? 0 : (int)((n - lo + FS - 1) / FS);
+        if (nk > KC) nk = KC;
+    }
+    // byte offset of load k from the block's first row: (4q + (c0 + FS k) lda) 4;
+    // the lane's part, and the uniform part of k
+    const unsigned voff = (unsigned)((4 * q + (int64_t)c0 * lda) * 4);
+    const unsigned kstep = (unsigned)(FS * lda * 4);
+    const float *A = uniform_ptr(K.A);
+    const double *U = uniform_ptr(uo);
+    // slots of columns past n hold zeros in every buffer (whatever a load past
+    // the descriptor leaves there), so their products with t are exact zeros
+#pragma unroll
+    for (int b = 0; b < FNBUF; ++b)
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+            if (c0 + FS * k >= n)
+                bufs[b * FBUF_F4 + wv * FWAVE_F4 + k * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+    voffs[threadIdx.x] = voff;
+    const unsigned avoff = lds_addr(voffs + threadIdx.x);
+    __asm__ volatile("" ::: "memory");
+    wait_lgkm0();
+    auto issue = [&](int64_t sb, int b) {
+        float4 *mine = bufs + b * FBUF_F4 + wv * FWAVE_F4;
+        // A from the block's first row on; columns past n read zeros
+        const __amdgpu_buffer_rsrc_t ra = raw_rsrc(A + sb * FR, (n * lda - sb * FR) * 4);
+        // the previous reads of this buffer are complete (each read group waits
+        // for itself); keep the loads after them in the schedule
+        __asm__ volatile("" ::: "memory");
+        // the lane's offset comes back from LDS here (kept there rather than in a
+        // register across the loop, where it would be spilled to scratch and its
+        // reload would wait for the loads in flight)
+        unsigned vb;
+        asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)"
+                     : "=v"(vb) : "v"(avoff) : "memory");
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+            if (k < nk)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lvoid *)(mine + k * 64), 16,
+                                                         vb + (unsigned)k * kstep, 0, 0, 0);
+        // lanes 0..FR/2-1 bring uo of the block's rows (one load instruction per wave)
+        const __amdgpu_buffer_rsrc_t ru = raw_rsrc(U + sb * FR, FR * 8);
+        if (lane < FR / 2)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ru, (lvoid *)(mine + KC * 64), 16,
+                                                     (unsigned)(16 * lane), 0, 0, 0);
+    };
+    double acc[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+    double ss = 0.0;
+    int par = 0;
+    // one block from buffer b: A t by rows, u~, then A^T u~ into acc
+    auto block = [&](int64_t sb, int b) {
+        const float4 *mine = bufs + b * FBUF_F4 + wv * FWAVE_F4;
+        const unsigned amine = lds_addr(mine + lane);
+        const int64_t r = sb * FR + 4 * q;
+        double p[4] = {0.0, 0.0, 0.0, 0.0};
+        {
+            f4v e[KC];
+            lds_read_cols<KC>(amine, e);
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                p[0] = fma((double)e[k].x, tv[k], p[0]);
+                p[1] = fma((double)e[k].y, tv[k], p[1]);
+                p[2] = fma((double)e[k].z, tv[k], p[2]);
+                p[3] = fma((double)e[k].w, tv[k], p[3]);
+            }
+        }
+        // over the wave's FS column groups (lanes q + FQ g), then over the 8 waves
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int o = FQ; o < 64; o <<= 1) p[i] += __shfl_xor(p[i], o);
+        double *rd = red + par * (8 * FR);
+        if (g == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) rd[wv * FR + 4 * q + i] = p[i];
+        }
+        // one barrier per block (the next block writes the other half of red).
+        // The row partials are LDS writes, complete at lgkmcnt(0); a plain
+        // barrier publishes them without waiting for the loads in flight.
+        __asm__ volatile("" ::: "memory");
+        wait_lgkm0();
+        __builtin_amdgcn_s_barrier();
+        __asm__ volatile("" ::: "memory");
+        par ^= 1;
+        double uu[4];
+        {
+            // wave w's partial of row 4q + i: pair 2 (w % 4) + i / 2, entry i % 2
+            // of the read of waves 4 (w / 4) ..; summed in wave order
+            double sacc[4];
+            const unsigned ar = lds_addr(rd + 4 * q);
+            {
+                d2v pr[8];
+                lds_read_red4(ar, pr);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    sacc[i] = pr[i / 2][i % 2];
+#pragma unroll
+                    for (int w = 1; w < 4; ++w) sacc[i] += pr[2 * w + i / 2][i % 2];
+                }
+            }
+            {
+                d2v pr[8];
+                lds_read_red4(ar + 4 * FR * 8, pr);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) sacc[i] += pr[2 * w + i / 2][i % 2];
+            }
+            d2v u0, u1;
+            lds_read_d4(lds_addr(reinterpret_cast<const double *>(mine + KC * 64) + 4 * q), u0, u1);
+            const double uol[4] = {u0.x, u0.y, u1.x, u1.y};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) uu[i] = (r + i < m) ? fma(-coef, uol[i], sacc[i]) : 0.0;
+        }
+        if (wv == 0 && g == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (r + i < m) {
+                    un[r + i] = uu[i];
+                    ss = fma(uu[i], uu[i], ss);
+                }
+        }
+        {
+            f4v e[KC];
+            lds_read_cols<KC>(amine, e);
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                double v = acc[k];
+                v = fma((double)e[k].x, uu[0], v);
+                v = fma((double)e[k].y, uu[1], v);
+                v = fma((double)e[k].z, uu[2], v);
+                v = fma((double)e[k].w, uu[3], v);
+                acc[k] = v;
+            }
+        }
+    };
+    // full blocks through FNBUF buffers: block i + FNBUF - 1 is issued before
+    // block i is reduced; the wait lets the loads of the blocks issued after
+    // block i stay in flight (nk + 1 instructions each; older stores of wave 0
+    // are waited for as well, which only makes it stricter)
+    for (int64_t i = 0; i < FNBUF - 1 && i < nb; ++i) issue(blk_of(i), (int)i);
+    for (int64_t i = 0; i < nb; ++i) {
+        if (i + FNBUF - 1 < nb) issue(blk_of(i + FNBUF - 1), (int)((i + FNBUF - 1) % FNBUF));
+        const int64_t after = nb - 1 - i < FNBUF - 1 ? nb - 1 - i : FNBUF - 1;
+        wait_vm_rt((int)after * (nk + 1));
+        __asm__ volatile("" ::: "memory");
+        block(blk_of(i), (int)(i % FNBUF));
+    }
+    // the last, partial block (m % FR rows) goes to the workgroup of its group
+    if (nsb > nfull && (nfull / FG) % G == wg) {
+        const int64_t sb = nfull;
+        const int b = (int)(nb % FNBUF);
+        float4 *mine = bufs + b * FBUF_F4 + wv * FWAVE_F4;
+        const int64_t r = sb * FR + 4 * q;
+        wait_vm<0>();
+        __asm__ volatile("" ::: "memory");
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const int64_t c = c0 + FS * k;
+            const float *col = A + (c < n ? c : n - 1) * lda;
+            float4 e;
+            e.x = r < m ? col[r] : 0.f;
+            e.y = r + 1 < m ? col[r + 1] : 0.f;
+            e.z = r + 2 < m ? col[r + 2] : 0.f;
+            e.w = r + 3 < m ? col[r + 3] : 0.f;
+            mine[k * 64 + lane] = e;
+        }
+        if (lane < FQ) {
+            double *ul = reinterpret_cast<double *>(mine + KC * 64) + 4 * lane;
+            const int64_t ru = sb * FR + 4 * lane;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ul[i] = ru + i < m ? U[ru + i] : 0.0;
+        }
+        __asm__ volatile("" ::: "memory");
+        wait_lgkm0();
+        __asm__ volatile("" ::: "memory");
+        block(sb, b);
+    }
+    // acc over the FQ row groups of the wave (lanes FQ g + q, fixed butterfly order)
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+#pragma unroll
+        for (int o = 1; o < FQ; o <<= 1) acc[k] += __shfl_xor(acc[k], o);
+    if (q == 0) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+            if (c0 + FS * k < n) K.pf[(c0 + FS * k) * G + wg] = acc[k];
+    }
+    wg_partial(ss, K.ssqA + wg, sh);
+}
+
+QRX_DEV void ph_fused(const KLoopArgs &K, const double *t, double coef, const double *uo,
+                      double *un, double *lds, double *red, unsigned *voffs, double *sh) {
+    const int64_t kc = (K.n + 8 * FS - 1) / (8 * FS);
+    if (kc <= 1) fused_pass<1>(K, t, coef, uo, un, lds, red, voffs, sh);
+    else if (kc <= 2) fused_pass<2>(K, t, coef, uo, un, lds, red, voffs, sh);
+    else if (kc <= 4) fused_pass<4>(K, t, coef, uo, un, lds, red, voffs, sh);
+    else fused_pass<8>(K, t, coef, uo, un, lds, red, voffs, sh);
+}
+
+
+// z[j] = sum over the workgroups of pf[j G + w] (j < n), one wave per column,
+// lanes over the workgroups in a fixed order.
+QRX_DEV void ph_combine_f(const KLoopArgs &K) {
+    const int64_t n = K.n;
+    const int G = gridDim.x;
+    constexpr int NW = LT / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned nvb = (unsigned)((n + NW - 1) / NW);
+    for (unsigned vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const int64_t j = (int64_t)vb * NW + wv;
+        if (j < n) {
+            const double *pj = K.pf + j * G;
+            double s = 0.0;
+            for (int w = lane; w < G; w += 64) s += pj[w];
+            s = wave_sum_d(s);
+            if (lane == 0) K.z[j] = s;
+        }
+    }
+}
+
 QRX_DEV unsigned tri_vblocks(int64_t np) { return (unsigned)((np / 2 + LT / 64 - 1) / (LT / 64)); }
 
 __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
-    __shared__ double us[GT_R];   // GEMV-T slice; GEMV-N staging
+    __shared__ __align__(16) double us[US_DOUBLES];   // GEMV-T slice; GEMV-N staging; one-pass buffers
     __shared__ double sh[LT];     // reductions
+    __shared__ __align__(16) double fred[2 * 8 * FR];   // row partials of the one-pass products
+    __shared__ unsigned fvoff[LT];                      // lane offsets of the one-pass loads
     __shared__ int sflag;
     __shared__ long long prof[2 * KP_COUNT];   // per-phase ticks and counts (workgroup 0)
     const unsigned G = gridDim.x;
@@ -533,6 +936,7 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
     bool pend = false, p_first = true;
     double *tbuf[2] = {K.t, K.t2};
     int tsel = 0;
+    const double *usrc = K.rc;   // u~_old of the one-pass products
     auto flush_update = [&]() -> bool {
         const double *tp = tbuf[tsel];
         const double pdc = p_dcoef, pxc = p_xcoef;
@@ -559,7 +963,10 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
             beta = rnorm;
             phibar = rnorm;
             const double ib = 1.0 / beta;
-            ph_each(m, [&](int64_t i) { K.u[i] = K.rc[i]; });
+            // the one-pass products read u~_old = rc where it is (certification
+            // rewrites rc only after a later iteration has moved u~ on)
+            if (K.fused) usrc = K.rc;
+            else ph_each(m, [&](int64_t i) { K.u[i] = K.rc[i]; });
             ph_tri(K, K.X, K.z, 1, 1.0, K.ssqA, sh, [&](int64_t c, double val) {
                 const double w = ib * val;
                 K.v[c] = w;
@@ -611,16 +1018,28 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
                 tsel ^= 1;
                 pend = false;
                 if (!bar_ph(KP_TRMV_N)) return fail_sync();
-                ph_gemv_n(K, tn, K.pn, nullptr, 0, us);
-                if (!bar_ph(KP_GEMV_N)) return fail_sync();
-                // u~ = A t - (alpha / beta) u~_old, beta = ||u~||
-                ph_combine_m(K, alpha / beta, K.u, K.u, K.ssqA, sh);
-                if (!bar_ph(KP_COMBINE_M)) return fail_sync();
-                beta = sqrt(wg_sum(K.ssqA, nblk(m), sh));
-                ph_gemv_t(K, K.u, K.pt, us);
-                if (!bar_ph(KP_GEMV_T)) return fail_sync();
-                ph_combine_n(K, nullptr, sh);
-                if (!bar_ph(KP_COMBINE_N)) return fail_sync();
+                if (K.fused) {
+                    // u~ = A t - (alpha / beta) u~_old and z = A^T u~ in one pass
+                    // over A; u~ alternates between two buffers
+                    double *un = (usrc == K.u) ? K.u2 : K.u;
+                    ph_fused(K, tn, alpha / beta, usrc, un, us, fred, fvoff, sh);
+                    usrc = un;
+                    if (!bar_ph(KP_FUSED)) return fail_sync();
+                    beta = sqrt(wg_sum(K.ssqA, G, sh));
+                    ph_combine_f(K);
+                    if (!bar_ph(KP_COMBINE_N)) return fail_sync();
+                } else {
+                    ph_gemv_n(K, tn, K.pn, nullptr, 0, us);
+                    if (!bar_ph(KP_GEMV_N)) return fail_sync();
+                    // u~ = A t - (alpha / beta) u~_old, beta = ||u~||
+                    ph_combine_m(K, alpha / beta, K.u, K.u, K.ssqA, sh);
+                    if (!bar_ph(KP_COMBINE_M)) return fail_sync();
+                    beta = sqrt(wg_sum(K.ssqA, nblk(m), sh));
+                    ph_gemv_t(K, K.u, K.pt, us);
+                    if (!bar_ph(KP_GEMV_T)) return fail_sync();
+                    ph_combine_n(K, nullptr, sh);
+                    if (!bar_ph(KP_COMBINE_N)) return fail_sync();
+                }
                 // v~ = X^T z / beta - beta v; alpha = ||v~||
                 const double ib = 1.0 / beta, bb = beta;
                 ph_tri(K, K.X, K.z, 1, 1.0, K.ssqA, sh, [&](int64_t c, double val) {
@@ -752,11 +1171,21 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
 
 }  // namespace
 
+bool kr_fused_ok(int64_t m, int64_t n, int64_t lda) {
+    if (n < 1 || n > kr_fused_max_n) return false;
+    const int64_t kc = (n + 8 * FS - 1) / (8 * FS);
+    const int64_t KC = kc <= 1 ? 1 : kc <= 2 ? 2 : kc <= 4 ? 4 : 8;
+    return (double)n * (double)lda * 4.0 < 2147483648.0 && (double)m * 8.0 < 2147483648.0 &&
+           (double)(8 * FS * KC) * (double)lda * 4.0 < 4294967296.0;
+}
+
 size_t kr_loop_ssq_doubles(int64_t m, int64_t np) {
     const int64_t len = (m > np ? m : np);
     const int64_t a = (len + LT - 1) / LT;              // elementwise virtual blocks
     const int64_t b = (np + LT / 64 - 1) / (LT / 64);   // per-column (wave) virtual blocks
-    return (size_t)((a > b ? a : b) + 1);
+    int64_t c = a > b ? a : b;
+    if (c < kr_max_grid) c = kr_max_grid;               // one-pass products: one per workgroup
+    return (size_t)(c + 1);
 }
 
 int kr_loop_grid(int device, int64_t m, int64_t n) {
@@ -781,6 +1210,7 @@ int kr_loop_grid(int device, int64_t m, int64_t n) {
         if (v > want) want = v;
     int64_t g = (int64_t)per * cus;
     if (want < g) g = want;
+    if (g > kr_max_grid) g = kr_max_grid;
     return (int)(g < 1 ? 1 : g);
 }
 

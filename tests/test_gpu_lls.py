@@ -263,3 +263,35 @@ def test_c5_full_size_fp16_scaled_vs_bf16_unscaled():
     assert its["fp16"] * 10 < its["bf16"]
     assert its["fp16x3"] <= 10
     h.close()
+
+
+@pytest.mark.parametrize("m,n", [(1000, 300), (2052, 1000), (4100, 129), (6000, 1024),
+                                 (520, 17), (5008, 200), (5012, 250), (1000, 1)])
+def test_one_pass_products_match_two_pass(qrx, m, n):
+    """LSQR forms A t and A^T u~ in one pass over A when n <= 1024 and A is
+    16-byte aligned with lda % 4 == 0; an odd leading dimension takes two GEMV
+    passes instead. The shapes cover n not a multiple of 16 or 128 (waves with
+    partly or wholly unused columns), odd counts of whole 16-row blocks and a
+    partial last block. Both paths certify eta_F <= 1e-10 on the same problem
+    (log-uniform spectrum, condition 1e4, FP16 products); they differ only in
+    summation order, so their iteration counts and solutions agree."""
+    import torch
+    g = np.random.default_rng(m * 7 + n)
+    A = synth.svd_matrix(g, m, n, synth.spectrum("loguniform", n, 1e4, g))
+    _, b = synth.lls_problem(g, A, "rel1e-6")
+    xo, _, _ = L.lls_direct(A, b)
+    res = []
+    for ld in (m, m + 1):
+        x, info = qrx.lstsq(dev(A, ld), dev64(b), prec="fp16", tol=1e-10, max_iter=5000,
+                            cutoff=64)
+        torch.cuda.synchronize()
+        x = host(x)
+        eta = M.eta_F(A, b, x)
+        fe = M.forward_error(x, xo)
+        print(f"{m}x{n} ld={ld}: iters={info['iters']} eta={eta:.2e} fwd={fe:.2e}")
+        assert info["status"] == 0, info
+        assert eta <= 1.05e-10
+        # a backward error of 1e-10 moves x by about kappa * 1e-10 here
+        assert fe <= 1e-4
+        res.append(info)
+    assert abs(res[0]["iters"] - res[1]["iters"]) <= 2 + 0.1 * res[1]["iters"]
