@@ -247,28 +247,11 @@ QRX_DEV void r_product(const RProd &rp, int w, double *A, double *B, int t) {
     }
 }
 
-// The final sweep (DO_Q only) may carry the R product: one extra workgroup,
-// the last, computes it while the others sweep.
+// The sweep of one workgroup over its chunks (see gram_pass_kernel).
 template <int W, bool DO_Q, bool DO_G>
-__global__ __launch_bounds__(GT, 2) void gram_pass_kernel(float *__restrict__ P, int64_t ld,
-                                                       int64_t m, int w, int64_t chunks_per,
-                                                       const double *__restrict__ X,
-                                                       double *__restrict__ part,
-                                                       const int *__restrict__ skip,
-                                                       PanelPack pk, RProd rp) {
-    if (skip && *skip) return;   // the first sweep already gave an orthonormal Q
-    using L = gram::Lds<W>;
-    __shared__ __align__(16) double C[L::C_DOUBLES];
-    __shared__ __align__(16) double Xs[DO_Q ? L::X_DOUBLES : 2];
-    __shared__ __align__(16) double red[DO_G ? L::RED_DOUBLES : 2];
-    const int t = threadIdx.x;
-    if constexpr (DO_Q && !DO_G) {
-        static_assert(L::C_DOUBLES >= W * W && L::X_DOUBLES >= W * W, "R product staging");
-        if (rp.Rfinal && blockIdx.x == gridDim.x - 1) {
-            r_product<W>(rp, w, C, Xs, t);
-            return;
-        }
-    }
+QRX_DEV void pass_body(float *__restrict__ P, int64_t ld, int64_t m, int w, int64_t chunks_per,
+                       const double *__restrict__ X, double *__restrict__ part, const PanelPack &pk,
+                       double *C, double *Xs, double *red, int t) {
     const int64_t nch = (m + CH - 1) / CH;
     const int64_t ch0 = (int64_t)blockIdx.x * chunks_per;
     const int64_t ch1 = (ch0 + chunks_per < nch) ? ch0 + chunks_per : nch;
@@ -292,6 +275,41 @@ __global__ __launch_bounds__(GT, 2) void gram_pass_kernel(float *__restrict__ P,
     }
 }
 
+// The final sweep (DO_Q only) may carry the R product: one extra workgroup,
+// the last, computes it while the others sweep. With skip set the sweep does
+// nothing (an earlier step finished the panel). With nogram set, a DO_Q, DO_G
+// sweep forms Q only (the first Cholesky factor was well conditioned enough
+// that the panel needs no second pass).
+template <int W, bool DO_Q, bool DO_G>
+__global__ __launch_bounds__(GT, 2) void gram_pass_kernel(float *__restrict__ P, int64_t ld,
+                                                       int64_t m, int w, int64_t chunks_per,
+                                                       const double *__restrict__ X,
+                                                       double *__restrict__ part,
+                                                       const int *__restrict__ skip,
+                                                       const int *__restrict__ nogram,
+                                                       PanelPack pk, RProd rp) {
+    if (skip && *skip) return;   // the panel is already finished
+    using L = gram::Lds<W>;
+    __shared__ __align__(16) double C[L::C_DOUBLES];
+    __shared__ __align__(16) double Xs[DO_Q ? L::X_DOUBLES : 2];
+    __shared__ __align__(16) double red[DO_G ? L::RED_DOUBLES : 2];
+    const int t = threadIdx.x;
+    if constexpr (DO_Q && !DO_G) {
+        static_assert(L::C_DOUBLES >= W * W && L::X_DOUBLES >= W * W, "R product staging");
+        if (rp.Rfinal && blockIdx.x == gridDim.x - 1) {
+            r_product<W>(rp, w, C, Xs, t);
+            return;
+        }
+    }
+    if constexpr (DO_Q && DO_G) {
+        if (nogram && *nogram) {
+            pass_body<W, true, false>(P, ld, m, w, chunks_per, X, part, pk, C, Xs, red, t);
+            return;
+        }
+    }
+    pass_body<W, DO_Q, DO_G>(P, ld, m, w, chunks_per, X, part, pk, C, Xs, red, t);
+}
+
 // First level of the Gram reduction when there are many partials: workgroup
 // (x, y) sums entries 64x .. 64x + 63 of the partials y, y + NS, y + 2 NS, ...
 // (NS = gridDim.y) into lvl[y]; its 8 waves sum interleaved subsets and the 8
@@ -299,7 +317,9 @@ __global__ __launch_bounds__(GT, 2) void gram_pass_kernel(float *__restrict__ P,
 // sums reach gram_chol through the kernel boundary, with no fence.
 template <int W>
 __global__ __launch_bounds__(CT) void gram_reduce_kernel(const double *__restrict__ part,
-                                                         int nparts, double *__restrict__ lvl) {
+                                                         int nparts, double *__restrict__ lvl,
+                                                         const int *__restrict__ skip) {
+    if (skip && *skip) return;   // the panel is already finished
     constexpr int NP = W * (W + 1) / 2;
     constexpr int NW = CT / 64;
     constexpr int RB = 8;
@@ -347,6 +367,15 @@ __global__ __launch_bounds__(CT) void gram_reduce_kernel(const double *__restric
 // within tau of the identity in every entry means Q1 is already orthonormal
 // to working accuracy: then R = Rprev is written, *skip = 1 and the final
 // sweep does nothing; otherwise *skip = 0 and the factorisation proceeds.
+//
+// pre: if set and nonzero on entry, the panel is already finished (the kernel
+// returns at once). kflag (first factorisation of a re-orthogonalised panel):
+// the kernel bounds kappa_2(R) by sqrt(||R||_1 ||R||_inf ||R^{-1}||_1
+// ||R^{-1}||_inf); at most ktau, one pass has left Q1 orthonormal to FP32
+// accuracy (Cholesky QR loses orthogonality like kappa^2 u in its arithmetic,
+// here FP64: 2^28 2^-53 < 2^-24), so it writes R into the panel's R block and
+// *kflag = 1 (the second pass then forms Q only and its Gram steps are
+// skipped); otherwise *kflag = 0 and R is left to the second factorisation.
 template <int W>
 __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict__ part, int nparts,
                                                        int w, double *__restrict__ Rout,
@@ -354,7 +383,9 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
                                                        const double *__restrict__ Rprev,
                                                        float *__restrict__ Rfinal, int64_t ldr,
                                                        int *__restrict__ skip, double tau,
-                                                       int prod) {
+                                                       int prod, const int *__restrict__ pre,
+                                                       int *__restrict__ kflag, double ktau) {
+    if (pre && *pre) return;
     constexpr int NP = W * (W + 1) / 2;
     constexpr int LS = W + 1;
     constexpr int NW = CT / 64;
@@ -442,7 +473,56 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
         Rout[idx] = up ? S[i + j * LS] : 0.0;
         Xout[idx] = up ? Xs[i + j * LS] : 0.0;
     }
-    if (!Rfinal || (Rprev && !prod)) return;
+    if (kflag) {
+        // kappa_2(R) <= sqrt(||R||_1 ||R||_inf ||X||_1 ||X||_inf). For each of the
+        // four norms, 8 threads share a column (or row) of W: thread t takes
+        // entries 8 (t % 8) .. + 7 of column or row t / 8 (mod W) of the upper
+        // triangle; sums over the 8, maxima over the columns, then over waves.
+        static_assert(W <= 64 && CT == 512, "thread mapping of the norms");
+        double mx[4];
+#pragma unroll
+        for (int nm = 0; nm < 4; ++nm) {
+            const double *M = (nm & 1) ? Xs : S;     // R or X
+            const bool cols = nm < 2;                // column sums (1-norm) or row sums (inf)
+            const int c = t >> 3, sub = t & 7;       // 64 columns/rows x 8 parts
+            double a = 0.0;
+            if (c < w) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = 8 * sub + e;
+                    // column c: rows k <= c; row c: columns k >= c (k < w)
+                    const bool in = cols ? (k <= c) : (k >= c && k < w);
+                    const double v = in ? (cols ? M[k + c * LS] : M[c + k * LS]) : 0.0;
+                    a += fabs(v);
+                }
+            }
+            a += __shfl_xor(a, 1);
+            a += __shfl_xor(a, 2);
+            a += __shfl_xor(a, 4);
+#pragma unroll
+            for (int o2 = 8; o2 < 64; o2 <<= 1) a = fmax(a, __shfl_xor(a, o2));
+            mx[nm] = a;
+        }
+        __syncthreads();   // Ub is free again after the elimination
+        if (lane == 0) {
+#pragma unroll
+            for (int nm = 0; nm < 4; ++nm) Ub[nm * NW + wv] = mx[nm];
+        }
+        __syncthreads();
+        double nrm[4];
+#pragma unroll
+        for (int nm = 0; nm < 4; ++nm) {
+            nrm[nm] = Ub[nm * NW];
+#pragma unroll
+            for (int q = 1; q < NW; ++q) nrm[nm] = fmax(nrm[nm], Ub[nm * NW + q]);
+        }
+        const double est2 = (nrm[0] * nrm[2]) * (nrm[1] * nrm[3]);   // >= kappa_2^2
+        const bool ok = est2 <= ktau * ktau;                        // NaN: keep the second pass
+        if (t == 0) *kflag = ok ? 1 : 0;
+        if (!ok) return;
+    } else if (!Rfinal || (Rprev && !prod)) {
+        return;
+    }
     if (Rprev) {
         double rv[NQ];
 #pragma unroll
@@ -550,6 +630,10 @@ int *gram_counter(double *ws) { return reinterpret_cast<int *>(ws); }
 // Re-orthogonalisation is skipped when every entry of Q1^T Q1 is within this
 // of the identity (a few FP32 rounding units: a second sweep could not do better).
 constexpr double kSkipTau = 1.0 / (1 << 21);
+// One Cholesky QR pass suffices when the bound of kappa_2(R1) is at most
+// kCondTau (see gram_chol_kernel): kappa^2 u64 = 2^28 2^-53 stays below FP32
+// rounding.
+constexpr double kCondTau = 16384.0;
 
 template <int W>
 static hipError_t gram_go(hipStream_t s, float *P, int64_t ld, int64_t m, int w, float *R,
@@ -571,34 +655,45 @@ static hipError_t gram_go(hipStream_t s, float *P, int64_t ld, int64_t m, int w,
     // partials as gram_chol reads them: the slice sums when there are many
     const double *cpart = ns ? lvl : part;
     const int cparts = ns ? ns : sp.parts;
-    auto reduce = [&] {
+    auto reduce = [&](const int *pre) {
         if (ns)
             hipLaunchKernelGGL(gram_reduce_kernel<W>, dim3(cb, ns), dim3(CT), 0, s,
-                               (const double *)part, sp.parts, lvl);
+                               (const double *)part, sp.parts, lvl, pre);
     };
     const int *noskip = nullptr;
     hipLaunchKernelGGL((gram_pass_kernel<W, false, true>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
-                       m, w, sp.chunks_per, (const double *)nullptr, part, noskip, none, RProd{});
-    reduce();
-    hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(1), dim3(CT), 0, s, cpart, cparts, w, R1, X1,
-                       (const double *)nullptr, reorth ? (float *)nullptr : R, ldr,
-                       (int *)nullptr, 0.0, 0);
+                       m, w, sp.chunks_per, (const double *)nullptr, part, noskip, noskip, none,
+                       RProd{});
+    reduce(noskip);
     if (!reorth) {
+        hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(1), dim3(CT), 0, s, cpart, cparts, w, R1, X1,
+                           (const double *)nullptr, R, ldr, (int *)nullptr, 0.0, 0, noskip,
+                           (int *)nullptr, 0.0);
         hipLaunchKernelGGL((gram_pass_kernel<W, true, false>), dim3(sp.parts), dim3(GT), 0, s, P,
                            ld, m, w, sp.chunks_per, (const double *)X1, (double *)nullptr, noskip,
-                           pk, RProd{});
+                           noskip, pk, RProd{});
         return hipGetLastError();
     }
+    // first factorisation; when R1 is well conditioned it finishes the panel's R
+    // and sets *skip: the second pass then forms Q only, and the second
+    // reduction, factorisation and final sweep do nothing
+    hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(1), dim3(CT), 0, s, cpart, cparts, w, R1, X1,
+                       (const double *)nullptr, R, ldr, (int *)nullptr, 0.0, 0, noskip, skip,
+                       kCondTau);
     hipLaunchKernelGGL((gram_pass_kernel<W, true, true>), dim3(sp.parts), dim3(GT), 0, s, P, ld,
-                       m, w, sp.chunks_per, (const double *)X1, part, noskip, pk, RProd{});
-    reduce();
+                       m, w, sp.chunks_per, (const double *)X1, part, noskip, (const int *)skip,
+                       pk, RProd{});
+    reduce(skip);
+    // second factorisation (G2 of the rounded Q1): within kSkipTau of I it keeps
+    // R = R1 and sets *skip; otherwise R = R2 R1 by one more workgroup of the
+    // final sweep
     hipLaunchKernelGGL(gram_chol_kernel<W>, dim3(1), dim3(CT), 0, s, cpart, cparts, w, R2, X2,
-                       (const double *)R1, R, ldr, skip, kSkipTau, 0);
-    // R = R2 R1 by one more workgroup of the final sweep
+                       (const double *)R1, R, ldr, skip, kSkipTau, 0, (const int *)skip,
+                       (int *)nullptr, 0.0);
     const RProd rp{R2, R1, R, ldr};
     hipLaunchKernelGGL((gram_pass_kernel<W, true, false>), dim3(sp.parts + 1), dim3(GT), 0, s, P,
                        ld, m, w, sp.chunks_per, (const double *)X2, (double *)nullptr,
-                       (const int *)skip, pk, rp);
+                       (const int *)skip, noskip, pk, rp);
     return hipGetLastError();
 }
 
@@ -1114,7 +1209,7 @@ static hipError_t leaf_go(hipStream_t s, float *P, int64_t ld, int64_t m, int w,
     auto reduce = [&] {
         if (ns)
             hipLaunchKernelGGL(gram_reduce_kernel<W>, dim3(cb, ns), dim3(CT), 0, s,
-                               (const double *)part, sp.parts, lvl);
+                               (const double *)part, sp.parts, lvl, (const int *)nullptr);
     };
     PanelPack none = pk;
     none.prec = 0;
