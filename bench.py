@@ -55,10 +55,10 @@ def qr_flops(m, n):
 # are the ones the counters were taken on (SHA-1 below); otherwise null.
 MEASURED_TRAFFIC = {
     "gram_panel": {
-        "bytes_per_launch": 68.98e6,
+        "bytes_per_launch": 51.61e6,
         "profile": "profiles/gram_panel_32768x4096_hbm_traffic.txt",
         "sources": {
-            "paper_1912_05508_amd/csrc/gram.hip": "dd8d77d4fe1c60df3e261bc1b48d21dc4aea2b91",
+            "paper_1912_05508_amd/csrc/gram.hip": "8b3c2b799329a06dfc85c04ac97fbea86252a238",
             "paper_1912_05508_amd/csrc/gram_common.hpp": "099a20c7447911dd6b1d4446ff87022b52f27298",
         },
     },
