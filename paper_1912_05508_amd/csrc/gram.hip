@@ -370,12 +370,13 @@ __global__ __launch_bounds__(CT) void gram_reduce_kernel(const double *__restric
 //
 // pre: if set and nonzero on entry, the panel is already finished (the kernel
 // returns at once). kflag (first factorisation of a re-orthogonalised panel):
-// the kernel bounds kappa_2(R) by sqrt(||R||_1 ||R||_inf ||R^{-1}||_1
-// ||R^{-1}||_inf); at most ktau, one pass has left Q1 orthonormal to FP32
-// accuracy (Cholesky QR loses orthogonality like kappa^2 u in its arithmetic,
-// here FP64: 2^28 2^-53 < 2^-24), so it writes R into the panel's R block and
-// *kflag = 1 (the second pass then forms Q only and its Gram steps are
-// skipped); otherwise *kflag = 0 and R is left to the second factorisation.
+// the kernel bounds kappa_2 of the column-equilibrated factor R D^-1 (D the
+// column norms); at most ktau, one pass has left Q1 orthonormal to FP32
+// accuracy (Cholesky QR with an FP64 Gram matrix loses orthogonality like
+// kappa^2 u64 of the equilibrated panel: 2^28 2^-53 < 2^-24), so it writes R
+// into the panel's R block and *kflag = 1 (the second pass then forms Q only
+// and its Gram steps are skipped); otherwise *kflag = 0 and R is left to the
+// second factorisation.
 template <int W>
 __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict__ part, int nparts,
                                                        int w, double *__restrict__ Rout,
@@ -474,16 +475,41 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
         Xout[idx] = up ? Xs[i + j * LS] : 0.0;
     }
     if (kflag) {
-        // kappa_2(R) <= sqrt(||R||_1 ||R||_inf ||X||_1 ||X||_inf). For each of the
-        // four norms, 8 threads share a column (or row) of W: thread t takes
-        // entries 8 (t % 8) .. + 7 of column or row t / 8 (mod W) of the upper
-        // triangle; sums over the 8, maxima over the columns, then over waves.
+        // kappa_2 of the column-equilibrated factor, R D^-1 with D the column
+        // norms of R (= those of the panel): at most sqrt(||R D^-1||_1
+        // ||R D^-1||_inf ||D X||_1 ||D X||_inf). Cholesky's rounding errors are
+        // relative to the columns' scale, so this, not kappa(R) itself, governs
+        // the orthogonality of one pass. For each of the four norms, 8 threads
+        // share a column (or row) of W: thread t takes entries 8 (t % 8) .. + 7
+        // of column or row t / 8 of the upper triangle; sums over the 8, maxima
+        // over the columns, then over the waves.
         static_assert(W <= 64 && CT == 512, "thread mapping of the norms");
+        static_assert(U >= 4 * NW + W, "Ub holds the wave maxima and the column norms");
+        double *dn = Ub + 4 * NW;                    // column norms of R
+        __syncthreads();                             // Ub is free again after the elimination
+        {
+            const int c = t >> 3, sub = t & 7;
+            double a = 0.0;
+            if (c < w) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = 8 * sub + e;
+                    const double v = k <= c ? S[k + c * LS] : 0.0;
+                    a = fma(v, v, a);
+                }
+            }
+            a += __shfl_xor(a, 1);
+            a += __shfl_xor(a, 2);
+            a += __shfl_xor(a, 4);
+            if (c < w && sub == 0) dn[c] = sqrt(a);
+        }
+        __syncthreads();
         double mx[4];
 #pragma unroll
         for (int nm = 0; nm < 4; ++nm) {
-            const double *M = (nm & 1) ? Xs : S;     // R or X
+            const bool isx = nm & 1;                 // R D^-1 or D X
             const bool cols = nm < 2;                // column sums (1-norm) or row sums (inf)
+            const double *M = isx ? Xs : S;
             const int c = t >> 3, sub = t & 7;       // 64 columns/rows x 8 parts
             double a = 0.0;
             if (c < w) {
@@ -492,8 +518,10 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
                     const int k = 8 * sub + e;
                     // column c: rows k <= c; row c: columns k >= c (k < w)
                     const bool in = cols ? (k <= c) : (k >= c && k < w);
-                    const double v = in ? (cols ? M[k + c * LS] : M[c + k * LS]) : 0.0;
-                    a += fabs(v);
+                    const int i = cols ? k : c, j = cols ? c : k;   // entry (i, j)
+                    const double v = in ? M[i + j * LS] : 0.0;
+                    // (R D^-1)_ij = R_ij / d_j, (D X)_ij = d_i X_ij
+                    a += in ? (isx ? fabs(v) * dn[i] : fabs(v) / dn[j]) : 0.0;
                 }
             }
             a += __shfl_xor(a, 1);
@@ -503,7 +531,7 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
             for (int o2 = 8; o2 < 64; o2 <<= 1) a = fmax(a, __shfl_xor(a, o2));
             mx[nm] = a;
         }
-        __syncthreads();   // Ub is free again after the elimination
+        __syncthreads();
         if (lane == 0) {
 #pragma unroll
             for (int nm = 0; nm < 4; ++nm) Ub[nm * NW + wv] = mx[nm];
@@ -516,7 +544,7 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
 #pragma unroll
             for (int q = 1; q < NW; ++q) nrm[nm] = fmax(nrm[nm], Ub[nm * NW + q]);
         }
-        const double est2 = (nrm[0] * nrm[2]) * (nrm[1] * nrm[3]);   // >= kappa_2^2
+        const double est2 = (nrm[0] * nrm[2]) * (nrm[1] * nrm[3]);   // >= kappa_2(R D^-1)^2
         const bool ok = est2 <= ktau * ktau;                        // NaN: keep the second pass
         if (t == 0) *kflag = ok ? 1 : 0;
         if (!ok) return;
