@@ -194,8 +194,62 @@ QRX_DEV void wg_update(int64_t m, int k, int n2, const float *Q1, float *A2, int
     __syncthreads();
 }
 
+// Second pass of the in-workgroup panel skipped when the bound of kappa_2 of the
+// column-equilibrated first factor is at most this (as in the single-problem
+// panel: one Cholesky-QR pass with an FP64 Gram matrix then leaves Q at the
+// FP32 rounding level).
+constexpr double kBCondTau = 16384.0;
+
+// The square of sqrt(||R D^-1||_1 ||R D^-1||_inf ||D X||_1 ||D X||_inf) >=
+// kappa_2(R D^-1), D the column norms of R: R (upper triangular) in S and
+// X = R^{-1} in Xc, column-major with stride 33, w <= 32 columns. Eight threads
+// share a column (or row), four entries each. T: 36 doubles of scratch. The
+// result is uniform.
+QRX_DEV double equil_kappa2_32(const double *S, const double *Xc, int w, double *T, int t) {
+    const int c = t >> 3, sub = t & 7;
+    double a = 0.0;
+    if (c < w) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * sub + e;
+            const double v = k <= c ? S[k + c * 33] : 0.0;
+            a = fma(v, v, a);
+        }
+    }
+    a += __shfl_xor(a, 1);
+    a += __shfl_xor(a, 2);
+    a += __shfl_xor(a, 4);
+    double *dn = T + 4;                           // T[0..3]: bmax scratch
+    __syncthreads();
+    if (c < w && sub == 0) dn[c] = sqrt(a);
+    __syncthreads();
+    double nr[4];
+#pragma unroll
+    for (int nm = 0; nm < 4; ++nm) {
+        const bool isx = nm & 1, cols = nm < 2;
+        const double *M = isx ? Xc : S;
+        double s = 0.0;
+        if (c < w) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = 4 * sub + e;
+                const bool in = cols ? (k <= c) : (k >= c && k < w);
+                const int i = cols ? k : c, j = cols ? c : k;
+                const double v = in ? fabs(M[i + j * 33]) : 0.0;
+                s += in ? (isx ? v * dn[i] : v / dn[j]) : 0.0;
+            }
+        }
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 4);
+        nr[nm] = bmax(s, T);
+    }
+    return (nr[0] * nr[2]) * (nr[1] * nr[3]);
+}
+
 // ---------------------------------------------------------------------------
-// In-workgroup panel: Cholesky QR twice with FP64 Gram matrices (w <= 32).
+// In-workgroup panel: Cholesky QR with FP64 Gram matrices (w <= 32), a second
+// pass when the first factor is not well conditioned enough.
 // ---------------------------------------------------------------------------
 QRX_DEV void wg_panel(float *P, int64_t ld, int64_t m, int w, float *Rb, int64_t ldr, double *lds,
                       int t) {
@@ -236,6 +290,17 @@ QRX_DEV void wg_panel(float *P, int64_t ld, int64_t m, int w, float *Rb, int64_t
     for (int idx = t; idx < 32 * 32; idx += BT) {
         const int i = idx % 32, j = idx / 32;
         R1[idx] = (i <= j && j < w) ? S[i + j * 33] : 0.0;
+    }
+    // one pass suffices: R = R1, Q = fl32(P X1)
+    const double est2 = equil_kappa2_32(S, Xc, w, T, t);
+    if (est2 <= kBCondTau * kBCondTau) {   // NaN compares false: second pass
+        for (int idx = t; idx < 32 * 32; idx += BT) {
+            const int i = idx % 32, j = idx / 32;
+            if (i < w && j < w) Rb[i + (int64_t)j * ldr] = (float)R1[idx];
+        }
+        gram::sweep<32, true, false>(P, ld, m, w, 0, nch, Xs, C, acc, t);
+        __syncthreads();
+        return;
     }
     zero();
     gram::sweep<32, true, true>(P, ld, m, w, 0, nch, Xs, C, acc, t);
