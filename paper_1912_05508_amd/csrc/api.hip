@@ -481,7 +481,7 @@ int ensure_pool(qrx_handle h, size_t bytes, void **out) {
 
 // ---- Krylov workspace --------------------------------------------------------
 struct KrWork {
-    double *X, *Xt, *T, *tpart, *u, *u2, *r, *rc, *v, *vn, *t, *t2, *d, *z, *vt, *x, *xbest, *q;
+    double *X, *Xt, *T, *tpart, *u, *u2, *r, *rc, *v, *vn, *t, *t2, *d, *z, *vt, *x, *xlo, *xbest, *q;
     double *part_n, *part_n2, *part_t, *part_f, *ssqA, *ssqB;
     unsigned *bar;
     int splits_n, splits_t;
@@ -509,6 +509,7 @@ void carve_kr(Carve &cv, int64_t m, int64_t n, bool precond, KrWork &k) {
     k.z = cv.take<double>(np);
     k.vt = cv.take<double>(np);
     k.x = cv.take<double>(np);
+    k.xlo = cv.take<double>(np);
     k.xbest = cv.take<double>(np);
     k.part_n = cv.take<double>((size_t)k.splits_n * m);
     k.part_n2 = cv.take<double>((size_t)k.splits_n * m);
@@ -559,7 +560,7 @@ int enqueue_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const floa
         r.end("trinv", 2.0 * (double)np * np * np / 3.0, 8.0 * np * np + 16.0 * np * np);
     }
     // the padded tails [n, np) of every n-vector must stay exactly zero
-    for (double *vec : {k.x, k.xbest, k.v, k.vn, k.t, k.t2, k.d, k.z, k.vt})
+    for (double *vec : {k.x, k.xlo, k.xbest, k.v, k.vn, k.t, k.t2, k.d, k.z, k.vt})
         QRX_TRY(kr_zero(s, np, vec));
     if (use_x0) {
         QRX_TRY(hipMemcpyAsync(k.x, x_user, n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -589,6 +590,7 @@ int enqueue_krylov(qrx_handle h, hipStream_t s, int64_t m, int64_t n, const floa
     a.flags = ws.flags;
     a.x = k.x;
     a.xbest = k.xbest;
+    a.xlo = k.xlo;
     a.u = k.u;
     a.u2 = k.u2;
     a.rc = k.rc;

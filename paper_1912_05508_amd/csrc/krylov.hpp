@@ -65,6 +65,8 @@ struct KLoopArgs {
     const double *colss, *normA;    // column sums of squares and ||A||_F from the scan
     const int *flags;               // scan / factorisation status flags (bit 0 non-finite, 1 singular)
     double *x, *xbest, *u, *u2, *rc, *q, *r, *v, *vn, *t, *t2, *d, *z, *vt;   // np- or m-vectors
+    double *xlo;                    // np: low parts of x (x + xlo accumulates the updates of
+                                    // one restart in double-double; zero at each restart)
     double *pn, *pn2, *pt;          // GEMV partials: splits_n x m (two), splits_t x np
     double *pf;                     // one-pass partials of A^T u: n x grid (fused only)
     double *ssqA, *ssqB;            // kr_loop_ssq_doubles(m, np) each

@@ -369,37 +369,99 @@ QRX_DEV double col_dot(const double *col, const double *in, int64_t i0, int64_t 
     return wave_sum_d(acc);
 }
 
-// Triangular products with one wave per output entry; each wave takes the pair
-// (c, np-1-c) so the work per wave is balanced. Virtual block = one pair per wave.
+// x += a * d for entry j, accumulated in double-double (x, xlo): over the
+// thousands of updates of a restart, rounding x after each one would add a
+// random walk of about sqrt(updates) * u |x| to it, which for a strongly
+// column-scaled A already exceeds the 1e-10 backward-error target; the pair
+// keeps x itself the rounded sum. The residual of a restart is that of x,
+// so xlo is dropped (zeroed) when the next restart begins.
+QRX_DEV void x_update(const KLoopArgs &K, int64_t j, double a, double d) {
+    double hi = K.x[j], lo = K.xlo[j];
+    dd_add_prod(hi, lo, a, d);
+    K.x[j] = hi;
+    K.xlo[j] = lo;
+}
+
+// Triangular products. Output entries come in pairs (c, np-1-c), whose two
+// columns have np + 1 entries in all, so that every pair is the same work; a
+// pair is split over WP waves of one workgroup (WP = 1..8, as many as the
+// grid's waves allow), wave s taking entries [s T/WP, (s+1) T/WP) of the two
+// columns laid end to end (T = np + 1), and the WP partial sums are added in
+// wave order (fixed reduction order). Virtual block = 8 / WP pairs.
 //   upper = 1: out[c] = sum_{i <= c} M[i, c] in[i]   (M = X: out = X^T in)
 //   upper = 0: out[c] = sum_{i >= c} M[i, c] in[i]   (M = X^T: out = X in)
-// each times `scale`. M == null stands for the identity. The epilogue receives (c, value) on lane 0
-// and returns the entry's contribution to the virtual block's ssq partial.
+// each times `scale`. M == null stands for the identity. The epilogue receives
+// (c, value) on one lane and returns the entry's contribution to the virtual
+// block's ssq partial.
+QRX_DEV int tri_waves_per_pair(int64_t np, unsigned G) {
+    const int64_t npairs = np / 2;
+    int wp = LT / 64;
+    while (wp > 1 && (int64_t)wp * npairs > (LT / 64) * (int64_t)G) wp >>= 1;
+    return wp;
+}
+QRX_DEV unsigned tri_vblocks(int64_t np, unsigned G) {
+    const int pw = (LT / 64) / tri_waves_per_pair(np, G);
+    return (unsigned)((np / 2 + pw - 1) / pw);
+}
+
 template <class E>
 QRX_DEV void ph_tri(const KLoopArgs &K, const double *M, const double *in, int upper,
                     double scale, double *ssq, double *sh, E epi) {
     const int64_t np = K.np;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     constexpr int NW = LT / 64;
+    const int wp = __builtin_amdgcn_readfirstlane(tri_waves_per_pair(np, gridDim.x));
+    const int pw = NW / wp;
+    const int pp = wv / wp, sg = wv % wp;        // pair within the block, segment of the pair
     const int64_t npairs = np / 2;
-    const int64_t nvb = (npairs + NW - 1) / NW;
+    const int64_t nvb = (npairs + pw - 1) / pw;
+    const int64_t T = np + 1;
+    double *part = sh + NW;                      // [pair][segment][2]
     for (int64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-        const int64_t p = vb * NW + wv;
-        double e2 = 0.0;
-        if (p < npairs) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int64_t c = h == 0 ? p : np - 1 - p;
-                double val;
-                if (M == nullptr) {
-                    val = in[c];
-                } else {
-                    const double *col = M + c * np;
-                    val = upper ? col_dot(col, in, 0, c + 1, lane) : col_dot(col, in, c, np, lane);
+        const int64_t p = vb * pw + pp;
+        const bool act = p < npairs;
+        const int64_t c0 = p, c1 = np - 1 - p;
+        // concatenated entries [0, L0) lie in column c0, [L0, T) in column c1
+        const int64_t L0 = upper ? c0 + 1 : np - c0;
+        const int64_t s0 = sg * T / wp, s1 = (sg + 1) * T / wp;
+        double v0 = 0.0, v1 = 0.0;
+        if (act) {
+            if (M == nullptr) {
+                if (sg == 0) {
+                    v0 = in[c0];
+                    v1 = in[c1];
                 }
-                val *= scale;
-                if (lane == 0) e2 += epi(c, val);
+            } else {
+                // the segment's share of column c0 (first stored row r0) ...
+                const int64_t a0 = s0 < L0 ? s0 : L0, b0 = s1 < L0 ? s1 : L0;
+                const int64_t r0 = upper ? 0 : c0;
+                if (a0 < b0) v0 = col_dot(M + c0 * np, in, r0 + a0, r0 + b0, lane);
+                // ... and of column c1
+                const int64_t a1 = (s0 > L0 ? s0 : L0) - L0, b1 = (s1 > L0 ? s1 : L0) - L0;
+                const int64_t r1 = upper ? 0 : c1;
+                if (a1 < b1) v1 = col_dot(M + c1 * np, in, r1 + a1, r1 + b1, lane);
             }
+        }
+        if (wp > 1) {
+            if (lane == 0) {
+                part[(pp * wp + sg) * 2] = v0;
+                part[(pp * wp + sg) * 2 + 1] = v1;
+            }
+            __syncthreads();
+            if (sg == 0) {
+                v0 = part[pp * wp * 2];
+                v1 = part[pp * wp * 2 + 1];
+                for (int q = 1; q < wp; ++q) {
+                    v0 += part[(pp * wp + q) * 2];
+                    v1 += part[(pp * wp + q) * 2 + 1];
+                }
+            }
+            __syncthreads();
+        }
+        double e2 = 0.0;
+        if (act && sg == 0 && lane == 0) {
+            e2 += epi(c0, v0 * scale);
+            e2 += epi(c1, v1 * scale);
         }
         if (ssq) {
             if (lane == 0) sh[wv] = e2;
@@ -814,8 +876,6 @@ QRX_DEV void ph_combine_f(const KLoopArgs &K) {
     }
 }
 
-QRX_DEV unsigned tri_vblocks(int64_t np) { return (unsigned)((np / 2 + LT / 64 - 1) / (LT / 64)); }
-
 __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
     __shared__ __align__(16) double us[US_DOUBLES];   // GEMV-T slice; GEMV-N staging; one-pass buffers
     __shared__ double sh[LT];     // reductions
@@ -944,14 +1004,14 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
         ph_each(np, [&](int64_t j) {
             const double dj = pfst ? tp[j] : fma(-pdc, K.d[j], tp[j]);
             K.d[j] = dj;
-            K.x[j] = fma(pxc, dj, K.x[j]);
+            x_update(K, j, pxc, dj);
         });
         pend = false;
         return bar_ph(KP_UPDATE);
     };
     // CGLS state
     double gamma = 0.0;
-    const unsigned ntri = tri_vblocks(np);
+    const unsigned ntri = tri_vblocks(np, G);
     const int64_t mx_mn = m > n ? m : n;
 
     while (best > tol && iters < K.max_iter) {
@@ -970,6 +1030,7 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
             ph_tri(K, K.X, K.z, 1, 1.0, K.ssqA, sh, [&](int64_t c, double val) {
                 const double w = ib * val;
                 K.v[c] = w;
+                K.xlo[c] = 0.0;
                 return w * w;
             });
             if (!bar_ph(KP_RESTART)) return fail_sync();
@@ -983,6 +1044,7 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
             ph_tri(K, K.X, K.z, 1, 1.0, K.ssqA, sh, [&](int64_t c, double val) {
                 K.vt[c] = val;
                 K.v[c] = val;
+                K.xlo[c] = 0.0;
                 return val * val;
             });
             if (!bar_ph(KP_RESTART)) return fail_sync();
@@ -1008,7 +1070,7 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
                     if (pd) {
                         const double dj = pfst ? tp[j] : fma(-pdc, K.d[j], tp[j]);
                         K.d[j] = dj;
-                        K.x[j] = fma(pxc, dj, K.x[j]);
+                        x_update(K, j, pxc, dj);
                     }
                 });
                 ph_tri(K, K.Xt, K.v, 0, ia, nullptr, sh, [&](int64_t c, double val) {
@@ -1082,7 +1144,7 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
                     const unsigned nvb = nblk(mx_mn);
                     for (unsigned vb = blockIdx.x; vb < nvb; vb += G) {
                         const int64_t i = (int64_t)vb * LT + threadIdx.x;
-                        if (i < n) K.x[i] = fma(a, K.t[i], K.x[i]);
+                        if (i < n) x_update(K, i, a, K.t[i]);
                         double v2 = 0.0;
                         if (i < m) {
                             const double v = fma(-a, K.q[i], K.r[i]);
@@ -1142,7 +1204,10 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
         if (score < best) {
             keep_if_better();
         } else {
-            ph_each(np, [&](int64_t j) { K.x[j] = K.xbest[j]; });
+            ph_each(np, [&](int64_t j) {
+                K.x[j] = K.xbest[j];
+                K.xlo[j] = 0.0;
+            });
             if (!bar_ph(KP_CERTIFY)) return fail_sync();
             if (!certify()) return fail_sync();
         }
@@ -1182,7 +1247,7 @@ bool kr_fused_ok(int64_t m, int64_t n, int64_t lda) {
 size_t kr_loop_ssq_doubles(int64_t m, int64_t np) {
     const int64_t len = (m > np ? m : np);
     const int64_t a = (len + LT - 1) / LT;              // elementwise virtual blocks
-    const int64_t b = (np + LT / 64 - 1) / (LT / 64);   // per-column (wave) virtual blocks
+    const int64_t b = np / 2 + 1;                        // triangular products: up to one per column pair
     int64_t c = a > b ? a : b;
     if (c < kr_max_grid) c = kr_max_grid;               // one-pass products: one per workgroup
     return (size_t)(c + 1);
