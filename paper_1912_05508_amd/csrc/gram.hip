@@ -371,12 +371,13 @@ __global__ __launch_bounds__(CT) void gram_reduce_kernel(const double *__restric
 // pre: if set and nonzero on entry, the panel is already finished (the kernel
 // returns at once). kflag (first factorisation of a re-orthogonalised panel):
 // the kernel bounds kappa_2 of the column-equilibrated factor R D^-1 (D the
-// column norms); at most ktau, one pass has left Q1 orthonormal to FP32
-// accuracy (Cholesky QR with an FP64 Gram matrix loses orthogonality like
-// kappa^2 u64 of the equilibrated panel: 2^28 2^-53 < 2^-24), so it writes R
-// into the panel's R block and *kflag = 1 (the second pass then forms Q only
-// and its Gram steps are skipped); otherwise *kflag = 0 and R is left to the
-// second factorisation.
+// column norms of R, i.e. sqrt of the diagonal of G); at most ktau, one pass
+// has left Q1 orthonormal to FP32 accuracy (Cholesky QR with an FP64 Gram
+// matrix loses orthogonality like kappa^2 u64 of the equilibrated panel:
+// 2^28 2^-53 < 2^-24), so it writes R into the panel's R block and *kflag = 1
+// (the second pass then forms Q only and its Gram steps are skipped);
+// otherwise *kflag = 0 and R is left to the second factorisation.
+// nparts is at most kDirectParts (the callers reduce more partials first).
 template <int W>
 __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict__ part, int nparts,
                                                        int w, double *__restrict__ Rout,
@@ -390,13 +391,13 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
     constexpr int NP = W * (W + 1) / 2;
     constexpr int LS = W + 1;
     constexpr int NW = CT / 64;
-    constexpr int PB = 4;                        // partials per round (PB * NQ loads in flight)
     constexpr int NQ = (W * W + CT - 1) / CT;   // entries of a W x W matrix per thread
-    constexpr int TP = (W == 64 && CT == 512) ? 2 * (8 * W + 4) : 4 * W + 4;   // pivot rows
+    constexpr int TP = (W == 64 && CT == 512) ? gram::kCholT64 : 4 * W + 4;   // pivot rows
     constexpr int U = (NW > TP) ? NW : TP;      // wave maxima, then pivot rows
     __shared__ double S[W * LS];       // G, then R (upper)
     __shared__ double Xs[W * LS];      // R^{-1}, then Rprev
-    __shared__ double Ub[U];           // wave maxima, then pivot rows of the elimination
+    __shared__ __align__(16) double Ub[U];   // wave maxima, then pivot rows of the elimination
+    __shared__ double dnb[W];          // column norms of the factor (single-pass bound)
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
     double gv[NQ];
@@ -408,23 +409,18 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
         off[q] = (idx < W * W && i <= j && j < w) ? upk(i, j) : -1;
     }
     {
-        int p = 0;
-        for (; p + PB <= nparts; p += PB) {
-            double v[PB][NQ];
+        // every load in flight at once (one round trip to memory), then the
+        // sums in partial order
+        double v[kDirectParts][NQ];
 #pragma unroll
-            for (int b = 0; b < PB; ++b)
-#pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    v[b][q] = off[q] >= 0 ? part[(int64_t)(p + b) * NP + off[q]] : 0.0;
-#pragma unroll
-            for (int b = 0; b < PB; ++b)
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) gv[q] += v[b][q];
-        }
-        for (; p < nparts; ++p)
+        for (int b = 0; b < kDirectParts; ++b)
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
-                if (off[q] >= 0) gv[q] += part[(int64_t)p * NP + off[q]];
+                v[b][q] = (b < nparts && off[q] >= 0) ? part[(int64_t)b * NP + off[q]] : 0.0;
+#pragma unroll
+        for (int b = 0; b < kDirectParts; ++b)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) gv[q] += v[b][q];
     }
 
     double dev = 0.0;
@@ -434,6 +430,7 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
             const int idx = t + q * CT, i = idx % W, j = idx / W;
             if (idx >= W * W) continue;
             S[i + j * LS] = gv[q];
+            if (i == j && j < w) dnb[i] = sqrt(gv[q]);   // column norms of R
             if (i <= j && j < w) {
                 const double e2 = fabs(gv[q] - (i == j ? 1.0 : 0.0));
                 dev = fmax(dev, (e2 == e2) ? e2 : 1e300);   // a NaN entry never passes
@@ -475,76 +472,28 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
         Xout[idx] = up ? Xs[i + j * LS] : 0.0;
     }
     if (kflag) {
-        // kappa_2 of the column-equilibrated factor, R D^-1 with D the column
-        // norms of R (= those of the panel): at most sqrt(||R D^-1||_1
-        // ||R D^-1||_inf ||D X||_1 ||D X||_inf). Cholesky's rounding errors are
+        // kappa_2(R D^-1) <= ||R D^-1||_F ||D X||_F = sqrt(w) ||D X||_F, the
+        // columns of R D^-1 having unit norm. Cholesky's rounding errors are
         // relative to the columns' scale, so this, not kappa(R) itself, governs
-        // the orthogonality of one pass. For each of the four norms, 8 threads
-        // share a column (or row) of W: thread t takes entries 8 (t % 8) .. + 7
-        // of column or row t / 8 of the upper triangle; sums over the 8, maxima
-        // over the columns, then over the waves.
-        static_assert(W <= 64 && CT == 512, "thread mapping of the norms");
-        static_assert(U >= 4 * NW + W, "Ub holds the wave maxima and the column norms");
-        double *dn = Ub + 4 * NW;                    // column norms of R
-        __syncthreads();                             // Ub is free again after the elimination
-        {
-            const int c = t >> 3, sub = t & 7;
-            double a = 0.0;
-            if (c < w) {
+        // the orthogonality of one pass. A zero or non-finite pivot never passes.
+        double a = 0.0;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int k = 8 * sub + e;
-                    const double v = k <= c ? S[k + c * LS] : 0.0;
-                    a = fma(v, v, a);
-                }
+        for (int q = 0; q < NQ; ++q) {
+            const int idx = t + q * CT, i = idx % W, j = idx / W;
+            if (idx < W * W && i <= j && j < w) {
+                const double v = dnb[i] * Xs[i + j * LS];
+                a = fma(v, v, a);
+                if (i == j && !(S[i + i * LS] > 0.0 && dnb[i] > 0.0)) a = HUGE_VAL;
             }
-            a += __shfl_xor(a, 1);
-            a += __shfl_xor(a, 2);
-            a += __shfl_xor(a, 4);
-            if (c < w && sub == 0) dn[c] = sqrt(a);
         }
+#pragma unroll
+        for (int o2 = 32; o2 > 0; o2 >>= 1) a += __shfl_xor(a, o2);
+        if (lane == 0) Ub[wv] = a;
         __syncthreads();
-        double mx[4];
+        double fro2 = Ub[0];
 #pragma unroll
-        for (int nm = 0; nm < 4; ++nm) {
-            const bool isx = nm & 1;                 // R D^-1 or D X
-            const bool cols = nm < 2;                // column sums (1-norm) or row sums (inf)
-            const double *M = isx ? Xs : S;
-            const int c = t >> 3, sub = t & 7;       // 64 columns/rows x 8 parts
-            double a = 0.0;
-            if (c < w) {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int k = 8 * sub + e;
-                    // column c: rows k <= c; row c: columns k >= c (k < w)
-                    const bool in = cols ? (k <= c) : (k >= c && k < w);
-                    const int i = cols ? k : c, j = cols ? c : k;   // entry (i, j)
-                    const double v = in ? M[i + j * LS] : 0.0;
-                    // (R D^-1)_ij = R_ij / d_j, (D X)_ij = d_i X_ij
-                    a += in ? (isx ? fabs(v) * dn[i] : fabs(v) / dn[j]) : 0.0;
-                }
-            }
-            a += __shfl_xor(a, 1);
-            a += __shfl_xor(a, 2);
-            a += __shfl_xor(a, 4);
-#pragma unroll
-            for (int o2 = 8; o2 < 64; o2 <<= 1) a = fmax(a, __shfl_xor(a, o2));
-            mx[nm] = a;
-        }
-        __syncthreads();
-        if (lane == 0) {
-#pragma unroll
-            for (int nm = 0; nm < 4; ++nm) Ub[nm * NW + wv] = mx[nm];
-        }
-        __syncthreads();
-        double nrm[4];
-#pragma unroll
-        for (int nm = 0; nm < 4; ++nm) {
-            nrm[nm] = Ub[nm * NW];
-#pragma unroll
-            for (int q = 1; q < NW; ++q) nrm[nm] = fmax(nrm[nm], Ub[nm * NW + q]);
-        }
-        const double est2 = (nrm[0] * nrm[2]) * (nrm[1] * nrm[3]);   // >= kappa_2(R D^-1)^2
+        for (int q = 1; q < NW; ++q) fro2 += Ub[q];
+        const double est2 = (double)w * fro2;                      // >= kappa_2(R D^-1)^2
         const bool ok = est2 <= ktau * ktau;                        // NaN: keep the second pass
         if (t == 0) *kflag = ok ? 1 : 0;
         if (!ok) return;
@@ -1036,7 +985,7 @@ __global__ __launch_bounds__(CT) void gram_chol_leaf_kernel(const double *__rest
     __shared__ double Xs[H * LS];    // X_AA
     __shared__ double GAB[H * LS];   // G_AB -> R_AB
     __shared__ double GBB[H * LS];   // G_BB -> S_BB -> R_BB, then R_AB X_BB
-    __shared__ double Ub[2 * (8 * H + 4)];
+    __shared__ __align__(16) double Ub[gram::kCholT64];
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
     const bool rfin = Rfinal && !Rprev;   // R block written here (single pass)

@@ -186,8 +186,8 @@ QRX_DEV void gram_store(double (&acc)[4][4], double *red, double *out, int t) {
 // diagonal zeroed, so that rows <= k, whose entry in that row is zero, are
 // left unchanged without a branch. Waves whose rows are all <= k skip the
 // step; one barrier per step. Entries left of the diagonal take finite values
-// that are never read. T is LDS scratch of 4W + 4 doubles (2 (8W + 4) for
-// W = 64 with 512 threads, which takes the four-pivot variant).
+// that are never read. T is LDS scratch of 4W + 4 doubles (kCholT64 for
+// W = 64 with 512 threads, which takes the blocked variant).
 // ---------------------------------------------------------------------------
 // 1 / sqrt(d) for d > 0: hardware estimate plus one Newton step.
 QRX_DEV double rsqrt_d(double d) {
@@ -203,88 +203,117 @@ QRX_DEV double readlane_d(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// The same elimination for W = 64 and 512 threads, four pivots per barrier.
-// A wave owns eight whole rows (two columns per lane). For the block of pivots
-// kk..kk+3 the owning wave eliminates within its four pivot rows in registers
-// (pivots and multipliers read across lanes), then publishes the four updated
-// rows, with their left entries up to kk+3 zeroed; after one
-// barrier every wave subtracts the rank-4 term from its rows below the block.
-// The reciprocal pivots are published with the rows.
-// T is LDS scratch of 2 (8W + 4) doubles.
-QRX_DEV void chol_inv64_b4(double *S, double *Xs, double *T, int t) {
-    constexpr int W = 64, LS = W + 1, RB = 8, CB = 2, NCB = 2 * W / CB, RL = 8 * W + 4;
+// The same elimination for W = 64 and 512 threads, blocked by eight pivots.
+// Wave b owns rows 8b .. 8b + 7 of [G | I] (two columns per lane). In round b
+// these rows have every earlier pivot applied; each lane of wave b reads the
+// 8 x 8 diagonal block D (through LDS), factors D = U^T U redundantly in
+// registers, and applies U^{-T} to its two columns of the eight rows, which
+// thereby become rows 8b .. 8b + 7 of [R | R^{-T}] (final, scaled). The wave
+// publishes them; after one barrier each wave below subtracts, from each of
+// its rows i, R[p][i] times row p for the eight rows p of the block (the
+// Schur-complement update of both halves, by the symmetry of the remaining
+// block). Eight barriers in all; the pivots of a block form one register-
+// resident chain in a single wave.
+constexpr int kCholT64 = 2 * 8 * 128 + 64;   // LDS scratch: two 8-row buffers, the block
+
+QRX_DEV void chol_inv64_b8(double *S, double *Xs, double *T, int t) {
+    constexpr int W = 64, LS = W + 1, RB = 8, RW = 2 * W;
     const int lane = t & 63;
-    const int i0 = (t / NCB) * RB, j0 = (t % NCB) * CB;   // one row block per wave
-    double M[RB][CB], sc[RB];
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int i0 = wv * RB, j0 = 2 * lane;
+    double M[RB][2];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        sc[r] = 0.0;
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int c = 0; c < CB; ++c) {
+        for (int c = 0; c < 2; ++c) {
             const int i = i0 + r, j = j0 + c;
             M[r][c] = (j < W) ? ((i <= j) ? S[i + j * LS] : S[j + i * LS])
                               : ((j - W == i) ? 1.0 : 0.0);
         }
-    }
+    double *Dsh = T + 2 * RB * RW;
     __syncthreads();
-    // pivot rows base..base+3 of this wave's registers (base 0 or 4)
-    auto eliminate = [&](auto base_c, int kk) {
-        constexpr int B = decltype(base_c)::value;
-        double *dst = T + ((kk / 4) & 1) * RL;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int p = kk + q;                     // pivot column: lane p / 2, slot q & 1
-            const double d = readlane_d(M[B + q][q & 1], p >> 1);
-            const double rinv = (d > 0.0) ? rsqrt_d(d) : 0.0;
-            const double dinv = rinv * rinv;
-            sc[B + q] = rinv;
-#pragma unroll
-            for (int r2 = q + 1; r2 < 4; ++r2) {
-                const double f = readlane_d(M[B + r2][q & 1], p >> 1) * dinv;
-#pragma unroll
-                for (int c = 0; c < CB; ++c) M[B + r2][c] = fma(-f, M[B + q][c], M[B + r2][c]);
-            }
-            if (lane == (p >> 1)) dst[8 * W + q] = dinv;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const int j = j0 + c;
-                dst[q * 2 * W + j] = (j <= kk + 3) ? 0.0 : M[B + q][c];
-            }
-    };
-    const int wlast = __builtin_amdgcn_readfirstlane(i0 + RB - 1);
-    const int wfirst = __builtin_amdgcn_readfirstlane(i0);
-    for (int kk = 0; kk < W; kk += 4) {
-        if (kk == wfirst) eliminate(std::integral_constant<int, 0>{}, kk);
-        else if (kk == wfirst + 4) eliminate(std::integral_constant<int, 4>{}, kk);
-        __syncthreads();
-        if (wlast > kk + 3) {
-            const double *row = T + ((kk / 4) & 1) * RL;
-            double rc[4][CB], rr[4][RB];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double dinv = row[8 * W + q];   // 1 / pivot (0 for a bad pivot)
-#pragma unroll
-                for (int c = 0; c < CB; ++c) rc[q][c] = row[q * 2 * W + j0 + c] * dinv;
-#pragma unroll
-                for (int r = 0; r < RB; ++r) rr[q][r] = row[q * 2 * W + i0 + r];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
+    for (int b = 0; b < W / RB; ++b) {
+        double *buf = T + (b & 1) * RB * RW;
+        if (wv == b) {
+            // the diagonal block: columns 8b .. 8b + 7 are in lanes 4b .. 4b + 3
+            if ((lane >> 2) == b) {
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
+                    *(double2 *)&Dsh[r * RB + (j0 - RB * b)] = make_double2(M[r][0], M[r][1]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            double D[RB][RB];
 #pragma unroll
-                    for (int c = 0; c < CB; ++c) M[r][c] = fma(-rr[q][r], rc[q][c], M[r][c]);
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int c = 0; c < RB; c += 2) {
+                    const double2 v = *(const double2 *)&Dsh[r * RB + c];
+                    D[r][c] = v.x;
+                    D[r][c + 1] = v.y;
+                }
+            // D = U^T U (upper part of D becomes U; a pivot <= 0 gives a zero row)
+            double rinv[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const double d = D[q][q];
+                const double ri = (d > 0.0) ? rsqrt_d(d) : 0.0;
+                rinv[q] = ri;
+#pragma unroll
+                for (int c = q; c < RB; ++c) D[q][c] *= ri;
+#pragma unroll
+                for (int r = q + 1; r < RB; ++r)
+#pragma unroll
+                    for (int c = r; c < RB; ++c) D[r][c] = fma(-D[q][r], D[q][c], D[r][c]);
+            }
+            // rows <- U^{-T} rows: row q = (row q - sum_{p<q} U[p][q] row p) / U[q][q]
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    double v = M[q][c];
+#pragma unroll
+                    for (int p2 = 0; p2 < q; ++p2) v = fma(-D[p2][q], M[p2][c], v);
+                    M[q][c] = v * rinv[q];
+                }
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                *(double2 *)&buf[r * RW + j0] = make_double2(M[r][0], M[r][1]);
+        }
+        __syncthreads();
+        if (wv > b) {
+            // rows i of this wave: M[i][.] -= sum_p R[p][i] R[p][.]
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                double mu[4][RB], rp[4][2];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double *row = buf + (4 * h + q) * RW;
+#pragma unroll
+                    for (int r = 0; r < RB; r += 2) {
+                        const double2 v = *(const double2 *)&row[i0 + r];
+                        mu[q][r] = v.x;
+                        mu[q][r + 1] = v.y;
+                    }
+                    const double2 v = *(const double2 *)&row[j0];
+                    rp[q][0] = v.x;
+                    rp[q][1] = v.y;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) M[r][c] = fma(-mu[q][r], rp[q][c], M[r][c]);
+            }
         }
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int c = 0; c < CB; ++c) {
+        for (int c = 0; c < 2; ++c) {
             const int i = i0 + r, j = j0 + c;
-            const double v = M[r][c] * sc[r];
+            const double v = M[r][c];
             if (j < W) {
                 if (i <= j) S[i + j * LS] = v;
             } else {
@@ -298,7 +327,7 @@ QRX_DEV void chol_inv64_b4(double *S, double *Xs, double *T, int t) {
 template <int W, int NT>
 QRX_DEV void chol_inv(double *S, double *Xs, double *T, int t) {
     if constexpr (W == 64 && NT == 512) {
-        chol_inv64_b4(S, Xs, T, t);
+        chol_inv64_b8(S, Xs, T, t);
         return;
     }
     constexpr int LS = W + 1;
