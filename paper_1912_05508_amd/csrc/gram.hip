@@ -400,39 +400,56 @@ __global__ __launch_bounds__(CT) void gram_chol_kernel(const double *__restrict_
     __shared__ double dnb[W];          // column norms of the factor (single-pass bound)
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
-    double gv[NQ];
-    int off[NQ];
+    // G = the sum of the partials, in partial order. Thread t takes the pairs
+    // of packed entries 2k, 2k + 1 for k = t, t + CT, ...: 16-byte loads, all
+    // in flight at once (one round trip to memory).
+    constexpr int NP2 = NP / 2, NC = (NP2 + CT - 1) / CT;
+    static_assert(NP % 2 == 0, "packed Gram blocks hold an even number of entries");
+    double2 gv[NC];
+    {
+        const double2 *p2 = reinterpret_cast<const double2 *>(part);
+        double2 v[kDirectParts][NC];
+#pragma unroll
+        for (int b = 0; b < kDirectParts; ++b)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int k = t + c * CT;
+                v[b][c] = (b < nparts && k < NP2) ? p2[(int64_t)b * NP2 + k] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            gv[c] = v[0][c];
+#pragma unroll
+            for (int b = 1; b < kDirectParts; ++b) {
+                gv[c].x += v[b][c].x;
+                gv[c].y += v[b][c].y;
+            }
+        }
+    }
+    // S: G in the upper triangle (zero in columns >= w), zero below it
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int idx = t + q * CT, i = idx % W, j = idx / W;
-        gv[q] = 0.0;
-        off[q] = (idx < W * W && i <= j && j < w) ? upk(i, j) : -1;
+        if (idx < W * W && i > j) S[i + j * LS] = 0.0;
     }
-    {
-        // every load in flight at once (one round trip to memory), then the
-        // sums in partial order
-        double v[kDirectParts][NQ];
-#pragma unroll
-        for (int b = 0; b < kDirectParts; ++b)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q)
-                v[b][q] = (b < nparts && off[q] >= 0) ? part[(int64_t)b * NP + off[q]] : 0.0;
-#pragma unroll
-        for (int b = 0; b < kDirectParts; ++b)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) gv[q] += v[b][q];
-    }
-
     double dev = 0.0;
-    {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int idx = t + q * CT, i = idx % W, j = idx / W;
-            if (idx >= W * W) continue;
-            S[i + j * LS] = gv[q];
-            if (i == j && j < w) dnb[i] = sqrt(gv[q]);   // column norms of R
-            if (i <= j && j < w) {
-                const double e2 = fabs(gv[q] - (i == j ? 1.0 : 0.0));
+    for (int c = 0; c < NC; ++c) {
+        const int k = t + c * CT;
+        if (k >= NP2) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = 2 * k + h;
+            // e = j (j + 1) / 2 + i, 0 <= i <= j
+            int j = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+            if (j * (j + 1) / 2 > e) --j;
+            if ((j + 1) * (j + 2) / 2 <= e) ++j;
+            const int i = e - j * (j + 1) / 2;
+            const double g = j < w ? (h ? gv[c].y : gv[c].x) : 0.0;
+            S[i + j * LS] = g;
+            if (j < w) {
+                if (i == j) dnb[i] = sqrt(g);   // column norms of R
+                const double e2 = fabs(g - (i == j ? 1.0 : 0.0));
                 dev = fmax(dev, (e2 == e2) ? e2 : 1e300);   // a NaN entry never passes
             }
         }
