@@ -58,8 +58,8 @@ MEASURED_TRAFFIC = {
         "bytes_per_launch": 51.61e6,
         "profile": "profiles/gram_panel_32768x4096_hbm_traffic.txt",
         "sources": {
-            "paper_1912_05508_amd/csrc/gram.hip": "8b3c2b799329a06dfc85c04ac97fbea86252a238",
-            "paper_1912_05508_amd/csrc/gram_common.hpp": "099a20c7447911dd6b1d4446ff87022b52f27298",
+            "paper_1912_05508_amd/csrc/gram.hip": "ad3793484a2172c129157b261732f93952abcd4d",
+            "paper_1912_05508_amd/csrc/gram_common.hpp": "5a1bdaca50c07099e236aef3e314d0a74c6688a6",
         },
     },
 }
