@@ -263,12 +263,10 @@ QRX_DEV void wg_panel(float *P, int64_t ld, int64_t m, int w, float *Rb, int64_t
     double *T = Xc + 32 * 33;               // pivot rows of the elimination (and scratch)
     double *R1 = T + 256;                   // first-sweep R
     const int64_t nch = (m + gram::CH - 1) / gram::CH;
-    double acc[4][4];
+    gram::gd4 acc[3];
     auto zero = [&]() {
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+        for (int x = 0; x < 3; ++x) acc[x] = gram::gd4{0.0, 0.0, 0.0, 0.0};
     };
     auto factor = [&]() {   // Gl -> S -> R, Xc; X into the sweep layout
         for (int idx = t; idx < 32 * 32; idx += BT) {
@@ -283,8 +281,8 @@ QRX_DEV void wg_panel(float *P, int64_t ld, int64_t m, int w, float *Rb, int64_t
         }
     };
     zero();
-    gram::sweep<32, false, true>(P, ld, m, w, 0, nch, Xs, C, acc, t);
-    gram::gram_store<32>(acc, red, Gl, t);
+    gram::sweep32<false, true>(P, ld, m, w, 0, nch, Xs, C, acc, t);
+    gram::gram_store32(acc, red, Gl, t);
     __syncthreads();
     factor();
     for (int idx = t; idx < 32 * 32; idx += BT) {
@@ -298,13 +296,13 @@ QRX_DEV void wg_panel(float *P, int64_t ld, int64_t m, int w, float *Rb, int64_t
             const int i = idx % 32, j = idx / 32;
             if (i < w && j < w) Rb[i + (int64_t)j * ldr] = (float)R1[idx];
         }
-        gram::sweep<32, true, false>(P, ld, m, w, 0, nch, Xs, C, acc, t);
+        gram::sweep32<true, false>(P, ld, m, w, 0, nch, Xs, C, acc, t);
         __syncthreads();
         return;
     }
     zero();
-    gram::sweep<32, true, true>(P, ld, m, w, 0, nch, Xs, C, acc, t);
-    gram::gram_store<32>(acc, red, Gl, t);
+    gram::sweep32<true, true>(P, ld, m, w, 0, nch, Xs, C, acc, t);
+    gram::gram_store32(acc, red, Gl, t);
     __syncthreads();
     // Q1 already orthonormal to working accuracy: R = R1, no second factorisation
     double dev = 0.0;
@@ -335,7 +333,7 @@ QRX_DEV void wg_panel(float *P, int64_t ld, int64_t m, int w, float *Rb, int64_t
             Rb[i + (int64_t)j * ldr] = (float)v;
         }
     }
-    gram::sweep<32, true, false>(P, ld, m, w, 0, nch, Xs, C, acc, t);
+    gram::sweep32<true, false>(P, ld, m, w, 0, nch, Xs, C, acc, t);
     __syncthreads();
 }
 

@@ -263,6 +263,13 @@ QRX_DEV void pass_body(float *__restrict__ P, int64_t ld, int64_t m, int w, int6
         sweep64<DO_Q, DO_G>(P, ld, m, w, ch0, ch1, Xs, C, acc, t, pk);
         if constexpr (DO_G) gram_store64(acc, part + (int64_t)blockIdx.x * (W * (W + 1) / 2), t);
         (void)red;
+    } else if constexpr (W == 32) {
+        gram::gd4 acc[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) acc[p] = gram::gd4{0.0, 0.0, 0.0, 0.0};
+        gram::sweep32<DO_Q, DO_G>(P, ld, m, w, ch0, ch1, Xs, C, acc, t);
+        if constexpr (DO_G)
+            gram::gram_store32(acc, red, part + (int64_t)blockIdx.x * (W * (W + 1) / 2), t);
     } else {
         double acc[4][4];
 #pragma unroll

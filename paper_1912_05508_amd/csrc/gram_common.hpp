@@ -171,6 +171,137 @@ QRX_DEV void gram_store(double (&acc)[4][4], double *red, double *out, int t) {
 }
 
 // ---------------------------------------------------------------------------
+// 32-column sweeps on the FP64 matrix cores (v_mfma_f64_16x16x4f64: A operand
+// lane l holds A[l % 16][l / 16], B operand B[l / 16][l % 16], result register
+// v of lane l holds D[4 v + l / 16][l % 16]). The four-by-four register tiles
+// of sweep() read two LDS values per two FMAs and leave the sweep bound by LDS;
+// a matrix-core step reads one value per lane per operand for 1024 FMAs.
+// Gram: wave w takes rows 16w .. 16w + 15 of each chunk (four steps of four
+// rows) for the three upper 16 x 16 blocks (0,0), (0,1), (1,1); gram_store32
+// adds the waves' sums at the end of the sweep. Q formation: wave w forms rows
+// 16w .. 16w + 15 of rows X, its two column blocks over K up to the block's
+// last column (X is upper triangular).
+// ---------------------------------------------------------------------------
+typedef double gd4 __attribute__((ext_vector_type(4)));
+QRX_DEV gd4 mfma_f64(double a, double b, gd4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <bool DO_Q, bool DO_G>
+QRX_DEV void sweep32(float *__restrict__ P, int64_t ld, int64_t m, int w, int64_t ch0, int64_t ch1,
+                     const double *Xs, double *C, gd4 (&acc)[3], int t) {
+    using L = Lds<32>;
+    constexpr int LDC = L::LDC, XLD = L::XLD;
+    constexpr int LPT = CH * 32 / GT;           // chunk elements each thread stages
+    static_assert(GT == 256 && CH == 64, "four waves, 16 chunk rows each");
+    const int lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int li = lane & 15, lk = lane >> 4;
+    float pre[LPT];
+    auto load = [&](int64_t ch) {
+#pragma unroll
+        for (int s = 0; s < LPT; ++s) {
+            const int e = t + GT * s;
+            const int rr = e % CH, cc = e / CH;
+            const int64_t r = ch * CH + rr;
+            pre[s] = (r < m && cc < w) ? P[r + cc * ld] : 0.0f;
+        }
+    };
+    if (ch0 < ch1) load(ch0);
+    for (int64_t ch = ch0; ch < ch1; ++ch) {
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < LPT; ++s) {
+            const int e = t + GT * s;
+            C[(e % CH) * LDC + e / CH] = (double)pre[s];
+        }
+        __syncthreads();
+        if (ch + 1 < ch1) load(ch + 1);
+        if constexpr (DO_Q) {
+            gd4 q[2];
+#pragma unroll
+            for (int Jb = 0; Jb < 2; ++Jb) {
+                q[Jb] = gd4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k4 = 0; k4 < 4 * (Jb + 1); ++k4) {
+                    const double a = C[(16 * wv + li) * LDC + 4 * k4 + lk];
+                    const double b = Xs[(4 * k4 + lk) * XLD + 16 * Jb + li];
+                    q[Jb] = mfma_f64(a, b, q[Jb]);
+                }
+            }
+            __syncthreads();   // every wave has read its rows of the chunk
+#pragma unroll
+            for (int Jb = 0; Jb < 2; ++Jb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    C[(16 * wv + 4 * v + lk) * LDC + 16 * Jb + li] = (double)(float)q[Jb][v];
+            __syncthreads();
+            // Q rows back to P, coalesced along the columns
+#pragma unroll
+            for (int s = 0; s < LPT; ++s) {
+                const int e = t + GT * s;
+                const int rr = e % CH, cc = e / CH;
+                const int64_t r = ch * CH + rr;
+                if (r < m && cc < w) P[r + cc * ld] = (float)C[rr * LDC + cc];
+            }
+        }
+        if constexpr (DO_G) {
+#pragma unroll
+            for (int k4 = 0; k4 < 4; ++k4) {
+                const double *row = C + (16 * wv + 4 * k4 + lk) * LDC + li;
+                const double r0 = row[0], r1 = row[16];
+                acc[0] = mfma_f64(r0, r0, acc[0]);
+                acc[1] = mfma_f64(r0, r1, acc[1]);
+                acc[2] = mfma_f64(r1, r1, acc[2]);
+            }
+        }
+    }
+}
+
+// The waves' Gram sums of sweep32 added in a fixed order ((w0 + w2) + (w1 + w3))
+// and the upper triangle of the 32 x 32 result written to out[upk(i, j)]
+// (global or LDS); red holds 1536 doubles. Ends with a barrier.
+QRX_DEV void gram_store32(gd4 (&acc)[3], double *red, double *out, int t) {
+    const int lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    static_assert(Lds<32>::RED_DOUBLES >= 2 * 12 * 64, "reduction buffer");
+    auto slot = [&](int s, int p, int v) { return red + ((s * 3 + p) * 4 + v) * 64 + lane; };
+    __syncthreads();   // red may still be read by the caller's previous step
+    if (wv >= 2) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) *slot(wv - 2, p, v) = acc[p][v];
+    }
+    __syncthreads();
+    if (wv < 2) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[p][v] += *slot(wv, p, v);
+    }
+    __syncthreads();
+    if (wv == 1) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) *slot(0, p, v) = acc[p][v];
+    }
+    __syncthreads();
+    if (wv == 0) {
+        const int Is[3] = {0, 0, 1}, Js[3] = {0, 1, 1};
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * Is[p] + 4 * v + (lane >> 4), j = 16 * Js[p] + (lane & 15);
+                if (i <= j) out[upk(i, j)] = acc[p][v] + *slot(0, p, v);
+            }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // Cholesky with the inverse of the factor: G = R^T R (R upper, R_kk > 0) and
 // X = R^{-1}, FP64 in LDS (column-major, stride W + 1). On entry S holds G in
 // its upper triangle (zero beyond w); on exit S holds R in its upper triangle
