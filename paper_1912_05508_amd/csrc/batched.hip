@@ -440,6 +440,11 @@ struct BVec {   // n-vectors in LDS (kBMaxN each)
     double *x, *xb, *v, *t, *d, *z, *y, *xs;
 };
 
+// The loops over A and R below load in groups (KB entries of A, or four
+// row steps) before they accumulate, so that a group's loads are in flight
+// together; the sums keep their sequential order.
+constexpr int KB = 8;
+
 // out = R^{-1} in (trans 0) or R^{-T} in (trans 1); R FP32 upper (n x n, ldr),
 // arithmetic in FP64. y is scratch, Rb holds a 64 x 65 block (LDS). Blocks of
 // 64 rows: the diagonal block is staged in LDS and solved by wave 0 (one row
@@ -457,10 +462,19 @@ QRX_DEV void wg_trsv(const float *R, int64_t ldr, int n, const double *in, doubl
         // Rb[i * 65 + c] = block entry the lane i uses at step c:
         // R[o+i][o+c] (trans 0) or R[o+c][o+i] (trans 1)
         __syncthreads();
-        for (int idx = t; idx < 64 * 64; idx += BT) {
-            const int r = idx % 64, c = idx / 64;    // R[o+r][o+c], coalesced along r
-            const float v = (r < bw && c < bw) ? R[(o + r) + (int64_t)(o + c) * ldr] : 0.0f;
-            if (trans) Rb[c * 65 + r] = v; else Rb[r * 65 + c] = v;
+        {
+            constexpr int NL = 64 * 64 / BT;
+            float v[NL];
+#pragma unroll
+            for (int s2 = 0; s2 < NL; ++s2) {
+                const int idx = t + s2 * BT, r = idx % 64, c = idx / 64;   // R[o+r][o+c], coalesced along r
+                v[s2] = (r < bw && c < bw) ? R[(o + r) + (int64_t)(o + c) * ldr] : 0.0f;
+            }
+#pragma unroll
+            for (int s2 = 0; s2 < NL; ++s2) {
+                const int idx = t + s2 * BT, r = idx % 64, c = idx / 64;
+                if (trans) Rb[c * 65 + r] = v[s2]; else Rb[r * 65 + c] = v[s2];
+            }
         }
         __syncthreads();
         if (wv == 0) {
@@ -482,13 +496,29 @@ QRX_DEV void wg_trsv(const float *R, int64_t ldr, int n, const double *in, doubl
         if (!trans) {
             for (int r = t; r < o; r += BT) {
                 double acc = 0.0;
-                for (int c = 0; c < bw; ++c) acc = fma((double)R[r + (int64_t)(o + c) * ldr], out[o + c], acc);
+                int c = 0;
+                for (; c + KB <= bw; c += KB) {
+                    float a[KB];
+#pragma unroll
+                    for (int k = 0; k < KB; ++k) a[k] = R[r + (int64_t)(o + c + k) * ldr];
+#pragma unroll
+                    for (int k = 0; k < KB; ++k) acc = fma((double)a[k], out[o + c + k], acc);
+                }
+                for (; c < bw; ++c) acc = fma((double)R[r + (int64_t)(o + c) * ldr], out[o + c], acc);
                 y[r] -= acc;
             }
         } else {
             for (int j = o + 64 + t; j < n; j += BT) {
                 double acc = 0.0;
-                for (int c = 0; c < bw; ++c) acc = fma((double)R[(o + c) + (int64_t)j * ldr], out[o + c], acc);
+                int c = 0;
+                for (; c + KB <= bw; c += KB) {
+                    float a[KB];
+#pragma unroll
+                    for (int k = 0; k < KB; ++k) a[k] = R[(o + c + k) + (int64_t)j * ldr];
+#pragma unroll
+                    for (int k = 0; k < KB; ++k) acc = fma((double)a[k], out[o + c + k], acc);
+                }
+                for (; c < bw; ++c) acc = fma((double)R[(o + c) + (int64_t)j * ldr], out[o + c], acc);
                 y[j] -= acc;
             }
         }
@@ -502,9 +532,19 @@ QRX_DEV void wg_trsv(const float *R, int64_t ldr, int n, const double *in, doubl
 QRX_DEV double wg_gemv_n(const BProb &p, const double *tv, double alpha, double *u, double *sh,
                          int t) {
     double ss = 0.0;
+    const int n = (int)p.n;
     for (int64_t r = t; r < p.m; r += BT) {
+        const float *ar = p.A + r;
         double acc = 0.0;
-        for (int j = 0; j < (int)p.n; ++j) acc = fma((double)p.A[r + (int64_t)j * p.lda], tv[j], acc);
+        int j = 0;
+        for (; j + KB <= n; j += KB) {
+            float a[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) a[k] = ar[(int64_t)(j + k) * p.lda];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) acc = fma((double)a[k], tv[j + k], acc);
+        }
+        for (; j < n; ++j) acc = fma((double)ar[(int64_t)j * p.lda], tv[j], acc);
         const double v = (alpha != 0.0) ? acc - alpha * u[r] : acc;
         u[r] = v;
         ss = fma(v, v, ss);
@@ -518,7 +558,19 @@ QRX_DEV void wg_gemv_t(const BProb &p, const double *u, double *z, int t) {
     for (int j = wv; j < (int)p.n; j += BT / 64) {
         const float *a = p.A + (int64_t)j * p.lda;
         double acc = 0.0;
-        for (int64_t r = lane; r < p.m; r += 64) acc = fma((double)a[r], u[r], acc);
+        int64_t r = lane;
+        for (; r + 3 * 64 < p.m; r += 4 * 64) {
+            float av[4];
+            double uv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                av[k] = a[r + 64 * k];
+                uv[k] = u[r + 64 * k];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc = fma((double)av[k], uv[k], acc);
+        }
+        for (; r < p.m; r += 64) acc = fma((double)a[r], u[r], acc);
         acc = wave_sum_d(acc);
         if (lane == 0) z[j] = acc;
     }
@@ -534,7 +586,17 @@ QRX_DEV double wg_certify(const BProb &p, const double *x, double *z, double *q,
     double ss = 0.0;
     for (int64_t r = t; r < p.m; r += BT) {
         double h = p.b[r], l = 0.0;
-        for (int j = 0; j < (int)p.n; ++j) dd_add_prod(h, l, -(double)p.A[r + (int64_t)j * p.lda], x[j]);
+        const float *ar = p.A + r;
+        const int n = (int)p.n;
+        int j = 0;
+        for (; j + KB <= n; j += KB) {
+            float a[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) a[k] = ar[(int64_t)(j + k) * p.lda];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) dd_add_prod(h, l, -(double)a[k], x[j + k]);
+        }
+        for (; j < n; ++j) dd_add_prod(h, l, -(double)ar[(int64_t)j * p.lda], x[j]);
         const double v = h + l;
         q[r] = v;
         ss = fma(v, v, ss);
