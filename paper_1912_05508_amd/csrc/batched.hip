@@ -364,7 +364,20 @@ QRX_DEV BRes wg_qr(const BProb &p, const BOp *ops, int copy, double *lds, double
         double s = 0.0;
         const float *a = p.A + (int64_t)j * p.lda;
         float *wcol = p.W + (int64_t)j * p.ldw;
-        for (int64_t r = lane; r < m; r += 64) {
+        // four rows of the lane at a time (their loads in flight together)
+        int64_t r = lane;
+        for (; r + 3 * 64 < m; r += 4 * 64) {
+            float v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = a[r + 64 * k];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!(fabsf(v[k]) <= 3.4028235e38f)) bad = 1;
+                s = fma((double)v[k], (double)v[k], s);
+                if (copy) wcol[r + 64 * k] = v[k];
+            }
+        }
+        for (; r < m; r += 64) {
             const float v = a[r];
             if (!(fabsf(v) <= 3.4028235e38f)) bad = 1;
             s = fma((double)v, (double)v, s);
