@@ -541,6 +541,21 @@ QRX_DEV void wg_trsv(const float *R, int64_t ldr, int n, const double *in, doubl
     __syncthreads();
 }
 
+// f(r) for the rows r = t, t + BT, ... of [0, m), four at a time: f is called
+// as f(r, v) after the four loads v = src[r] of a group are issued together.
+template <class F>
+QRX_DEV void rows4(int64_t m, const double *src, int t, F f) {
+    int64_t r = t;
+    for (; r + 3 * BT < m; r += 4 * BT) {
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = src[r + k * BT];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f(r + k * BT, v[k]);
+    }
+    for (; r < m; r += BT) f(r, src[r]);
+}
+
 // u <- A t - alpha u (alpha = 0: u <- A t); returns ||u||^2. t in LDS.
 QRX_DEV double wg_gemv_n(const BProb &p, const double *tv, double alpha, double *u, double *sh,
                          int t) {
@@ -662,7 +677,7 @@ QRX_DEV void wg_lsqr(const BProb &p, const BRes &qr, double tol, int max_iter, q
     // it with the eta_F target through the largest column norm
     const double trig = normA > 0.0 ? qr.rho / normA : 1.0;
     double bb = 0.0;
-    for (int64_t r = t; r < p.m; r += BT) bb = fma(p.b[r], p.b[r], bb);
+    rows4(p.m, p.b, t, [&](int64_t, double v) { bb = fma(v, v, bb); });
     const double bnorm = sqrt(bsum(bb, sh));
     double gamma = 1.0, best = 1e300, eta = 0.0, rnorm = 0.0, best_eta = 0.0, best_rn = 0.0;
     double first_eta = 0.0;
@@ -692,7 +707,7 @@ QRX_DEV void wg_lsqr(const BProb &p, const BRes &qr, double tol, int max_iter, q
         }
         // LSQR on the correction: min || A R^{-1} y - q ||, x += R^{-1} y
         double beta = rnorm;
-        for (int64_t r = t; r < p.m; r += BT) p.u[r] = p.q[r] / beta;
+        rows4(p.m, p.q, t, [&](int64_t r, double v) { p.u[r] = v / beta; });
         for (int j = t; j < kBMaxN; j += BT) V.z[j] = V.z[j] / beta;   // A^T u
         __syncthreads();
         wg_trsv(p.R, p.ldr, n, V.z, V.y, V.v, Rb, 1, t);                     // v = R^{-T} A^T u
@@ -712,7 +727,7 @@ QRX_DEV void wg_lsqr(const BProb &p, const BRes &qr, double tol, int max_iter, q
             const double b2 = wg_gemv_n(p, V.t, alpha, p.u, sh, t);   // u = A t - alpha u
             beta = sqrt(b2);
             if (beta > 0.0)
-                for (int64_t r = t; r < p.m; r += BT) p.u[r] /= beta;
+                rows4(p.m, p.u, t, [&](int64_t r, double v) { p.u[r] = v / beta; });
             __syncthreads();
             wg_gemv_t(p, p.u, V.z, t);                                   // z = A^T u
             wg_trsv(p.R, p.ldr, n, V.z, V.y, V.xs, Rb, 1, t);                // xs = R^{-T} z
