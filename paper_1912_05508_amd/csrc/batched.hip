@@ -456,7 +456,7 @@ struct BVec {   // n-vectors in LDS (kBMaxN each)
 // The loops over A and R below load in groups (KB entries of A, or four
 // row steps) before they accumulate, so that a group's loads are in flight
 // together; the sums keep their sequential order.
-constexpr int KB = 8;
+constexpr int KB = 16;
 
 // out = R^{-1} in (trans 0) or R^{-T} in (trans 1); R FP32 upper (n x n, ldr),
 // arithmetic in FP64. y is scratch, Rb holds a 64 x 65 block (LDS). Blocks of
@@ -587,16 +587,16 @@ QRX_DEV void wg_gemv_t(const BProb &p, const double *u, double *z, int t) {
         const float *a = p.A + (int64_t)j * p.lda;
         double acc = 0.0;
         int64_t r = lane;
-        for (; r + 3 * 64 < p.m; r += 4 * 64) {
-            float av[4];
-            double uv[4];
+        for (; r + 7 * 64 < p.m; r += 8 * 64) {
+            float av[8];
+            double uv[8];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < 8; ++k) {
                 av[k] = a[r + 64 * k];
                 uv[k] = u[r + 64 * k];
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) acc = fma((double)av[k], uv[k], acc);
+            for (int k = 0; k < 8; ++k) acc = fma((double)av[k], uv[k], acc);
         }
         for (; r < p.m; r += 64) acc = fma((double)a[r], u[r], acc);
         acc = wave_sum_d(acc);
