@@ -556,51 +556,85 @@ QRX_DEV void rows4(int64_t m, const double *src, int t, F f) {
     for (; r < m; r += BT) f(r, src[r]);
 }
 
-// u <- A t - alpha u (alpha = 0: u <- A t); returns ||u||^2. t in LDS.
+// u <- A t - alpha u (alpha = 0: u <- A t); returns ||u||^2. t in LDS. A
+// thread takes two of its rows at a time (r and r + BT).
 QRX_DEV double wg_gemv_n(const BProb &p, const double *tv, double alpha, double *u, double *sh,
                          int t) {
     double ss = 0.0;
     const int n = (int)p.n;
-    for (int64_t r = t; r < p.m; r += BT) {
-        const float *ar = p.A + r;
-        double acc = 0.0;
-        int j = 0;
-        for (; j + KB <= n; j += KB) {
-            float a[KB];
-#pragma unroll
-            for (int k = 0; k < KB; ++k) a[k] = ar[(int64_t)(j + k) * p.lda];
-#pragma unroll
-            for (int k = 0; k < KB; ++k) acc = fma((double)a[k], tv[j + k], acc);
-        }
-        for (; j < n; ++j) acc = fma((double)ar[(int64_t)j * p.lda], tv[j], acc);
+    auto finish = [&](int64_t r, double acc) {
         const double v = (alpha != 0.0) ? acc - alpha * u[r] : acc;
         u[r] = v;
         ss = fma(v, v, ss);
+    };
+    for (int64_t r = t; r < p.m; r += 2 * BT) {
+        const int64_t r2 = r + BT;
+        const bool two = r2 < p.m;
+        const float *ar = p.A + r;
+        const float *ar2 = p.A + (two ? r2 : r);
+        double acc = 0.0, acc2 = 0.0;
+        int j = 0;
+        for (; j + KB <= n; j += KB) {
+            float a[KB], b[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                a[k] = ar[(int64_t)(j + k) * p.lda];
+                b[k] = ar2[(int64_t)(j + k) * p.lda];
+            }
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                acc = fma((double)a[k], tv[j + k], acc);
+                acc2 = fma((double)b[k], tv[j + k], acc2);
+            }
+        }
+        for (; j < n; ++j) {
+            acc = fma((double)ar[(int64_t)j * p.lda], tv[j], acc);
+            acc2 = fma((double)ar2[(int64_t)j * p.lda], tv[j], acc2);
+        }
+        finish(r, acc);
+        if (two) finish(r2, acc2);
     }
     return bsum(ss, sh);
 }
 
-// z <- A^T u (one wave per column, fixed reduction order); z in LDS.
+// z <- A^T u (one wave per column, fixed reduction order); z in LDS. A wave
+// takes two columns at a time (j and j + 4), sharing the loads of u.
 QRX_DEV void wg_gemv_t(const BProb &p, const double *u, double *z, int t) {
     const int lane = t & 63, wv = t >> 6;
-    for (int j = wv; j < (int)p.n; j += BT / 64) {
+    constexpr int NWV = BT / 64;
+    for (int j = wv; j < (int)p.n; j += 2 * NWV) {
+        const int j2 = j + NWV;
+        const bool two = j2 < (int)p.n;
         const float *a = p.A + (int64_t)j * p.lda;
-        double acc = 0.0;
+        const float *a2 = p.A + (int64_t)(two ? j2 : j) * p.lda;
+        double acc = 0.0, acc2 = 0.0;
         int64_t r = lane;
         for (; r + 7 * 64 < p.m; r += 8 * 64) {
-            float av[8];
+            float av[8], bv[8];
             double uv[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 av[k] = a[r + 64 * k];
+                bv[k] = a2[r + 64 * k];
                 uv[k] = u[r + 64 * k];
             }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) acc = fma((double)av[k], uv[k], acc);
+            for (int k = 0; k < 8; ++k) {
+                acc = fma((double)av[k], uv[k], acc);
+                acc2 = fma((double)bv[k], uv[k], acc2);
+            }
         }
-        for (; r < p.m; r += 64) acc = fma((double)a[r], u[r], acc);
+        for (; r < p.m; r += 64) {
+            const double uu = u[r];
+            acc = fma((double)a[r], uu, acc);
+            acc2 = fma((double)a2[r], uu, acc2);
+        }
         acc = wave_sum_d(acc);
-        if (lane == 0) z[j] = acc;
+        acc2 = wave_sum_d(acc2);
+        if (lane == 0) {
+            z[j] = acc;
+            if (two) z[j2] = acc2;
+        }
     }
     __syncthreads();
 }
