@@ -646,22 +646,41 @@ QRX_DEV double wg_certify(const BProb &p, const double *x, double *z, double *q,
                           double bnorm, double &eta, double &rnorm, double *sh, int t,
                           double tol) {
     double ss = 0.0;
-    for (int64_t r = t; r < p.m; r += BT) {
+    const int n = (int)p.n;
+    // two of the thread's rows at a time (r and r + BT)
+    for (int64_t r = t; r < p.m; r += 2 * BT) {
+        const int64_t r2 = r + BT;
+        const bool two = r2 < p.m;
         double h = p.b[r], l = 0.0;
+        double h2 = two ? p.b[r2] : 0.0, l2 = 0.0;
         const float *ar = p.A + r;
-        const int n = (int)p.n;
+        const float *ar2 = p.A + (two ? r2 : r);
         int j = 0;
         for (; j + KB <= n; j += KB) {
-            float a[KB];
+            float a[KB], b[KB];
 #pragma unroll
-            for (int k = 0; k < KB; ++k) a[k] = ar[(int64_t)(j + k) * p.lda];
+            for (int k = 0; k < KB; ++k) {
+                a[k] = ar[(int64_t)(j + k) * p.lda];
+                b[k] = ar2[(int64_t)(j + k) * p.lda];
+            }
 #pragma unroll
-            for (int k = 0; k < KB; ++k) dd_add_prod(h, l, -(double)a[k], x[j + k]);
+            for (int k = 0; k < KB; ++k) {
+                dd_add_prod(h, l, -(double)a[k], x[j + k]);
+                dd_add_prod(h2, l2, -(double)b[k], x[j + k]);
+            }
         }
-        for (; j < n; ++j) dd_add_prod(h, l, -(double)ar[(int64_t)j * p.lda], x[j]);
+        for (; j < n; ++j) {
+            dd_add_prod(h, l, -(double)ar[(int64_t)j * p.lda], x[j]);
+            dd_add_prod(h2, l2, -(double)ar2[(int64_t)j * p.lda], x[j]);
+        }
         const double v = h + l;
         q[r] = v;
         ss = fma(v, v, ss);
+        if (two) {
+            const double v2 = h2 + l2;
+            q[r2] = v2;
+            ss = fma(v2, v2, ss);
+        }
     }
     rnorm = sqrt(bsum(ss, sh));
     wg_gemv_t(p, q, z, t);
