@@ -55,11 +55,11 @@ def qr_flops(m, n):
 # are the ones the counters were taken on (SHA-1 below); otherwise null.
 MEASURED_TRAFFIC = {
     "gram_panel": {
-        "bytes_per_launch": 51.61e6,
+        "bytes_per_launch": 51.6e6,
         "profile": "profiles/gram_panel_32768x4096_hbm_traffic.txt",
         "sources": {
-            "paper_1912_05508_amd/csrc/gram.hip": "ad3793484a2172c129157b261732f93952abcd4d",
-            "paper_1912_05508_amd/csrc/gram_common.hpp": "5a1bdaca50c07099e236aef3e314d0a74c6688a6",
+            "paper_1912_05508_amd/csrc/gram.hip": "ed979e2e5c5f5fbc3e00bf4ea7e30a6c1e71b7fe",
+            "paper_1912_05508_amd/csrc/gram_common.hpp": "4128eec69003331f0c5a2126c3b4d0e8b46f63cb",
         },
     },
 }
