@@ -58,7 +58,7 @@ MEASURED_TRAFFIC = {
         "bytes_per_launch": 51.6e6,
         "profile": "profiles/gram_panel_32768x4096_hbm_traffic.txt",
         "sources": {
-            "paper_1912_05508_amd/csrc/gram.hip": "ed979e2e5c5f5fbc3e00bf4ea7e30a6c1e71b7fe",
+            "paper_1912_05508_amd/csrc/gram.hip": "4c5eeae971a0e956428ab7b6b5e67fb4d71655b6",
             "paper_1912_05508_amd/csrc/gram_common.hpp": "4128eec69003331f0c5a2126c3b4d0e8b46f63cb",
         },
     },

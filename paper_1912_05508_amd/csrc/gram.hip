@@ -44,6 +44,7 @@ constexpr int kMaxParts = 512;   // Gram partials (one per sweep workgroup)
 constexpr int kMaxSlices = 8;    // first-level reduction workgroups per column block
 constexpr int kSliceParts = 64;  // partials summed by one of them (8 per wave)
 constexpr int kDirectParts = 8;  // at most this many partials go to gram_chol unreduced
+static_assert(kMaxSlices <= kDirectParts, "gram_chol sums at most kDirectParts partials");
 
 // ---------------------------------------------------------------------------
 // 64-column sweeps on the FP64 matrix cores (v_mfma_f64_16x16x4f64: A operand
