@@ -365,7 +365,20 @@ QRX_DEV double col_dot(const double *col, const double *in, int64_t i0, int64_t 
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc = fma(c[u], w[u], acc);
     }
-    for (; i < i1; i += 64) acc = fma(col[i], in[i], acc);
+    // the rest (fewer than eight per lane): loaded together, then added in order
+    // (an entry past the end contributes fma(0, 0, acc) = acc)
+    {
+        double c[8], w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t k = i + (int64_t)u * 64;
+            const bool in_range = k < i1;
+            c[u] = in_range ? col[k] : 0.0;
+            w[u] = in_range ? in[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(c[u], w[u], acc);
+    }
     return wave_sum_d(acc);
 }
 
