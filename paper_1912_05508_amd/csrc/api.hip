@@ -1169,7 +1169,8 @@ static int drain_timing(qrx_handle h) {
     static const char *names[KP_COUNT] = {
         "krylov:init", "krylov:certify", "krylov:restart", "krylov:trmv_n", "krylov:gemv_n",
         "krylov:combine_m", "krylov:gemv_t", "krylov:combine_n", "krylov:trmv_t",
-        "krylov:update", "krylov:fused_pass"};
+        "krylov:update", "krylov:fused_pass", "krylov:certify_gemv_n", "krylov:certify_resid",
+        "krylov:certify_gemv_t", "krylov:certify_combine"};
     for (auto &p : h->phase_pending) {
         const double mn = (double)p.m * (double)p.n, tri = (double)p.np * (p.np + 1) / 2.0;
         for (int ph = 0; ph < KP_COUNT; ++ph) {
@@ -1187,6 +1188,12 @@ static int drain_timing(qrx_handle h) {
                     break;
                 // A once, u~_old read and u~ written, one n-vector of partials per workgroup
                 case KP_FUSED: fl = 4.0 * mn; by = 4.0 * mn + 16.0 * p.m + 8.0 * p.grid * p.n; break;
+                // certification: A x in double-double (hi and lo partials), the residual
+                // from b and the partials, A^T r, the column sums
+                case KP_CERT_GEMV_N: fl = 2.0 * mn; by = 4.0 * mn + 16.0 * p.splits_n * p.m; break;
+                case KP_CERT_RESID: by = 16.0 * p.splits_n * p.m + 16.0 * p.m; break;
+                case KP_CERT_GEMV_T: fl = 2.0 * mn; by = 4.0 * mn + 8.0 * p.m + 8.0 * p.splits_t * p.n; break;
+                case KP_CERT_COMBINE: by = 8.0 * p.splits_t * p.n + 8.0 * p.n; break;
                 default: break;
             }
             qrx_kernel_stat &s = h->stats[names[ph]];

@@ -85,7 +85,9 @@ struct KLoopArgs {
 // Phases of the persistent Krylov kernel, for its per-phase timing.
 enum {
     KP_INIT = 0, KP_CERTIFY, KP_RESTART, KP_TRMV_N, KP_GEMV_N, KP_COMBINE_M, KP_GEMV_T,
-    KP_COMBINE_N, KP_TRMV_T, KP_UPDATE, KP_FUSED, KP_COUNT
+    KP_COMBINE_N, KP_TRMV_T, KP_UPDATE, KP_FUSED,
+    // the four steps of a certification (KP_CERTIFY: returning to the best x)
+    KP_CERT_GEMV_N, KP_CERT_RESID, KP_CERT_GEMV_T, KP_CERT_COMBINE, KP_COUNT
 };
 // Largest n for the one-pass LSQR products, and the most workgroups a
 // persistent Krylov launch uses (the fused partials are sized for it).

@@ -128,20 +128,31 @@ QRX_DEV void ph_gemv_n(const KLoopArgs &K, const double *in, double *pn, double 
             __syncthreads();
             if (!act) continue;
             int64_t j = c0;
-            if (v4 && !dd) {
+            if (v4) {
                 constexpr int GU = 16;   // column loads in flight per thread
                 for (; j + GU <= c1; j += GU) {
                     float4 q[GU];
 #pragma unroll
                     for (int u = 0; u < GU; ++u)
                         q[u] = *reinterpret_cast<const float4 *>(K.A + (j + u) * K.lda + r);
+                    if (dd) {
 #pragma unroll
-                    for (int u = 0; u < GU; ++u) {
-                        const double xj = stage[j + u - c0];
-                        h[0] = fma((double)q[u].x, xj, h[0]);
-                        h[1] = fma((double)q[u].y, xj, h[1]);
-                        h[2] = fma((double)q[u].z, xj, h[2]);
-                        h[3] = fma((double)q[u].w, xj, h[3]);
+                        for (int u = 0; u < GU; ++u) {
+                            const double xj = stage[j + u - c0];
+                            dd_add_prod(h[0], l[0], (double)q[u].x, xj);
+                            dd_add_prod(h[1], l[1], (double)q[u].y, xj);
+                            dd_add_prod(h[2], l[2], (double)q[u].z, xj);
+                            dd_add_prod(h[3], l[3], (double)q[u].w, xj);
+                        }
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < GU; ++u) {
+                            const double xj = stage[j + u - c0];
+                            h[0] = fma((double)q[u].x, xj, h[0]);
+                            h[1] = fma((double)q[u].y, xj, h[1]);
+                            h[2] = fma((double)q[u].z, xj, h[2]);
+                            h[3] = fma((double)q[u].w, xj, h[3]);
+                        }
                     }
                 }
             }
@@ -969,15 +980,15 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
     double rnorm = 0.0, eta = 0.0, score = 0.0;
     auto certify = [&]() -> bool {
         ph_gemv_n(K, K.x, K.pn, K.pn2, 1, us);
-        if (!bar_ph(KP_CERTIFY)) return false;
+        if (!bar_ph(KP_CERT_GEMV_N)) return false;
         ph_resid(K, K.ssqA, sh);
-        if (!bar_ph(KP_CERTIFY)) return false;
+        if (!bar_ph(KP_CERT_RESID)) return false;
         rnorm = sqrt(wg_sum(K.ssqA, nblk(m), sh));
         ph_gemv_t(K, K.rc, K.pt, us);
-        if (!bar_ph(KP_CERTIFY)) return false;
+        if (!bar_ph(KP_CERT_GEMV_T)) return false;
         ph_combine_n(K, K.ssqA, sh);
         ph_ssq(K.x, np, K.ssqB, sh);
-        if (!bar_ph(KP_CERTIFY)) return false;
+        if (!bar_ph(KP_CERT_COMBINE)) return false;
         const double znorm = sqrt(wg_sum(K.ssqA, (n + LT / 64 - 1) / (LT / 64), sh));
         const double xnorm = sqrt(wg_sum(K.ssqB, nblk(np), sh));
         eta = (rnorm > 0.0 && normA > 0.0) ? znorm / (normA * rnorm) : 0.0;
