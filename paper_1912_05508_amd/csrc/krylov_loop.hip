@@ -279,7 +279,16 @@ QRX_DEV void ph_combine_m(const KLoopArgs &K, double coef, double *y, double *ou
         double v2 = 0.0;
         if (r < m) {
             double s = 0.0;
-            for (int q = 0; q < K.splits_n; ++q) s += K.pn[(int64_t)q * m + r];
+            // four splits' partials loaded together, added in split order
+            int q = 0;
+            for (; q + 4 <= K.splits_n; q += 4) {
+                double v[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[k] = K.pn[(int64_t)(q + k) * m + r];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) s += v[k];
+            }
+            for (; q < K.splits_n; ++q) s += K.pn[(int64_t)q * m + r];
             if (y) s = fma(-coef, y[r], s);
             out[r] = s;
             v2 = s * s;
@@ -297,7 +306,22 @@ QRX_DEV void ph_resid(const KLoopArgs &K, double *ssq, double *sh) {
         double v2 = 0.0;
         if (r < m) {
             double h = K.b[r], l = 0.0;
-            for (int q = 0; q < K.splits_n; ++q) {
+            // four splits' hi and lo partials loaded together, added in split order
+            int q = 0;
+            for (; q + 4 <= K.splits_n; q += 4) {
+                double ph[4], pl[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    ph[k] = K.pn[(int64_t)(q + k) * m + r];
+                    pl[k] = K.pn2[(int64_t)(q + k) * m + r];
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    dd_add(h, l, -ph[k]);
+                    dd_add(h, l, -pl[k]);
+                }
+            }
+            for (; q < K.splits_n; ++q) {
                 dd_add(h, l, -K.pn[(int64_t)q * m + r]);
                 dd_add(h, l, -K.pn2[(int64_t)q * m + r]);
             }
