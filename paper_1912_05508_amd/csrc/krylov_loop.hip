@@ -74,6 +74,15 @@ QRX_DEV bool grid_barrier(unsigned *bar, unsigned nwg, int *sflag) {
     return *sflag != 0;
 }
 
+// threadIdx.x behind an empty asm statement: values a phase derives from it
+// are computed inside the phase instead of being hoisted to the start of the
+// kernel, where they would stay live across every phase (and be spilled).
+QRX_DEV int lane_id_opaque() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // ---- workgroup reductions --------------------------------------------------------
 // Sum of p[0..count) in a fixed order: thread-strided partial sums, then a tree.
 QRX_DEV double wg_sum(const double *p, int64_t count, double *sh) {
@@ -115,7 +124,7 @@ QRX_DEV void ph_gemv_n(const KLoopArgs &K, const double *in, double *pn, double 
     const int64_t nvb = nrb * K.splits_n;
     for (int64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
         const int64_t rb = vb % nrb, s = vb / nrb;
-        const int64_t r = (rb * LT + threadIdx.x) * 4;
+        const int64_t r = (rb * LT + lane_id_opaque()) * 4;
         const int64_t j0 = s * K.cchunk;
         const int64_t j1 = (j0 + K.cchunk < n) ? j0 + K.cchunk : n;
         const bool act = r < m;
@@ -124,7 +133,7 @@ QRX_DEV void ph_gemv_n(const KLoopArgs &K, const double *in, double *pn, double 
         for (int64_t c0 = j0; c0 < j1; c0 += GN_STAGE) {
             const int64_t c1 = (c0 + GN_STAGE < j1) ? c0 + GN_STAGE : j1;
             __syncthreads();
-            for (int64_t j = c0 + threadIdx.x; j < c1; j += LT) stage[j - c0] = in[j];
+            for (int64_t j = c0 + lane_id_opaque(); j < c1; j += LT) stage[j - c0] = in[j];
             __syncthreads();
             if (!act) continue;
             int64_t j = c0;
@@ -193,7 +202,7 @@ QRX_DEV void ph_gemv_t(const KLoopArgs &K, const double *in, double *pt, double 
     const int64_t m = K.m, n = K.n;
     const int64_t ncg = (n + GT_C - 1) / GT_C;
     const int64_t nvb = ncg * K.splits_t;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = lane_id_opaque() & 63, wv = lane_id_opaque() >> 6;
     constexpr int CW = 4;
     // split-major order: a workgroup's consecutive virtual blocks share their row
     // split whenever the grid is a multiple of the split count, so the slice of
@@ -206,7 +215,7 @@ QRX_DEV void ph_gemv_t(const KLoopArgs &K, const double *in, double *pt, double 
         const int cnt = (int)(re - rs);
         if (s != staged) {
             __syncthreads();
-            for (int i = threadIdx.x; i < GT_R; i += LT) us[i] = (i < cnt) ? in[rs + i] : 0.0;
+            for (int i = lane_id_opaque(); i < GT_R; i += LT) us[i] = (i < cnt) ? in[rs + i] : 0.0;
             __syncthreads();
             staged = s;
         }
@@ -275,7 +284,7 @@ QRX_DEV void ph_combine_m(const KLoopArgs &K, double coef, double *y, double *ou
     const int64_t m = K.m;
     const unsigned nvb = nblk(m);
     for (unsigned vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-        const int64_t r = (int64_t)vb * LT + threadIdx.x;
+        const int64_t r = (int64_t)vb * LT + lane_id_opaque();
         double v2 = 0.0;
         if (r < m) {
             double s = 0.0;
@@ -302,7 +311,7 @@ QRX_DEV void ph_resid(const KLoopArgs &K, double *ssq, double *sh) {
     const int64_t m = K.m;
     const unsigned nvb = nblk(m);
     for (unsigned vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-        const int64_t r = (int64_t)vb * LT + threadIdx.x;
+        const int64_t r = (int64_t)vb * LT + lane_id_opaque();
         double v2 = 0.0;
         if (r < m) {
             double h = K.b[r], l = 0.0;
@@ -339,7 +348,7 @@ QRX_DEV void ph_resid(const KLoopArgs &K, double *ssq, double *sh) {
 QRX_DEV void ph_combine_n(const KLoopArgs &K, double *ssq, double *sh) {
     const int64_t n = K.n;
     constexpr int NW = LT / 64;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = lane_id_opaque() & 63, wv = lane_id_opaque() >> 6;
     const unsigned nvb = (unsigned)((n + NW - 1) / NW);
     for (unsigned vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
         const int64_t j = (int64_t)vb * NW + wv;
@@ -368,7 +377,7 @@ QRX_DEV void ph_combine_n(const KLoopArgs &K, double *ssq, double *sh) {
 QRX_DEV void ph_ssq(const double *v, int64_t len, double *ssq, double *sh) {
     const unsigned nvb = nblk(len);
     for (unsigned vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-        const int64_t j = (int64_t)vb * LT + threadIdx.x;
+        const int64_t j = (int64_t)vb * LT + lane_id_opaque();
         const double e = j < len ? v[j] : 0.0;
         wg_partial(e * e, ssq + vb, sh);
     }
@@ -380,7 +389,7 @@ template <class F>
 QRX_DEV void ph_each(int64_t len, F f) {
     const unsigned nvb = nblk(len);
     for (unsigned vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-        const int64_t j = (int64_t)vb * LT + threadIdx.x;
+        const int64_t j = (int64_t)vb * LT + lane_id_opaque();
         if (j < len) f(j);
     }
 }
@@ -456,7 +465,7 @@ template <class E>
 QRX_DEV void ph_tri(const KLoopArgs &K, const double *M, const double *in, int upper,
                     double scale, double *ssq, double *sh, E epi) {
     const int64_t np = K.np;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = lane_id_opaque() & 63, wv = lane_id_opaque() >> 6;
     constexpr int NW = LT / 64;
     const int wp = __builtin_amdgcn_readfirstlane(tri_waves_per_pair(np, gridDim.x));
     const int pw = NW / wp;
@@ -674,7 +683,7 @@ QRX_DEV void fused_pass(const KLoopArgs &K, const double *t, double coef, const 
                         double *un, double *lds, double *red, unsigned *voffs, double *sh) {
     const int64_t m = K.m, n = K.n, lda = K.lda;
     const int G = gridDim.x, wg = blockIdx.x;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = lane_id_opaque() & 63, wv = lane_id_opaque() >> 6;
     const int q = lane % FQ, g = lane / FQ;
     constexpr int CW = FS * KC;                  // columns per wave
     float4 *bufs = reinterpret_cast<float4 *>(lds);
@@ -719,8 +728,8 @@ QRX_DEV void fused_pass(const KLoopArgs &K, const double *t, double coef, const 
         for (int k = 0; k < KC; ++k)
             if (c0 + FS * k >= n)
                 bufs[b * FBUF_F4 + wv * FWAVE_F4 + k * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-    voffs[threadIdx.x] = voff;
-    const unsigned avoff = lds_addr(voffs + threadIdx.x);
+    voffs[lane_id_opaque()] = voff;
+    const unsigned avoff = lds_addr(voffs + lane_id_opaque());
     __asm__ volatile("" ::: "memory");
     wait_lgkm0();
     auto issue = [&](int64_t sb, int b) {
@@ -910,7 +919,7 @@ QRX_DEV void ph_combine_f(const KLoopArgs &K) {
     const int64_t n = K.n;
     const int G = gridDim.x;
     constexpr int NW = LT / 64;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = lane_id_opaque() & 63, wv = lane_id_opaque() >> 6;
     const unsigned nvb = (unsigned)((n + NW - 1) / NW);
     for (unsigned vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
         const int64_t j = (int64_t)vb * NW + wv;
@@ -1002,6 +1011,9 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
     // certification of the current x: rc = b - A x (double-double), z = A^T rc,
     // eta_F = ||z|| / (||A||_F ||rc||), compatible ratio, score = min of the two
     double rnorm = 0.0, eta = 0.0, score = 0.0;
+    // The squares of the last phase (x in [0, nblk(np)), z after them) go to
+    // ssqB: the phase after a certification (a restart) writes ssqA while
+    // another workgroup may still be summing these.
     auto certify = [&]() -> bool {
         ph_gemv_n(K, K.x, K.pn, K.pn2, 1, us);
         if (!bar_ph(KP_CERT_GEMV_N)) return false;
@@ -1010,10 +1022,11 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
         rnorm = sqrt(wg_sum(K.ssqA, nblk(m), sh));
         ph_gemv_t(K, K.rc, K.pt, us);
         if (!bar_ph(KP_CERT_GEMV_T)) return false;
-        ph_combine_n(K, K.ssqA, sh);
+        double *sz = K.ssqB + nblk(np);
+        ph_combine_n(K, sz, sh);
         ph_ssq(K.x, np, K.ssqB, sh);
         if (!bar_ph(KP_CERT_COMBINE)) return false;
-        const double znorm = sqrt(wg_sum(K.ssqA, (n + LT / 64 - 1) / (LT / 64), sh));
+        const double znorm = sqrt(wg_sum(sz, (n + LT / 64 - 1) / (LT / 64), sh));
         const double xnorm = sqrt(wg_sum(K.ssqB, nblk(np), sh));
         eta = (rnorm > 0.0 && normA > 0.0) ? znorm / (normA * rnorm) : 0.0;
         const double den = normA * xnorm + bnorm;
@@ -1191,7 +1204,7 @@ __global__ __launch_bounds__(LT, 1) void krylov_loop_kernel(KLoopArgs K) {
                 {
                     const unsigned nvb = nblk(mx_mn);
                     for (unsigned vb = blockIdx.x; vb < nvb; vb += G) {
-                        const int64_t i = (int64_t)vb * LT + threadIdx.x;
+                        const int64_t i = (int64_t)vb * LT + lane_id_opaque();
                         if (i < n) x_update(K, i, a, K.t[i]);
                         double v2 = 0.0;
                         if (i < m) {
@@ -1298,6 +1311,9 @@ size_t kr_loop_ssq_doubles(int64_t m, int64_t np) {
     const int64_t b = np / 2 + 1;                        // triangular products: up to one per column pair
     int64_t c = a > b ? a : b;
     if (c < kr_max_grid) c = kr_max_grid;               // one-pass products: one per workgroup
+    // a certification's squares of x and z, side by side
+    const int64_t d = (np + LT - 1) / LT + (np + LT / 64 - 1) / (LT / 64);
+    if (c < d) c = d;
     return (size_t)(c + 1);
 }
 
