@@ -38,7 +38,8 @@ struct KLoopArgs {
     double *pn, *pn2, *pt;          // GEMV partials: splits_n x m (two), splits_t x np
     double *pf;                     // one-pass partials of A^T u: n x grid (fused only)
     double *ssqA, *ssqB;            // kr_loop_ssq_doubles(m, np) each
-    unsigned *bar;                  // 3 barrier words, zero at launch
+    unsigned *bar;                  // 64 barrier words, zero at launch (word 2: abort flag;
+                                    // bytes 16..23: the 64-bit arrival count)
     double *x_user;                 // n: receives the best certified iterate
     qrx_lls_info *info;             // device
     int splits_n, splits_t;

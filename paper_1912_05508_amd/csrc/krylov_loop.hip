@@ -39,25 +39,26 @@ constexpr int GT_C = 4 * (LT / 64);  // columns per GEMV-T virtual block (4 per 
 constexpr unsigned kSpinLimit = 1u << 24;   // barrier polls before giving up (seconds)
 
 // ---- grid barrier -------------------------------------------------------------
-// bar[0] = arrivals, bar[1] = generation, bar[2] = abort flag; all zero at launch.
-// Thread 0 releases the workgroup's writes (agent scope) with its arrival; the
-// last arrival resets the count and bumps the generation; the others poll the
-// generation. A poll limit or an abort raised by another workgroup ends the
+// A 64-bit arrival count that only grows (bytes 16..23 of bar) and an abort
+// flag (bar[2]); all zero at launch. Thread 0 releases the workgroup's writes
+// (agent scope) with its arrival; the workgroups of barrier k (counting from 0)
+// wait until the count reaches (k + 1) nwg, k being its own arrival's count
+// divided by nwg. The arrivals are read-modify-writes of one location, so the
+// value that ends the wait carries every arrival's release; the last arrival
+// does not wait. A poll limit or an abort raised by another workgroup ends the
 // wait with `false`, so every workgroup leaves even if the launch was not
 // co-resident.
 QRX_DEV bool grid_barrier(unsigned *bar, unsigned nwg, int *sflag) {
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        const unsigned g = __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned prev =
-            __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == nwg - 1) {
-            __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(bar + 1, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        unsigned long long *cnt = reinterpret_cast<unsigned long long *>(bar + 4);
+        const unsigned long long prev =
+            __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long target = (prev / nwg + 1) * nwg;
+        if (prev + 1 != target) {
             unsigned polls = 0;
-            while (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 if (__hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
                     ++polls > kSpinLimit) {
                     __hip_atomic_store(bar + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
