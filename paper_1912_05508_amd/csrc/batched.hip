@@ -354,7 +354,8 @@ struct BProb {
 };
 
 template <class Tr>
-QRX_DEV BRes wg_qr(const BProb &p, const BOp *ops, int copy, double *lds, double *sh, int t) {
+QRX_DEV BRes wg_qr(const BProb &p, const BOp *ops, int copy, double *lds, double *sh, int t_in) {
+    const int t = t_in;
     const int lane = t & 63, wv = t >> 6;
     const int64_t m = p.m;
     const int n = (int)p.n;
@@ -397,6 +398,11 @@ QRX_DEV BRes wg_qr(const BProb &p, const BOp *ops, int copy, double *lds, double
         for (int o = p.op0; o < p.op0 + p.nops; ++o) {
             const BOp op = uniform_v(ops[o]);
             float *Wc = p.W + (int64_t)op.c0 * p.ldw;
+            // the lane index behind an empty asm statement: what the step derives
+            // from it is computed here, not hoisted out of the loops over steps and
+            // problems (where it would stay live across them and be spilled)
+            int t = t_in;
+            asm volatile("" : "+v"(t));
             if (op.kind == 0) {
                 wg_panel(Wc, p.ldw, m, op.k, p.R + op.c0 + (int64_t)op.c0 * p.ldr, p.ldr, lds, t);
             } else {
