@@ -887,7 +887,7 @@ QRX_DEV bool load_problem(const BArgs &a, int pi, BProb &p) {
 // longest-first order. For least squares the factorisation's results go to the
 // per-problem records of phase 2; a bad descriptor is reported here.
 template <class Tr>
-__global__ __launch_bounds__(BT) void bqr_queue_kernel(BArgs a) {
+__global__ __launch_bounds__(BT, 2) void bqr_queue_kernel(BArgs a) {
     __shared__ __align__(16) double lds[kBqrLds];
     __shared__ double sh[4];
     __shared__ int s_idx;
