@@ -706,7 +706,11 @@ QRX_DEV double wg_certify(const BProb &p, const double *x, double *z, double *q,
 // One problem's R-preconditioned LSQR (Sec. 3.2.3) in one workgroup, from x = 0,
 // certified with a double-double residual and restarted on it; writes x and *info.
 QRX_DEV void wg_lsqr(const BProb &p, const BRes &qr, double tol, int max_iter, qrx_lls_info *info,
-                     double *lds, double *sh, int t) {
+                     double *lds, double *sh, int t_in) {
+    // the lane index is re-read through an empty asm statement in each outer and
+    // inner iteration, so that what the steps derive from it is computed there
+    // and not kept live (and spilled) across the whole solve
+    int t = t_in;
     double *vecs = lds;   // 8 n-vectors, then the 64 x 65 block of the triangular solves
     float *Rb = reinterpret_cast<float *>(lds + 8 * kBMaxN);
     const int n = (int)p.n;
@@ -742,6 +746,8 @@ QRX_DEV void wg_lsqr(const BProb &p, const BRes &qr, double tol, int max_iter, q
     double first_eta = 0.0;
     int iters = 0, restarts = 0, stall = 0, status = QRX_ENOCONV;
     for (int outer = 0;; ++outer) {
+        t = t_in;
+        asm volatile("" : "+v"(t));
         // certify the current x; q = residual, z = A^T q
         const double score = wg_certify(p, V.x, V.z, p.q, normA, bnorm, eta, rnorm, sh, t, tol);
         if (outer == 0) first_eta = eta;
@@ -782,6 +788,8 @@ QRX_DEV void wg_lsqr(const BProb &p, const BRes &qr, double tol, int max_iter, q
         double phibar = beta, rhobar = alpha;
         const int every = 50;
         for (int it = 0; it < every && iters < max_iter; ++it) {
+            t = t_in;
+            asm volatile("" : "+v"(t));
             ++iters;
             const double b2 = wg_gemv_n(p, V.t, alpha, p.u, sh, t);   // u = A t - alpha u
             beta = sqrt(b2);
@@ -834,8 +842,7 @@ QRX_DEV void wg_lsqr(const BProb &p, const BRes &qr, double tol, int max_iter, q
 // The persistent batched kernels: each workgroup takes the next problem from an
 // atomic queue over the longest-first order until the queue is empty. The QR
 // kernel factors it; for least squares a second kernel, with its own queue,
-// runs LSQR on each factored problem (it fits four workgroups per CU where the
-// QR fits one).
+// runs LSQR on each factored problem. Both kernels hold two workgroups per CU.
 // ---------------------------------------------------------------------------
 // The next queue index for this workgroup (uniform: every lane gets it in a
 // scalar register; read back through LDS it would count as divergent, and the
@@ -885,7 +892,10 @@ QRX_DEV bool load_problem(const BArgs &a, int pi, BProb &p) {
 
 // Phase 1 of a batch: every problem's QR, taken off the first work queue in the
 // longest-first order. For least squares the factorisation's results go to the
-// per-problem records of phase 2; a bad descriptor is reported here.
+// per-problem records of phase 2; a bad descriptor is reported here. Its
+// registers are bounded for two workgroups per CU: a second workgroup hides
+// the latency of the first's loads (4096 mixed problems: 38.5 -> 31.1 ms),
+// which outweighs the few registers spilled outside the product loops.
 template <class Tr>
 __global__ __launch_bounds__(BT, 2) void bqr_queue_kernel(BArgs a) {
     __shared__ __align__(16) double lds[kBqrLds];
