@@ -895,7 +895,7 @@ QRX_DEV bool load_problem(const BArgs &a, int pi, BProb &p) {
 // per-problem records of phase 2; a bad descriptor is reported here. Its
 // registers are bounded for two workgroups per CU: a second workgroup hides
 // the latency of the first's loads (4096 mixed problems: 38.5 -> 31.1 ms),
-// which outweighs the few registers spilled outside the product loops.
+// which outweighs the registers it then spills (about 56 per lane).
 template <class Tr>
 __global__ __launch_bounds__(BT, 2) void bqr_queue_kernel(BArgs a) {
     __shared__ __align__(16) double lds[kBqrLds];
