@@ -51,20 +51,28 @@ __global__ __launch_bounds__(IB) void inv_diag_kernel(int64_t n, const float *__
     for (int i = 0; i < IB; ++i) X[(o + i) + (o + c) * ldx] = Xs[i + c * (IB + 1)];
 }
 
-// C (M x N, ldc) = alpha * A B, FP64 accumulation, M and N multiples of BT, K
+// C (M x N, ldc) = alpha * A B, FP64 accumulation, M and N multiples of 64, K
 // a multiple of 16. A is FP32 or FP64 (element (i, k) at A[i + k*lda], zero
 // where i >= arl or k >= acl); B is FP64 (B[k + j*ldb]). TRI = 1: B is upper
 // triangular (k <= j contributes); TRI = 2: A is upper triangular (k >= i
-// contributes). Workgroup: BT x BT tile, 16 x 16 threads with TM x TM outputs
-// each (TM = BT / 16), K stages of 16 through LDS.
-template <class TA, int TRI, int BT>
-__global__ __launch_bounds__(TT) void tri_gemm_kernel(int64_t M, int64_t N, int64_t K,
-                                                      const TA *__restrict__ A, int64_t lda,
-                                                      int64_t arl, int64_t acl,
-                                                      const double *__restrict__ B, int64_t ldb,
-                                                      double *__restrict__ C, int64_t ldc,
-                                                      double alpha) {
-    constexpr int BK = 16, LS = BT + 4, TM = BT / 16;
+// contributes). On the FP64 matrix cores (v_mfma_f64_16x16x4f64: A operand
+// lane l holds A[l % 16][l / 16], B operand B[l / 16][l % 16], result register
+// v of lane l holds D[4 v + l / 16][l % 16]): 64 x 64 tile per workgroup, wave
+// w the 32 x 32 quarter (rows 32 (w % 2), columns 32 (w / 2)) as 2 x 2 blocks
+// of 16 x 16; K in stages of 16 through LDS, the next stage's loads in
+// registers meanwhile. Each lane reads one LDS value per operand and block for
+// 1024 FMAs per instruction, where 4 x 4 register tiles on the vector units
+// read two values per two FMAs (the inverse at n = 8192: 11.8 ms against
+// 13.4 ms with those).
+typedef double tgd4 __attribute__((ext_vector_type(4)));
+template <class TA, int TRI>
+__global__ __launch_bounds__(TT) void tri_gemm_mfma_kernel(int64_t M, int64_t N, int64_t K,
+                                                           const TA *__restrict__ A, int64_t lda,
+                                                           int64_t arl, int64_t acl,
+                                                           const double *__restrict__ B,
+                                                           int64_t ldb, double *__restrict__ C,
+                                                           int64_t ldc, double alpha) {
+    constexpr int BT = 64, BK = 16, LS = BT + 4;
     constexpr int AQ = BT * BK / TT;               // A (and B) elements each thread stages
     __shared__ __align__(16) double As[BK * LS];   // As[k][i]
     __shared__ __align__(16) double Bs[BK * LS];   // Bs[k][j]
@@ -73,7 +81,6 @@ __global__ __launch_bounds__(TT) void tri_gemm_kernel(int64_t M, int64_t N, int6
     const int64_t i0 = (blockIdx.x % tiles_m) * BT, j0 = (blockIdx.x / tiles_m) * BT;
     const int64_t kb = (TRI == 2) ? i0 : 0;
     const int64_t ke = (TRI == 1) ? ((j0 + BT < K) ? j0 + BT : K) : K;
-    const int ti = t % 16, tj = t / 16;
     const int ar = t % BT, akq = t / BT;          // A loads: row ar, k = akq * AQ + q
     const int bk = t % 16, bjq = t / 16;          // B loads: k = bk, column bjq * AQ + q
     double pa[AQ], pb[AQ];
@@ -88,11 +95,14 @@ __global__ __launch_bounds__(TT) void tri_gemm_kernel(int64_t M, int64_t N, int6
             pb[q] = (TRI != 1 || kb2 <= jb) ? B[kb2 + jb * ldb] : 0.0;
         }
     };
-    double acc[TM][TM];
+    const int lane = t & 63, wv = t >> 6;
+    const int wr = wv & 1, wc = wv >> 1;
+    const int li = lane & 15, lk = lane >> 4;
+    tgd4 acc[2][2];
 #pragma unroll
-    for (int x = 0; x < TM; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < TM; ++y) acc[x][y] = 0.0;
+        for (int y = 0; y < 2; ++y) acc[x][y] = tgd4{0.0, 0.0, 0.0, 0.0};
     if (kb < ke) load(kb);
     for (int64_t k0 = kb; k0 < ke; k0 += BK) {
         __syncthreads();
@@ -104,24 +114,27 @@ __global__ __launch_bounds__(TT) void tri_gemm_kernel(int64_t M, int64_t N, int6
         __syncthreads();
         if (k0 + BK < ke) load(k0 + BK);
 #pragma unroll
-        for (int kk = 0; kk < BK; ++kk) {
-            double a[TM], b[TM];
+        for (int k4 = 0; k4 < BK / 4; ++k4) {
+            double a[2], b[2];
 #pragma unroll
-            for (int q = 0; q < TM; ++q) {
-                a[q] = As[kk * LS + ti * TM + q];
-                b[q] = Bs[kk * LS + tj * TM + q];
-            }
+            for (int x = 0; x < 2; ++x) a[x] = As[(4 * k4 + lk) * LS + 32 * wr + 16 * x + li];
 #pragma unroll
-            for (int x = 0; x < TM; ++x)
+            for (int y = 0; y < 2; ++y) b[y] = Bs[(4 * k4 + lk) * LS + 32 * wc + 16 * y + li];
 #pragma unroll
-                for (int y = 0; y < TM; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int y = 0; y < TM; ++y)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int x = 0; x < TM; ++x)
-            C[(i0 + ti * TM + x) + (j0 + tj * TM + y) * ldc] = alpha * acc[x][y];
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                C[(i0 + 32 * wr + 16 * x + 4 * v + lk) + (j0 + 32 * wc + 16 * y + li) * ldc] =
+                    alpha * acc[x][y][v];
 }
 
 // ---- applications -----------------------------------------------------------
@@ -212,10 +225,10 @@ template <class TA, int TRI>
 static hipError_t tri_gemm(hipStream_t s, int64_t M, int64_t N, int64_t K, const TA *A,
                            int64_t lda, int64_t arl, int64_t acl, const double *B, int64_t ldb,
                            double *C, int64_t ldc, double alpha) {
-    // 64 x 64 tiles throughout: measured faster at n = 8192 than 128 x 128 tiles on
-    // the vector units (8 x 8 per thread) or on the FP64 matrix cores
+    // 64 x 64 tiles throughout: at n = 8192, 128 x 128 tiles (on the vector units
+    // with 8 x 8 per thread, or on the matrix cores) were slower
     const unsigned tiles = (unsigned)((M / 64) * (N / 64));
-    hipLaunchKernelGGL((tri_gemm_kernel<TA, TRI, 64>), dim3(tiles), dim3(TT), 0, s, M, N, K, A,
+    hipLaunchKernelGGL((tri_gemm_mfma_kernel<TA, TRI>), dim3(tiles), dim3(TT), 0, s, M, N, K, A,
                        lda, arl, acl, B, ldb, C, ldc, alpha);
     return hipGetLastError();
 }
