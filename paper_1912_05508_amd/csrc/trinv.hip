@@ -17,6 +17,9 @@
 #include "qrx_internal.hpp"
 #include "krylov.hpp"
 
+#include <cstring>
+#include <vector>
+
 namespace qrx {
 
 constexpr int IB = 64;     // leaf block
@@ -62,23 +65,20 @@ __global__ __launch_bounds__(IB) void inv_diag_kernel(int64_t n, const float *__
 // of 16 x 16; K in stages of 16 through LDS, the next stage's loads in
 // registers meanwhile. Each lane reads one LDS value per operand and block for
 // 1024 FMAs per instruction, where 4 x 4 register tiles on the vector units
-// read two values per two FMAs (the inverse at n = 8192: 11.8 ms against
-// 13.4 ms with those).
+// read two values per two FMAs (the inverse at n = 8192, one launch per node
+// and product: 11.8 ms against 13.4 ms with those).
 typedef double tgd4 __attribute__((ext_vector_type(4)));
 template <class TA, int TRI>
-__global__ __launch_bounds__(TT) void tri_gemm_mfma_kernel(int64_t M, int64_t N, int64_t K,
-                                                           const TA *__restrict__ A, int64_t lda,
-                                                           int64_t arl, int64_t acl,
-                                                           const double *__restrict__ B,
-                                                           int64_t ldb, double *__restrict__ C,
-                                                           int64_t ldc, double alpha) {
+QRX_DEV void tri_tile(int64_t M, int64_t K, const TA *__restrict__ A, int64_t lda, int64_t arl,
+                      int64_t acl, const double *__restrict__ B, int64_t ldb,
+                      double *__restrict__ C, int64_t ldc, double alpha, int64_t tile) {
     constexpr int BT = 64, BK = 16, LS = BT + 4;
     constexpr int AQ = BT * BK / TT;               // A (and B) elements each thread stages
     __shared__ __align__(16) double As[BK * LS];   // As[k][i]
     __shared__ __align__(16) double Bs[BK * LS];   // Bs[k][j]
     const int t = threadIdx.x;
     const int64_t tiles_m = M / BT;
-    const int64_t i0 = (blockIdx.x % tiles_m) * BT, j0 = (blockIdx.x / tiles_m) * BT;
+    const int64_t i0 = (tile % tiles_m) * BT, j0 = (tile / tiles_m) * BT;
     const int64_t kb = (TRI == 2) ? i0 : 0;
     const int64_t ke = (TRI == 1) ? ((j0 + BT < K) ? j0 + BT : K) : K;
     const int ar = t % BT, akq = t / BT;          // A loads: row ar, k = akq * AQ + q
@@ -135,6 +135,47 @@ __global__ __launch_bounds__(TT) void tri_gemm_mfma_kernel(int64_t M, int64_t N,
             for (int v = 0; v < 4; ++v)
                 C[(i0 + 32 * wr + 16 * x + 4 * v + lk) + (j0 + 32 * wc + 16 * y + li) * ldc] =
                     alpha * acc[x][y][v];
+}
+
+// One level of the recursion in one launch: the products of up to kTriNodes
+// nodes of equal depth (disjoint column ranges, so independent), their tiles
+// numbered node after node. At n = 8192 this takes 14 launches where one per
+// node and product took 254, and the inverse 6.6 ms where it took 11.8. Node k covers columns [c0, c0 + s1 + s2); its
+// T = R12 X22 (TRI = 1) or X12 = -X11 T (TRI = 2) uses the T block at toff.
+constexpr int kTriNodes = 64;
+struct TriLevel {
+    int count;
+    int tile0[kTriNodes + 1];   // first tile of each node; tile0[count] = all tiles
+    int c0[kTriNodes], s1[kTriNodes], s2[kTriNodes];
+    int64_t toff[kTriNodes];
+};
+
+template <int TRI>
+__global__ __launch_bounds__(TT) void tri_level_kernel(const TriLevel lv, int64_t n,
+                                                       const float *__restrict__ R, int64_t ldr,
+                                                       double *__restrict__ X, int64_t ldx,
+                                                       double *__restrict__ T) {
+    // this workgroup's node: the last k with tile0[k] <= blockIdx.x (binary search)
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = lv.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (lv.tile0[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t c0 = lv.c0[lo], s1 = lv.s1[lo], s2 = lv.s2[lo];
+    double *Tk = T + lv.toff[lo];
+    const int64_t tile = b - lv.tile0[lo];
+    if constexpr (TRI == 1) {
+        // T = R12 X22 (s1 x s2, ld s1); R beyond n is the identity, so R12 is zero there
+        tri_tile<float, 1>(s1, s2, R + c0 + (c0 + s1) * ldr, ldr, n - c0, n - (c0 + s1),
+                           X + (c0 + s1) + (c0 + s1) * ldx, ldx, Tk, s1, 1.0, tile);
+    } else {
+        // X12 = -X11 T
+        const int64_t big = (int64_t)1 << 62;
+        tri_tile<double, 2>(s1, s1, X + c0 + c0 * ldx, ldx, big, big, Tk, s1,
+                            X + c0 + (c0 + s1) * ldx, ldx, -1.0, tile);
+    }
 }
 
 // ---- applications -----------------------------------------------------------
@@ -221,36 +262,17 @@ hipError_t kr_transpose(hipStream_t s, int64_t np, const double *X, double *Xt) 
 // ---------------------------------------------------------------------------
 size_t kr_trinv_tmp_doubles(int64_t np) { return (size_t)(np / 2 + IB) * (size_t)(np / 2 + IB); }
 
-template <class TA, int TRI>
-static hipError_t tri_gemm(hipStream_t s, int64_t M, int64_t N, int64_t K, const TA *A,
-                           int64_t lda, int64_t arl, int64_t acl, const double *B, int64_t ldb,
-                           double *C, int64_t ldc, double alpha) {
-    // 64 x 64 tiles throughout: at n = 8192, 128 x 128 tiles (on the vector units
-    // with 8 x 8 per thread, or on the matrix cores) were slower
-    const unsigned tiles = (unsigned)((M / 64) * (N / 64));
-    hipLaunchKernelGGL((tri_gemm_mfma_kernel<TA, TRI>), dim3(tiles), dim3(TT), 0, s, M, N, K, A,
-                       lda, arl, acl, B, ldb, C, ldc, alpha);
-    return hipGetLastError();
-}
-
-// Columns [c0, c0 + w) of X (w a multiple of 64, leaves already inverted).
-static hipError_t trinv_node(hipStream_t s, int64_t n, const float *R, int64_t ldr, double *X,
-                             int64_t ldx, double *T, int64_t c0, int64_t w) {
-    if (w <= IB) return hipSuccess;
+// Internal nodes of the recursion (w > 64), with their depth.
+struct TriNode {
+    int64_t c0, w;
+    int depth;
+};
+static void tri_nodes(std::vector<TriNode> &out, int64_t c0, int64_t w, int depth) {
+    if (w <= IB) return;
     const int64_t s1 = IB * ((w / IB + 1) / 2), s2 = w - s1;
-    hipError_t e = trinv_node(s, n, R, ldr, X, ldx, T, c0, s1);
-    if (e != hipSuccess) return e;
-    e = trinv_node(s, n, R, ldr, X, ldx, T, c0 + s1, s2);
-    if (e != hipSuccess) return e;
-    // T = R12 X22 (s1 x s2, ld s1); R beyond n is the identity, so R12 is zero there
-    const int64_t arl = n - c0, acl = n - (c0 + s1);
-    e = tri_gemm<float, 1>(s, s1, s2, s2, R + c0 + (c0 + s1) * ldr, ldr, arl, acl,
-                           X + (c0 + s1) + (c0 + s1) * ldx, ldx, T, s1, 1.0);
-    if (e != hipSuccess) return e;
-    // X12 = -X11 T
-    const int64_t big = (int64_t)1 << 62;
-    return tri_gemm<double, 2>(s, s1, s2, s1, X + c0 + c0 * ldx, ldx, big, big, T, s1,
-                               X + c0 + (c0 + s1) * ldx, ldx, -1.0);
+    out.push_back({c0, w, depth});
+    tri_nodes(out, c0, s1, depth + 1);
+    tri_nodes(out, c0 + s1, s2, depth + 1);
 }
 
 hipError_t kr_trinv(hipStream_t s, int64_t n, int64_t np, const float *R, int64_t ldr, double *X,
@@ -260,7 +282,44 @@ hipError_t kr_trinv(hipStream_t s, int64_t n, int64_t np, const float *R, int64_
                        np);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return trinv_node(s, n, R, ldr, X, np, T, 0, np);
+    std::vector<TriNode> nodes;
+    tri_nodes(nodes, 0, np, 0);
+    int maxd = -1;
+    for (const TriNode &d : nodes) maxd = d.depth > maxd ? d.depth : maxd;
+    // deepest level first: a node's children are complete before its products.
+    // The T blocks of one launch lie side by side: sum of s1 s2 <= (np / 2)^2,
+    // within the kr_trinv_tmp_doubles(np) of T. 64 x 64 tiles throughout: at
+    // n = 8192, 128 x 128 tiles (vector units with 8 x 8 per thread, or matrix
+    // cores) were slower.
+    for (int d = maxd; d >= 0; --d) {
+        size_t i = 0;
+        while (i < nodes.size()) {
+            TriLevel lv;
+            memset(&lv, 0, sizeof(lv));
+            int64_t tiles = 0, toff = 0;
+            for (; i < nodes.size() && lv.count < kTriNodes; ++i) {
+                if (nodes[i].depth != d) continue;
+                const int64_t w = nodes[i].w, s1 = IB * ((w / IB + 1) / 2), s2 = w - s1;
+                const int k = lv.count++;
+                lv.tile0[k] = (int)tiles;
+                lv.c0[k] = (int)nodes[i].c0;
+                lv.s1[k] = (int)s1;
+                lv.s2[k] = (int)s2;
+                lv.toff[k] = toff;
+                tiles += (s1 / IB) * (s2 / IB);
+                toff += s1 * s2;
+            }
+            if (lv.count == 0) continue;
+            lv.tile0[lv.count] = (int)tiles;
+            hipLaunchKernelGGL(tri_level_kernel<1>, dim3((unsigned)tiles), dim3(TT), 0, s, lv, n,
+                               R, ldr, X, np, T);
+            hipLaunchKernelGGL(tri_level_kernel<2>, dim3((unsigned)tiles), dim3(TT), 0, s, lv, n,
+                               R, ldr, X, np, T);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
 }
 
 size_t kr_trmv_part_doubles(int64_t np) { return (size_t)((np + TCS - 1) / TCS) * (size_t)np; }
