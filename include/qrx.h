@@ -251,10 +251,11 @@ int qrx_batch_plan_destroy(qrx_batch_plan plan);
  * and the persistent kernels on `stream`: the QR kernel, whose workgroups each
  * take the next problem off an atomic queue over the longest-first order and
  * factor it, then (least squares) the LSQR kernel, which takes the problems off
- * a second queue in the same order and iterates each to the end. The two run
- * at different occupancies (the QR holds a 32-column panel and a product tile
- * per workgroup; LSQR needs a fraction of that), which is why they are two
- * launches rather than one.
+ * a second queue in the same order and iterates each to the end. They are two
+ * launches rather than one because each kernel is compiled for its own
+ * register and LDS budget (the QR holds a 32-column panel and a product tile
+ * per workgroup; LSQR needs a fraction of that): one kernel carrying the QR's
+ * footprint through the LSQR phase took about twice as long.
  * Nothing is synchronised and nothing is allocated when `work` is given (or the
  * handle's workspace is already large enough), so the call can be recorded into
  * a HIP graph. Problems are independent: a singular, non-finite or invalid
